@@ -1,0 +1,330 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-types an oracle formula: each compares the oracle with a
+brute-force search, a finite difference, a closed form, an invariance of the
+problem, or a value printed in the paper.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.linalg import polar
+from scipy.optimize import minimize
+
+import synth
+from oracle import nsrgs as O
+
+
+def _rand_orth(rng, d):
+    q, r = np.linalg.qr(rng.standard_normal((d, d)))
+    return q * np.sign(np.diag(r))
+
+
+# ---------------------------------------------------------------- sgn (Sec. 2.1)
+
+def _best_o2(M):
+    """argmax_{U in O(2)} tr(U^T M) in closed form (rotation vs reflection)."""
+    m11, m12, m21, m22 = M[0, 0], M[0, 1], M[1, 0], M[1, 1]
+    th_r = math.atan2(m21 - m12, m11 + m22)
+    R = np.array([[math.cos(th_r), -math.sin(th_r)], [math.sin(th_r), math.cos(th_r)]])
+    th_f = math.atan2(m12 + m21, m11 - m22)
+    Fm = np.array([[math.cos(th_f), math.sin(th_f)], [math.sin(th_f), -math.cos(th_f)]])
+    return R if np.trace(R.T @ M) >= np.trace(Fm.T @ M) else Fm
+
+
+def _euler(a, b, c):
+    ca, sa, cb, sb, cc, sc = map(lambda t: t, (math.cos(a), math.sin(a), math.cos(b),
+                                               math.sin(b), math.cos(c), math.sin(c)))
+    Rz1 = np.array([[ca, -sa, 0], [sa, ca, 0], [0, 0, 1]])
+    Ry = np.array([[cb, 0, sb], [0, 1, 0], [-sb, 0, cb]])
+    Rz2 = np.array([[cc, -sc, 0], [sc, cc, 0], [0, 0, 1]])
+    return Rz1 @ Ry @ Rz2
+
+
+def _best_o3(M):
+    """argmax over O(3) = SO(3) u (-SO(3)) of tr(U^T M): grid search + refinement."""
+    best = (-np.inf, None)
+    grid_a = np.linspace(-math.pi, math.pi, 25)
+    grid_b = np.linspace(0, math.pi, 13)
+    for sign in (1.0, -1.0):
+        for a in grid_a:
+            for b in grid_b:
+                for c in grid_a:
+                    v = sign * np.trace(_euler(a, b, c).T @ M)
+                    if v > best[0]:
+                        best = (v, (sign, a, b, c))
+    sign, a, b, c = best[1]
+    res = minimize(lambda p: -sign * np.trace(_euler(*p).T @ M), [a, b, c],
+                   method="Nelder-Mead", options=dict(xatol=1e-12, fatol=1e-15, maxiter=20000))
+    return sign * _euler(*res.x)
+
+
+def test_sgn_matches_closed_form_d2():
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        M = rng.standard_normal((2, 2))
+        assert np.abs(O.sgn(M) - _best_o2(M)).max() < 1e-13
+
+
+def test_sgn_matches_brute_force_d3():
+    rng = np.random.default_rng(1)
+    for _ in range(4):
+        M = rng.standard_normal((3, 3))
+        U = _best_o3(M)
+        assert np.trace(O.sgn(M).T @ M) >= np.trace(U.T @ M) - 1e-12
+        assert np.abs(O.sgn(M) - U).max() < 1e-5
+
+
+def test_sgn_matches_scipy_polar_and_blocks():
+    rng = np.random.default_rng(2)
+    Ms = rng.standard_normal((50, 4, 4))
+    S = O.sgn(Ms)
+    for k in range(50):
+        u, _ = polar(Ms[k])
+        assert np.abs(S[k] - u).max() < 1e-13
+    stack = Ms.reshape(-1, 4)
+    assert np.abs(O.sgn_blocks(stack, 4).reshape(50, 4, 4) - S).max() == 0.0
+
+
+# ---------------------------------------------------- Newton-Schulz (Alg. 1)
+
+def test_newton_schulz_singular_value_map():
+    # S(U Sigma V^T) = U f(Sigma) V^T with f(s) = (3 s - s^3) / 2, applied per step.
+    rng = np.random.default_rng(3)
+    for d in (2, 3, 4, 10):
+        for _ in range(20):
+            U, V = _rand_orth(rng, d), _rand_orth(rng, d)
+            s = rng.uniform(0.05, math.sqrt(3) - 0.05, size=d)
+            M = U @ np.diag(s) @ V.T
+            for Ts in range(0, 7):
+                f = s.copy()
+                for _ in range(Ts):
+                    f = 1.5 * f - 0.5 * f ** 3
+                want = U @ np.diag(f) @ V.T
+                assert np.abs(O.newton_schulz(M, Ts) - want).max() < 1e-14
+
+
+def test_newton_schulz_lemma_2_1_bound():
+    rng = np.random.default_rng(4)
+    for d in (2, 3, 5):
+        for _ in range(50):
+            U, V = _rand_orth(rng, d), _rand_orth(rng, d)
+            s = rng.uniform(0.1, 1.38, size=d)        # ||I - M^T M|| < 1
+            M = U @ np.diag(s) @ V.T
+            r0 = np.linalg.norm(np.eye(d) - M.T @ M, 2)
+            assert r0 < 1
+            pol = O.sgn(M)
+            for t in range(6):
+                S = O.newton_schulz(M, t)
+                rt = np.linalg.norm(np.eye(d) - S.T @ S, 2)
+                assert np.linalg.norm(S - pol, 2) <= rt + 1e-15
+                assert rt <= r0 ** (2 ** t) + 1e-15
+
+
+def test_newton_schulz_converges_to_sgn_inside_sqrt3():
+    rng = np.random.default_rng(5)
+    Ms = rng.standard_normal((100, 3, 3))
+    Ms /= np.linalg.norm(Ms, axis=(1, 2), keepdims=True)   # sigma_max <= 1 < sqrt(3)
+    S = O.newton_schulz(Ms, 40)
+    assert np.abs(S - O.sgn(Ms)).max() < 1e-12
+
+
+# ----------------------------------------- gradient and projection (Sec. 2.2)
+
+def test_gradient_equals_finite_difference_of_f_i():
+    rng = np.random.default_rng(6)
+    n, d = 6, 3
+    A = rng.standard_normal((n * d, n * d))
+    A = A + A.T
+    X = np.concatenate([_rand_orth(rng, d) for _ in range(n)])
+    G = O.euclidean_gradient(A, X, d)
+    h = 1e-6
+    for i in range(n):
+        fd = np.zeros((d, d))
+        for a in range(d):
+            for b in range(d):
+                Xp, Xm = X.copy(), X.copy()
+                Xp[i * d + a, b] += h
+                Xm[i * d + a, b] -= h
+                fd[a, b] = (O.partial_objective(A, Xp, d, i) - O.partial_objective(A, Xm, d, i)) / (2 * h)
+        assert np.abs(fd - G[i * d:(i + 1) * d]).max() < 1e-6
+
+
+def test_offdiag_product_brute_force_loops():
+    rng = np.random.default_rng(7)
+    n, d = 5, 3
+    A = rng.standard_normal((n * d, n * d))
+    X = rng.standard_normal((n * d, d))
+    C = O.offdiag_product(A, X, d)
+    for i in range(n):
+        for a in range(d):
+            for k in range(d):
+                acc = 0.0
+                for j in range(n):
+                    if j == i:
+                        continue
+                    for b in range(d):
+                        acc += A[i * d + a, j * d + b] * X[j * d + b, k]
+                assert abs(acc - C[i * d + a, k]) < 1e-13
+
+
+def test_tangent_projection_is_the_orthogonal_projection_on_O_d():
+    rng = np.random.default_rng(8)
+    d = 4
+    for _ in range(20):
+        X = _rand_orth(rng, d)
+        G = rng.standard_normal((d, d))
+        P = O.tangent_projection(X, G, d)
+        H = X.T @ P
+        assert np.abs(H + H.T).max() < 1e-13                        # P in T_X
+        assert np.abs(O.tangent_projection(X, P, d) - P).max() < 1e-13  # idempotent
+        K = rng.standard_normal((d, d))
+        K = K - K.T
+        assert abs(np.sum((G - P) * (X @ K))) < 1e-12               # residual normal to T_X
+        S = rng.standard_normal((d, d))
+        S = S + S.T
+        assert np.abs(O.tangent_projection(X, X @ S, d)).max() < 1e-13  # normal space killed
+
+
+# -------------------------------------------------------------- whole solve
+
+def _cfg0(seed=0, sigma=2.0, n=100, d=3):
+    Z = synth.haar_blocks(n, d, seed)
+    A = synth.measurement_matrix(Z, sigma, seed)
+    return Z, A
+
+
+def test_noiseless_spectral_init_and_recovery():
+    n, d = 60, 3
+    Z = synth.haar_blocks(n, d, 3)
+    A = synth.measurement_matrix(Z, 0.0, 3)
+    X0 = O.spectral_init(A, d)
+    assert O.dist_F(X0, Z) < 1e-12
+    Xs = synth.perturbed_start(Z, 0.15, seed=9)
+    res = O.solve(A, d, T=12, X0=O.sgn_blocks(Xs, d))
+    assert O.dist_F(Xs, Z) > 0.5
+    assert O.dist_F(res.X, Z) < 1e-12
+
+
+def test_gauge_equivariance():
+    # A -> D A D^T with D = diag(R_i) maps the solution X to D X (up to O(d)).
+    Z, A = _cfg0(seed=1, n=50)
+    d, n = 3, 50
+    rng = np.random.default_rng(10)
+    D = np.zeros_like(A)
+    for i in range(n):
+        D[i * d:(i + 1) * d, i * d:(i + 1) * d] = _rand_orth(rng, d)
+    r1 = O.solve(A, d, T=30)
+    r2 = O.solve(D @ A @ D.T, d, T=30)
+    assert O.dist_F(r2.X, D @ r1.X) < 1e-10
+
+
+def test_global_rotation_equivariance():
+    Z, A = _cfg0(seed=2, n=50)
+    d = 3
+    Q = _rand_orth(np.random.default_rng(11), d)
+    X0 = O.spectral_init(A, d)
+    r1 = O.solve(A, d, T=25, X0=X0)
+    r2 = O.solve(A, d, T=25, X0=X0 @ Q)
+    assert np.abs(r2.X - r1.X @ Q).max() < 1e-12
+
+
+def test_block_permutation_equivariance():
+    Z, A = _cfg0(seed=3, n=40)
+    d, n = 3, 40
+    perm = np.random.default_rng(12).permutation(n)
+    idx = (perm[:, None] * d + np.arange(d)).ravel()
+    r1 = O.solve(A, d, T=20)
+    r2 = O.solve(A[np.ix_(idx, idx)], d, T=20)
+    assert O.dist_F(r2.X, r1.X[idx]) < 1e-10
+
+
+def test_ns_rgs_tracks_exact_polar_rgs():
+    # Both retractions share fixed points; at the paper's regime the NS
+    # iterates stay within rounding of the exact-polar sequence.
+    Z, A = _cfg0()
+    d = 3
+    X0 = O.spectral_init(A, d)
+    a = O.solve(A, d, Ts=3, T=100, X0=X0, retraction="ns")
+    b = O.solve(A, d, Ts=3, T=100, X0=X0, retraction="polar")
+    assert O.dist_F(a.X, b.X) / 10.0 < 1e-12
+    c = O.solve(A, d, Ts=1, T=100, X0=X0, retraction="ns")
+    assert O.dist_F(c.X, b.X) / 10.0 < 1e-12
+
+
+def test_converged_point_is_stationary_and_orthogonal():
+    Z, A = _cfg0()
+    d = 3
+    r = O.solve(A, d, T=100)
+    Xb = O.as_blocks(r.X, d)
+    assert np.abs(Xb @ np.swapaxes(Xb, 1, 2) - np.eye(d)).max() < 1e-13
+    G = O.euclidean_gradient(A, r.X, d)
+    P = O.tangent_projection(r.X, G, d)
+    assert np.abs(P).max() < 1e-10 * np.abs(G).max()
+    assert r.max_orth_defects[-1] < 1e-13
+
+
+@pytest.mark.parametrize("n,c", [(100, 0.35), (300, 0.1)])
+def test_first_order_alignment_error(n, c):
+    # Linearising the stationarity condition around Z gives
+    # E_i = sigma skew(M_i) / n with M_i ~ N(0, n - 1) entrywise, hence
+    # d_F(X, Z) / sqrt(n) ~= sigma sqrt(d (d - 1) / (2 n)).
+    d = 3
+    sigma = synth.sigma_for(c, n, d)
+    Z = synth.haar_blocks(n, d, 100 + n)
+    A = synth.measurement_matrix(Z, sigma, 200 + n)
+    r = O.solve(A, d, T=100)
+    pred = sigma * math.sqrt(d * (d - 1) / (2.0 * n))
+    assert abs(O.alignment_error(r.X, Z) / pred - 1.0) < 0.1
+
+
+@pytest.mark.slow
+def test_table1_p1_rel_err(golden_dir):
+    want = np.loadtxt(os.path.join(golden_dir, "table1_p1_relerr.txt"))
+    n, d = 500, 25
+    nd = n * d
+    rng = np.random.default_rng(1)
+    W = rng.standard_normal((nd, nd))
+    W = np.triu(W) + np.triu(W, 1).T
+    for i in range(n):
+        W[i * d:(i + 1) * d, i * d:(i + 1) * d] = 0.0           # W_ii = 0
+    Z = synth.haar_blocks(n, d, 1)
+    ZZ = Z @ Z.T
+    X_init = None
+    for sigma, rel in sorted(want, key=lambda r: r[0] != 0.1):
+        A = ZZ + sigma * W
+        if X_init is None:                                       # eigsh once (sigma = 0.1)
+            X_init = O.spectral_init(A, d)
+        res = O.solve(A, d, Ts=1, T=100, stop="objective", tol=1e-8, X0=X_init)
+        got = O.rel_err(res.X, Z, form="gram")
+        assert abs(got / rel - 1.0) < 0.01, (sigma, got, rel)
+    del W
+
+
+# ------------------------------------------------------------------ metrics
+
+def test_dist_F_brute_force_and_invariance():
+    rng = np.random.default_rng(13)
+    n, d = 7, 2
+    X = rng.standard_normal((n * d, d))
+    Y = rng.standard_normal((n * d, d))
+    best = np.inf
+    for th in np.linspace(-math.pi, math.pi, 200001):
+        c, s = math.cos(th), math.sin(th)
+        for Q in (np.array([[c, -s], [s, c]]), np.array([[c, s], [s, -c]])):
+            best = min(best, np.linalg.norm(X - Y @ Q))
+    assert abs(O.dist_F(X, Y) - best) < 1e-8
+    Q = _rand_orth(rng, d)
+    assert O.dist_F(X @ Q, X) < 1e-14
+    # closed form ||X||^2 + ||Y||^2 - 2 ||Y^T X||_* at a non-small distance
+    nuc = np.linalg.norm(Y.T @ X, "nuc")
+    cf = math.sqrt(np.sum(X * X) + np.sum(Y * Y) - 2 * nuc)
+    assert abs(O.dist_F(X, Y) - cf) < 1e-12 * cf
+
+
+def test_rel_err_gram_form_and_mse():
+    Z, A = _cfg0(n=50)
+    r = O.solve(A, 3, T=30)
+    assert abs(O.rel_err(r.X, Z, "gram") - O.rel_err(r.X, Z)) < 1e-9
+    assert abs(O.mse(r.X, Z) - O.alignment_error(r.X, Z) ** 2) < 1e-15
