@@ -1,0 +1,208 @@
+"""Benchmark of the NS-RGS hot path on one MI355X.
+
+Workload: n = 20000 blocks, d = 3 (A is 60000 x 60000), sigma = 0.2 sqrt(n/d),
+Haar ground truth, A generated on the device from the seeded counter-based
+generator (synthetic data, the paper's measurement model).  One timed step is
+one NS-RGS iteration (sync_step: the stream over A fused with the gradient
+step and the Newton-Schulz retraction of every block).  The headline value is
+iterations per second with A stored in FP32; the same loop is timed with A in
+BF16, BF16 hi+lo and FP8-e4m3 (row-scaled), and a full solve (spectral init +
+200 iterations) is run per format for accuracy against the ground truth.
+
+Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N, D = 20000, 3
+C_NOISE = 0.2
+SEED = 20000
+SOLVE_ITERS = 200
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for fn in ("stream_impl.h", "device.h"):
+        with open(os.path.join(ROOT, "paper_2604_07372_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile():
+    """HBM bytes per launch of the FP32 step kernel from committed rocprofv3
+    counter summaries, or None when they were taken on another kernel source."""
+    path = os.path.join(ROOT, "profiles", "step_f32_n20000_d3_counters.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except OSError:
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(budget_s: float = 12.0):
+    """The FP64 oracle's NS-RGS step timed on the host cores, on a bounded
+    sample: the n = 2000 sub-instance of the same model (A 6000 x 6000), one
+    oracle step per repetition, scaled to n = 20000 by the (nd)^2 cost ratio."""
+    import numpy as np
+    import synth
+    from oracle import nsrgs as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    n, d = 2000, D
+    Z = synth.haar_blocks(n, d, SEED)
+    A = synth.measurement_matrix(Z, synth.sigma_for(C_NOISE, n, d), SEED)
+    X = synth.perturbed_start(Z, 0.05, SEED + 1)
+    O.rgs_step(A, X, d, Ts=3)
+    reps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        X = O.rgs_step(A, X, d, Ts=3).X
+        reps += 1
+    dt = (time.perf_counter() - t0) / reps
+    scale = (N * D / (n * d)) ** 2
+    return {"value": 1.0 / (dt * scale), "unit": "iter/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{reps} FP64 oracle steps on the n=2000 sub-instance (A 6000x6000), "
+                      f"{dt * 1e3:.2f} ms each, scaled by (60000/6000)^2 = {scale:.0f} to n=20000"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--formats", default="f32,bf16,bf16_split,fp8")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {a.gpus}); this build has no multi-GPU path.",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    import paper_2604_07372_amd as P
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n, d = N, D
+    nd = n * d
+    sigma = synth.sigma_for(C_NOISE, n, d)
+    print(f"[bench] generating A: n={n} d={d} sigma={sigma:.4f}", file=sys.stderr, flush=True)
+    Z = synth.haar_blocks(n, d, SEED)
+    Zd = torch.from_numpy(Z).to(dev)
+    A32 = P.generate(Zd, sigma, SEED, fmt=P.F32)
+    stores = {"f32": P.stored(A32, P.F32)}
+    fmts = [f for f in a.formats.split(",") if f]
+    for name in fmts:
+        if name != "f32":
+            stores[name] = P.convert(A32, P.FORMATS[name])
+    torch.cuda.synchronize()
+    X0 = torch.from_numpy(synth.perturbed_start(Z, 0.05, SEED + 1)).to(dev, torch.float32)
+
+    results = {}
+    for name in fmts:
+        Am = stores[name]
+        ws = P.workspace(n, d, Am.fmt)
+        Xa, Xb = X0.clone(), torch.empty_like(X0)
+        for _ in range(a.warmup):
+            P.step(Am, n, d, Xa, Xb, ws)
+            Xa, Xb = Xb, Xa
+        torch.cuda.synchronize()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        start.record()
+        for _ in range(a.steps):
+            P.step(Am, n, d, Xa, Xb, ws)
+            Xa, Xb = Xb, Xa
+        end.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = start.elapsed_time(end) / a.steps
+        a_bytes = Am.data.shape[0] * Am.data.shape[0] * {"f32": 4, "bf16": 2, "bf16_split": 4, "fp8": 1}[name]
+        a_bytes += (nd * 4 if name == "fp8" else 0) + 2 * nd * d * 4
+        results[name] = {"ms_per_step": ms, "iters_per_s": 1e3 / ms, "wall_s": wall,
+                         "alg_bytes": a_bytes, "alg_GBps": a_bytes / (ms * 1e-3) / 1e9}
+        print(f"[bench] {name}: {ms:.4f} ms/iter, {1e3 / ms:.1f} it/s, "
+              f"{results[name]['alg_GBps']:.0f} GB/s", file=sys.stderr, flush=True)
+
+    solve = {}
+    if not a.no_solve:
+        from oracle import nsrgs as O   # metric only: alignment error of the GPU result vs Z
+        pred = sigma * math.sqrt(d * (d - 1) / (2.0 * n))
+        for name in fmts:
+            Am = stores[name]
+            ws = P.workspace(n, d, Am.fmt)
+            X = torch.empty((nd, d), dtype=torch.float32, device=dev)
+            kw = {}
+            if name in ("bf16", "fp8"):
+                kw = dict(refine_iters=10, A_refine=stores["f32"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = P.solve(Am, n, d, X, ws, ns_steps=3, max_iters=SOLVE_ITERS, **kw)
+            dt = time.perf_counter() - t0
+            e = O.alignment_error(X.cpu().double().numpy(), Z)
+            solve[name] = {"solve_s": dt, "align_err": e, "first_order_pred": pred,
+                           "iters": info["iters"], "init_residual": info["init_residual"],
+                           "refine_iters": kw.get("refine_iters", 0)}
+            print(f"[bench] solve {name}: {dt:.3f} s, align err {e:.6f} (first-order {pred:.6f})",
+                  file=sys.stderr, flush=True)
+        ref = solve.get("f32", {}).get("align_err")
+        if ref:
+            for name in solve:
+                solve[name]["align_err_rel_vs_f32"] = abs(solve[name]["align_err"] - ref) / ref
+
+    f32 = results["f32"]
+    roof = {"bound": "hbm", "achieved": f32["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": f32["alg_GBps"] / HBM_PEAK_GBS, "traffic": traffic_from_profile(),
+            "kernel": "stream_kernel<F32, d=3, mode 0> (sync_step)",
+            "alg_bytes_per_launch": f32["alg_bytes"]}
+    cpu = None
+    if not a.no_cpu_baseline:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        cpu = cpu_baseline()
+    out = {
+        "metric": "NS-RGS iters/s (sync_step, n=20000, d=3, FP32 A)",
+        "value": f32["iters_per_s"],
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": f32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (A = ZZ^T + sigma W generated on device, Philox4x32-10)",
+        "config": {"workload": "dense NS-RGS step, n=20000, d=3, sigma=0.2*sqrt(n/d), A 60000x60000",
+                   "n": n, "d": d, "ns_steps": 3, "mu": "1/n"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "formats": {k: {kk: round(vv, 4) if isinstance(vv, float) else vv for kk, vv in r.items()}
+                    for k, r in results.items()},
+        "speedup_vs_f32": {k: results["f32"]["ms_per_step"] / r["ms_per_step"] for k, r in results.items()},
+        "solve": solve,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,194 @@
+/*
+ * nsrgs.h -- C ABI of the NS-RGS library for AMD MI355X (gfx950).
+ *
+ * NS-RGS (Peng, Han, Chen, Huang, "NS-RGS: Newton-Schulz Based Riemannian
+ * Gradient Method for Orthogonal Group Synchronization") recovers
+ * Z_1..Z_n in O(d) from the symmetric block measurement matrix
+ *     A = Z Z^T + sigma W   (nd x nd, blocks A_ij = Z_i Z_j^T + sigma W_ij),
+ * Sec. 2.2, eq. (def:measurements).  Algorithm 2 starts from the spectral
+ * initialization X^0 = sgn(Y), Y the top-d eigenvectors of A, and then for
+ * every block i in parallel (a Jacobi sweep over X^t):
+ *     G_i = sum_{j != i} (X_i - A_ij X_j)            (Euclidean gradient)
+ *     F_i = X_i - mu (G_i - X_i G_i^T X_i) / 2        (pseudo tangent step)
+ *     X_i <- S^{Ts}(F_i),  S: S <- S (3I - S^T S)/2   (Algorithm 1)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every pointer argument named A/X/ws/out is a DEVICE pointer (HIP memory
+ *   of the current device) owned by the caller.  The library never frees it.
+ *   Pointers to nsrgs_matrix / nsrgs_info / option structs are HOST pointers.
+ * - Stacked d x d blocks: an "n*d x d" array X is row-major, block i occupying
+ *   rows [i*d, (i+1)*d).  X is double when A is NSRGS_A_F64, float otherwise.
+ * - A is row-major with leading dimension ld (elements): element (r, c) at
+ *   r*ld + c.  ld >= n*d and ld % 16 == 0; the buffer holds n*d full rows of
+ *   ld elements (padding columns are never used as data); base pointers are
+ *   16-byte aligned.  A must be symmetric; only the off-diagonal blocks enter
+ *   the gradient, the diagonal blocks enter only the spectral initialization.
+ * - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue work
+ *   on it and return without waiting unless stated otherwise.
+ * - Return value: an nsrgs_status.  On error nothing has been enqueued and
+ *   nsrgs_last_error() (per calling thread) describes the problem.  Device
+ *   errors of earlier asynchronous work surface as NSRGS_ERR_DEVICE.
+ * - Limits: 2 <= n, 1 <= d <= 16, n*d < 2^31.
+ * - The library never allocates device memory inside sync_step / sync_solve /
+ *   sync_init_spectral: scratch space is the caller's workspace `ws` of
+ *   sync_workspace_bytes() bytes, prepared once by sync_workspace_init().
+ *   Two calls that run at the same time must not share a workspace.
+ */
+#ifndef NSRGS_H
+#define NSRGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NSRGS_VERSION 100
+
+typedef enum {
+  NSRGS_OK = 0,
+  NSRGS_ERR_INVALID_ARG = 1,   /* bad size, pointer, alignment, aliasing, format */
+  NSRGS_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement   */
+  NSRGS_ERR_OUT_OF_MEMORY = 3, /* workspace too small / server memory exhausted  */
+  NSRGS_ERR_DEVICE = 4,        /* a HIP runtime call failed                      */
+  NSRGS_ERR_NOT_CONVERGED = 5, /* tolerance not met within the budget            */
+  NSRGS_ERR_NONFINITE = 6      /* a NaN/Inf appeared in an iterate               */
+} nsrgs_status;
+
+/* Storage formats of A (precision forms).  The reduced formats are produced
+ * from an FP32 matrix by nsrgs_convert(). */
+typedef enum {
+  NSRGS_A_F64 = 0,        /* double                                              */
+  NSRGS_A_F32 = 1,        /* float                                               */
+  NSRGS_A_BF16 = 2,       /* bfloat16 (uint16 codes), round-to-nearest-even of A */
+  NSRGS_A_BF16_SPLIT = 3, /* hi = bf16(A) in `data`, lo = bf16(A - hi) in
+                             `data_lo`; the value used is hi + lo               */
+  NSRGS_A_FP8_E4M3 = 4    /* OCP e4m3 codes (uint8) and per-row float scales
+                             s_r = max_c |A_rc| / 448; value = s_r * e4m3(code) */
+} nsrgs_a_format;
+
+typedef struct {
+  int32_t fmt;             /* nsrgs_a_format                                    */
+  const void *data;        /* device; n*d rows of ld elements                   */
+  const void *data_lo;     /* device; BF16_SPLIT low part (same layout), else NULL */
+  const float *row_scale;  /* device; FP8 per-row scales (n*d floats), else NULL */
+  int64_t ld;              /* leading dimension in elements                     */
+} nsrgs_matrix;
+
+/* Monitors of the last iteration, filled from device memory by the calls
+ * that synchronize (sync_solve, sync_init_spectral, sync_read_info). */
+typedef struct {
+  int32_t iters;            /* iterations done (solve) / subspace iterations (init) */
+  int32_t nonfinite;        /* 1 if a NaN/Inf was seen in the last iterate          */
+  int32_t converged;        /* 1 if the tolerance was met                           */
+  int32_t status;           /* nsrgs_status of the whole call                       */
+  double rel_change;        /* ||X^{t+1}-X^t||_F / ||X^t||_F of the last step       */
+  double max_orth_defect;   /* max_i ||I - F_i^T F_i||_F of the last step           */
+  double init_residual;     /* init: ||A Y - Y T||_F / ||T||_F of the last iteration */
+  double ritz[16];          /* init: top-d Ritz values (descending)                 */
+  double ritz_next;         /* reserved (NaN)                                        */
+} nsrgs_info;
+
+/* Options of sync_solve beyond the arguments named in its signature.
+ * Pass NULL for the defaults given in brackets. */
+typedef struct {
+  int32_t init;             /* 1: run sync_init_spectral into X first [1]           */
+  int32_t init_iters;       /* max subspace iterations of the init [60]             */
+  double init_tol;          /* init: relative residual tolerance [0: default]      */
+  int32_t refine_iters;     /* precision form: final iterations on A_refine [0]     */
+  const nsrgs_matrix *A_refine; /* matrix for those iterations (e.g. F32 or
+                                   BF16_SPLIT copy of A), or NULL [NULL]          */
+  int32_t check_every;      /* iterations enqueued between host checks [16]         */
+} nsrgs_solve_opts;
+
+/* ---- status and version ------------------------------------------------ */
+const char *nsrgs_status_string(int status);
+const char *nsrgs_last_error(void);
+int nsrgs_version(void);
+
+/* ---- workspace ----------------------------------------------------------
+ * Bytes of device workspace needed by sync_step / sync_solve /
+ * sync_init_spectral for one problem of size (n, d) in format fmt (0 on
+ * invalid arguments).  sync_workspace_init clears its control words
+ * (asynchronously, on `stream`); every later call leaves them cleared. */
+size_t sync_workspace_bytes(int n, int d, int fmt);
+int sync_workspace_init(void *ws, size_t ws_bytes, void *stream);
+
+/* ---- sync_step: one iteration of Algorithm 2 (paper Sec. 2.2) -------------
+ * X_out = NS-RGS update of X_in: for every block i,
+ *   C_i = sum_{j != i} A_ij X_in_j, G_i = (n-1) X_in_i - C_i,
+ *   F_i = X_in_i - mu (G_i - X_in_i G_i^T X_in_i)/2,
+ *   X_out_i = ns_steps Newton-Schulz steps from F_i (Algorithm 1).
+ * A is streamed from memory once; C, G and F stay on chip.
+ * mu <= 0 selects mu = 1/n (Theorem 3.1).  ns_steps in [0, 64].
+ * X_in and X_out are n*d x d device arrays that must not overlap.
+ * Monitors (rel_change, max_orth_defect, nonfinite) go to the workspace and
+ * can be read with sync_read_info.  Asynchronous. */
+int sync_step(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps,
+              const void *X_in, void *X_out, void *ws, size_t ws_bytes,
+              void *stream);
+
+/* Copy the monitors of the last step / init on this workspace to *info
+ * (waits for `stream`). */
+int sync_read_info(const void *ws, size_t ws_bytes, int n, int d, int fmt,
+                   nsrgs_info *info, void *stream);
+
+/* ---- sync_init_spectral: spectral initialization (Alg. 2) -----------------
+ * Y = top-d (largest algebraic) eigenvectors of A by block subspace
+ * iteration on d columns, Y_{k+1} = (A Y_k) R^{-1} with A Y_k = Q R by
+ * Cholesky-QR (Grams reduced and factored in FP64), then X0_i = sgn(Y_i) for
+ * every block (Newton-Schulz in FP64 from the Frobenius-scaled block, run to
+ * convergence: the exact polar factor).  Stops after the first iteration
+ * k >= 1 with ||A Y_k - Y_k T_k||_F <= tol ||T_k||_F, T_k = Y_k^T A Y_k
+ * (tol <= 0: 1e-13 for F64 storage, 1e-5 otherwise), or after max_iters
+ * iterations (<= 0: 60; returns NSRGS_ERR_NOT_CONVERGED, X0 still written).
+ * info->ritz receives the eigenvalues of T_k (FP64 Jacobi), descending.
+ * Subspace iteration finds the dominant (largest |lambda|) subspace, which is
+ * the top-d one whenever lambda_d > |lambda_min| (true below the spectral
+ * threshold of the measurement model).  X0 is an n*d x d device array.
+ * Waits for the stream and fills *info (nullable). */
+int sync_init_spectral(const nsrgs_matrix *A, int n, int d, void *X0,
+                       int max_iters, double tol, void *ws, size_t ws_bytes,
+                       void *stream, nsrgs_info *info);
+
+/* ---- sync_solve: Algorithm 2 end to end -----------------------------------
+ * X (device, n*d x d) receives the result; with opts->init == 0 it must hold
+ * X^0 on entry.  Runs at most max_iters iterations; tol > 0 stops after the
+ * first iteration with ||X^{t+1}-X^t||_F / ||X^t||_F <= tol (tol <= 0 runs
+ * exactly max_iters).  With opts->refine_iters = k > 0 and opts->A_refine
+ * set, the last k of the max_iters iterations run on A_refine instead of A
+ * (after an early stop on A, k more iterations run on A_refine).
+ * Waits for the stream and fills *info (nullable).  Returns NSRGS_ERR_NONFINITE
+ * if an iterate became non-finite. */
+int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps,
+               int max_iters, double tol, void *X, void *ws, size_t ws_bytes,
+               void *stream, const nsrgs_solve_opts *opts, nsrgs_info *info);
+
+/* ---- inputs: measurement generator and format conversion ----------------
+ * nsrgs_generate_measurement writes A = Z Z^T + sigma W in F64 or F32
+ * (fmt), element (r, c) computed in double and rounded once, where
+ * W(r, c) = W(c, r) = sqrt(-2 ln u1) cos(2 pi u2) with u1, u2 53-bit uniforms
+ * from Philox4x32-10 (Salmon et al., SC'11) at counter
+ * (max(r,c), min(r,c), 0, 0) and key (seed mod 2^32, seed >> 32).
+ * zero_diag_blocks != 0 sets W_ii = 0 (paper's model, A_ii = I).  p < 1 keeps
+ * an off-diagonal block pair with probability p (counter (j, i, 1, 0) for
+ * blocks i < j, uniform from the first output word), else A_ij = A_ji = 0.
+ * Z is an n*d x d double device array.  Asynchronous. */
+int nsrgs_generate_measurement(const double *Z, int n, int d, double sigma,
+                               uint64_t seed, int zero_diag_blocks, double p,
+                               int fmt, void *A, int64_t ld, void *stream);
+
+/* Convert an FP32 matrix (nd x nd, leading dimension ld) into `out` of format
+ * out->fmt (BF16, BF16_SPLIT or FP8_E4M3, same ld); out's pointers name the
+ * destination buffers (data, data_lo, row_scale).  Round to nearest even;
+ * e4m3 saturates to +-448.  Asynchronous. */
+int nsrgs_convert(const float *A32, int nd, int64_t ld, const nsrgs_matrix *out,
+                  void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NSRGS_H */

@@ -1,0 +1,288 @@
+"""NS-RGS on AMD MI355X: Python binding of libnsrgs.so (the C ABI in include/nsrgs.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch provides device memory and the current HIP stream.  The
+binding refuses to work without the compiled library (no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import torch
+
+__all__ = [
+    "F64", "F32", "BF16", "BF16_SPLIT", "FP8_E4M3", "FORMATS", "NsrgsError",
+    "lib", "StoredMatrix", "Workspace", "workspace", "step", "read_info",
+    "init_spectral", "solve", "generate", "convert", "stored", "padded_ld",
+    "Info",
+]
+
+F64, F32, BF16, BF16_SPLIT, FP8_E4M3 = 0, 1, 2, 3, 4
+FORMATS = {"f64": F64, "f32": F32, "bf16": BF16, "bf16_split": BF16_SPLIT, "fp8": FP8_E4M3}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnsrgs.so")
+
+
+class NsrgsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"nsrgs status {status}: {message}")
+        self.status = status
+
+
+class _Matrix(ctypes.Structure):
+    _fields_ = [("fmt", ctypes.c_int32), ("data", ctypes.c_void_p), ("data_lo", ctypes.c_void_p),
+                ("row_scale", ctypes.c_void_p), ("ld", ctypes.c_int64)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("nonfinite", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("rel_change", ctypes.c_double), ("max_orth_defect", ctypes.c_double),
+                ("init_residual", ctypes.c_double), ("ritz", ctypes.c_double * 16),
+                ("ritz_next", ctypes.c_double)]
+
+    def as_dict(self, d: int | None = None) -> dict:
+        out = {k: getattr(self, k) for k, _ in self._fields_ if k != "ritz"}
+        out["ritz"] = list(self.ritz)[: (d or 16)]
+        return out
+
+
+class _SolveOpts(ctypes.Structure):
+    _fields_ = [("init", ctypes.c_int32), ("init_iters", ctypes.c_int32),
+                ("init_tol", ctypes.c_double), ("refine_iters", ctypes.c_int32),
+                ("A_refine", ctypes.POINTER(_Matrix)), ("check_every", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libnsrgs.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_07372_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    pm = ctypes.POINTER(_Matrix)
+    sig = {
+        "nsrgs_status_string": (ctypes.c_char_p, [i32]),
+        "nsrgs_last_error": (ctypes.c_char_p, []),
+        "nsrgs_version": (i32, []),
+        "sync_workspace_bytes": (sz, [i32, i32, i32]),
+        "sync_workspace_init": (i32, [vp, sz, vp]),
+        "sync_step": (i32, [pm, i32, i32, dbl, i32, vp, vp, vp, sz, vp]),
+        "sync_read_info": (i32, [vp, sz, i32, i32, i32, ctypes.POINTER(Info), vp]),
+        "sync_init_spectral": (i32, [pm, i32, i32, vp, i32, dbl, vp, sz, vp, ctypes.POINTER(Info)]),
+        "sync_solve": (i32, [pm, i32, i32, dbl, i32, i32, dbl, vp, vp, sz, vp,
+                             ctypes.POINTER(_SolveOpts), ctypes.POINTER(Info)]),
+        "nsrgs_generate_measurement": (i32, [vp, i32, i32, dbl, ctypes.c_uint64, i32, dbl, i32, vp, i64, vp]),
+        "nsrgs_convert": (i32, [vp, i32, i64, pm, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int, allow=()):
+    if status != 0 and status not in allow:
+        msg = lib().nsrgs_last_error().decode() or lib().nsrgs_status_string(status).decode()
+        raise NsrgsError(status, msg)
+    return status
+
+
+def _stream(device=None) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def padded_ld(nd: int) -> int:
+    """Smallest leading dimension >= nd that the library accepts (multiple of 16)."""
+    return (nd + 15) // 16 * 16
+
+
+class StoredMatrix:
+    """Device storage of A in one format: tensors plus the leading dimension.
+
+    data     : F64 float64 / F32 float32 / BF16 and BF16_SPLIT int16 codes /
+               FP8 uint8 codes, shape (nd, ld)
+    data_lo  : BF16_SPLIT low part, same shape
+    row_scale: FP8 per-row float32 scales, shape (nd,)
+    """
+
+    def __init__(self, fmt: int, data: torch.Tensor, nd: int, data_lo=None, row_scale=None):
+        self.fmt = int(fmt)
+        self.data = data
+        self.data_lo = data_lo
+        self.row_scale = row_scale
+        self.nd = int(nd)
+        self.ld = int(data.shape[1])
+
+    def c(self) -> _Matrix:
+        return _Matrix(self.fmt, _ptr(self.data), _ptr(self.data_lo), _ptr(self.row_scale), self.ld)
+
+    @property
+    def nbytes(self) -> int:
+        tot = self.data.numel() * self.data.element_size()
+        if self.data_lo is not None:
+            tot += self.data_lo.numel() * self.data_lo.element_size()
+        if self.row_scale is not None:
+            tot += self.row_scale.numel() * 4
+        return tot
+
+
+def stored(A: torch.Tensor, fmt: int = F32) -> StoredMatrix:
+    """Wrap a float32/float64 device matrix (nd x ld, ld padded) as F32/F64 storage,
+    or convert a float32 one into BF16 / BF16_SPLIT / FP8 on the device."""
+    nd = A.shape[0]
+    if fmt in (F64, F32):
+        want = torch.float64 if fmt == F64 else torch.float32
+        if A.dtype != want:
+            raise TypeError(f"format {fmt} needs a {want} matrix")
+        return StoredMatrix(fmt, A, nd)
+    return convert(A, fmt)
+
+
+class Workspace:
+    """Device workspace for one (n, d, precision) problem; prepared on creation."""
+
+    def __init__(self, n: int, d: int, fmt: int, device="cuda"):
+        nbytes = lib().sync_workspace_bytes(n, d, fmt)
+        if nbytes == 0:
+            raise NsrgsError(1, f"invalid workspace request n={n} d={d} fmt={fmt}")
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-buf.data_ptr()) % 256
+        self._buf = buf
+        self.tensor = buf[off: off + nbytes]
+        self.nbytes = nbytes
+        self.n, self.d, self.fmt = n, d, fmt
+        _check(lib().sync_workspace_init(self.ptr, nbytes, _stream()))
+
+    @property
+    def ptr(self) -> int:
+        return self.tensor.data_ptr()
+
+
+def workspace(n: int, d: int, fmt: int, device="cuda") -> Workspace:
+    return Workspace(n, d, fmt, device)
+
+
+def _xdtype(fmt: int):
+    return torch.float64 if fmt == F64 else torch.float32
+
+
+def _check_x(X: torch.Tensor, nd: int, d: int, fmt: int, name: str):
+    if not X.is_cuda or X.dtype != _xdtype(fmt) or tuple(X.shape) != (nd, d) or not X.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {_xdtype(fmt)} CUDA tensor of shape ({nd}, {d})")
+
+
+def step(A: StoredMatrix, n: int, d: int, X_in: torch.Tensor, X_out: torch.Tensor,
+         ws: Workspace, mu: float = 0.0, ns_steps: int = 3) -> None:
+    """One NS-RGS iteration (sync_step), asynchronous on the current stream."""
+    _check_x(X_in, n * d, d, A.fmt, "X_in")
+    _check_x(X_out, n * d, d, A.fmt, "X_out")
+    m = A.c()
+    _check(lib().sync_step(ctypes.byref(m), n, d, float(mu), int(ns_steps), X_in.data_ptr(),
+                           X_out.data_ptr(), ws.ptr, ws.nbytes, _stream()))
+
+
+def read_info(ws: Workspace) -> dict:
+    info = Info()
+    _check(lib().sync_read_info(ws.ptr, ws.nbytes, ws.n, ws.d, ws.fmt, ctypes.byref(info), _stream()))
+    return info.as_dict(ws.d)
+
+
+def init_spectral(A: StoredMatrix, n: int, d: int, X0: torch.Tensor, ws: Workspace,
+                  max_iters: int = 0, tol: float = 0.0, check: bool = True) -> dict:
+    """Spectral initialization X0 = sgn(top-d eigenvectors of A) (sync_init_spectral)."""
+    _check_x(X0, n * d, d, A.fmt, "X0")
+    m = A.c()
+    info = Info()
+    st = lib().sync_init_spectral(ctypes.byref(m), n, d, X0.data_ptr(), int(max_iters), float(tol),
+                                  ws.ptr, ws.nbytes, _stream(), ctypes.byref(info))
+    if check:
+        _check(st, allow=(5,))
+    out = info.as_dict(d)
+    out["status"] = st
+    return out
+
+
+def solve(A: StoredMatrix, n: int, d: int, X: torch.Tensor, ws: Workspace, mu: float = 0.0,
+          ns_steps: int = 3, max_iters: int = 100, tol: float = 0.0, init: bool = True,
+          init_iters: int = 60, init_tol: float = 0.0, refine_iters: int = 0,
+          A_refine: StoredMatrix | None = None, check_every: int = 16, check: bool = True) -> dict:
+    """Algorithm 2 end to end (sync_solve).  X receives the result (and holds X0 if init=False)."""
+    _check_x(X, n * d, d, A.fmt, "X")
+    m = A.c()
+    mref = A_refine.c() if A_refine is not None else None
+    opts = _SolveOpts(int(init), int(init_iters), float(init_tol), int(refine_iters),
+                      ctypes.pointer(mref) if mref is not None else None, int(check_every))
+    info = Info()
+    st = lib().sync_solve(ctypes.byref(m), n, d, float(mu), int(ns_steps), int(max_iters), float(tol),
+                          X.data_ptr(), ws.ptr, ws.nbytes, _stream(), ctypes.byref(opts), ctypes.byref(info))
+    if check:
+        _check(st, allow=(5,))
+    out = info.as_dict(d)
+    out["status"] = st
+    return out
+
+
+def generate(Z: torch.Tensor, sigma: float, seed: int, fmt: int = F32, zero_diag_blocks: bool = False,
+             p: float = 1.0, ld: int | None = None) -> torch.Tensor:
+    """A = Z Z^T + sigma W on the device (Philox4x32-10 noise); F64 or F32, shape (nd, ld)."""
+    if not Z.is_cuda or Z.dtype != torch.float64 or Z.dim() != 2 or not Z.is_contiguous():
+        raise ValueError("Z must be a contiguous float64 CUDA tensor (n*d, d)")
+    nd, d = Z.shape
+    n = nd // d
+    ld = ld or padded_ld(nd)
+    A = torch.empty((nd, ld), dtype=_xdtype(fmt), device=Z.device)
+    if ld > nd:
+        A[:, nd:].zero_()
+    _check(lib().nsrgs_generate_measurement(Z.data_ptr(), n, d, float(sigma), int(seed),
+                                            int(zero_diag_blocks), float(p), int(fmt), A.data_ptr(),
+                                            ld, _stream()))
+    return A
+
+
+def convert(A32: torch.Tensor, fmt: int) -> StoredMatrix:
+    """One-time conversion of an FP32 device matrix (nd, ld) into BF16 / BF16_SPLIT / FP8."""
+    if not A32.is_cuda or A32.dtype != torch.float32 or A32.dim() != 2 or not A32.is_contiguous():
+        raise ValueError("A32 must be a contiguous float32 CUDA tensor (nd, ld)")
+    nd, ld = A32.shape
+    if fmt in (BF16, BF16_SPLIT):
+        data = torch.zeros((nd, ld), dtype=torch.int16, device=A32.device)
+        lo = torch.zeros((nd, ld), dtype=torch.int16, device=A32.device) if fmt == BF16_SPLIT else None
+        out = StoredMatrix(fmt, data, nd, data_lo=lo)
+    elif fmt == FP8_E4M3:
+        data = torch.zeros((nd, ld), dtype=torch.uint8, device=A32.device)
+        sc = torch.empty((nd,), dtype=torch.float32, device=A32.device)
+        out = StoredMatrix(fmt, data, nd, row_scale=sc)
+    else:
+        raise ValueError(f"cannot convert to format {fmt}")
+    m = out.c()
+    _check(lib().nsrgs_convert(A32.data_ptr(), nd, ld, ctypes.byref(m), _stream()))
+    return out
+
+
+def upload(A: "numpy.ndarray", fmt: int = F32, device="cuda") -> StoredMatrix:  # noqa: F821
+    """Copy a host matrix (nd x nd, float64) to the device in F64 or F32 with padded ld."""
+    import numpy as np
+    nd = A.shape[0]
+    ld = padded_ld(nd)
+    host = np.zeros((nd, ld), dtype=np.float64 if fmt == F64 else np.float32)
+    host[:, :nd] = A
+    t = torch.from_numpy(host).to(device)
+    return StoredMatrix(fmt, t, nd)
+
+
+__all__.append("upload")

@@ -1,0 +1,458 @@
+// C ABI of the NS-RGS library: argument checks, workspace layout, launch
+// configuration and the host side of the solve loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "device.h"
+#include "kernels.h"
+#include "nsrgs.h"
+
+namespace nsrgs {
+
+static thread_local std::string g_last_error;
+
+static int fail(int status, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return status;
+}
+
+static int dev_fail(hipError_t e, const char *what) {
+  return fail(NSRGS_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define NSRGS_HIP(call, what)                 \
+  do {                                        \
+    hipError_t e_ = (call);                   \
+    if (e_ != hipSuccess) return dev_fail(e_, what); \
+  } while (0)
+
+static bool valid_fmt(int fmt) { return fmt >= NSRGS_A_F64 && fmt <= NSRGS_A_FP8_E4M3; }
+static size_t xbytes(int fmt) { return fmt == NSRGS_A_F64 ? 8 : 4; }
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// ---- workspace layout ------------------------------------------------------
+struct WsLayout {
+  size_t ctl, stats, xalt, y0, y1, w, parts, total;
+};
+
+static WsLayout layout(int n, int d, int fmt) {
+  const size_t nd = (size_t)n * d;
+  const size_t xb = xbytes(fmt);
+  WsLayout L{};
+  size_t off = 0;
+  L.ctl = off;   off += align256(sizeof(DevCtl));
+  L.stats = off; off += align256((size_t)n * sizeof(PanelStat));  // <= n panels
+  L.xalt = off;  off += align256(nd * d * xb);                    // ping-pong iterate
+  L.y0 = off;    off += align256(nd * d * xb);                    // init basis
+  L.y1 = off;    off += align256(nd * d * xb);
+  L.w = off;     off += align256(nd * d * xb);                    // A Y
+  const size_t gram = (size_t)n * 2 * d * d * xb;                 // <= n panels
+  const size_t apply = ((nd + 255) / 256) * 2 * sizeof(double);
+  L.parts = off; off += align256(std::max(gram, apply));
+  L.total = off;
+  return L;
+}
+
+static int check_common(int n, int d) {
+  if (n < 2) return fail(NSRGS_ERR_INVALID_ARG, "n must be >= 2 (got %d)", n);
+  if (d < 1 || d > kMaxD) return fail(NSRGS_ERR_INVALID_ARG, "d must be in [1, %d] (got %d)", kMaxD, d);
+  if ((int64_t)n * d >= (int64_t)1 << 31) return fail(NSRGS_ERR_INVALID_ARG, "n*d too large");
+  return NSRGS_OK;
+}
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+static int check_matrix(const nsrgs_matrix *A, int n, int d) {
+  if (!A) return fail(NSRGS_ERR_INVALID_ARG, "A is NULL");
+  if (!valid_fmt(A->fmt)) return fail(NSRGS_ERR_INVALID_ARG, "unknown A format %d", (int)A->fmt);
+  if (!A->data) return fail(NSRGS_ERR_INVALID_ARG, "A->data is NULL");
+  const int64_t nd = (int64_t)n * d;
+  if (A->ld < nd) return fail(NSRGS_ERR_INVALID_ARG, "ld (%lld) < n*d (%lld)", (long long)A->ld, (long long)nd);
+  if (A->ld % 16) return fail(NSRGS_ERR_INVALID_ARG, "ld (%lld) must be a multiple of 16", (long long)A->ld);
+  if (!aligned16(A->data)) return fail(NSRGS_ERR_INVALID_ARG, "A->data must be 16-byte aligned");
+  if (A->fmt == NSRGS_A_BF16_SPLIT) {
+    if (!A->data_lo) return fail(NSRGS_ERR_INVALID_ARG, "BF16_SPLIT needs data_lo");
+    if (!aligned16(A->data_lo)) return fail(NSRGS_ERR_INVALID_ARG, "A->data_lo must be 16-byte aligned");
+  }
+  if (A->fmt == NSRGS_A_FP8_E4M3 && !A->row_scale)
+    return fail(NSRGS_ERR_INVALID_ARG, "FP8_E4M3 needs row_scale");
+  return NSRGS_OK;
+}
+
+static int check_ws(const void *ws, size_t ws_bytes, int n, int d, int fmt) {
+  if (!ws) return fail(NSRGS_ERR_INVALID_ARG, "workspace is NULL");
+  if (((uintptr_t)ws & 255u) != 0) return fail(NSRGS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  const size_t need = layout(n, d, fmt).total;
+  if (ws_bytes < need)
+    return fail(NSRGS_ERR_OUT_OF_MEMORY, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  return NSRGS_OK;
+}
+
+static bool overlap(const void *a, const void *b, size_t bytes) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + bytes && y < x + bytes;
+}
+
+// ---- launch configuration --------------------------------------------------
+static int env_int(const char *name, int dflt) {
+  const char *v = getenv(name);
+  return (v && *v) ? atoi(v) : dflt;
+}
+
+StreamConfig choose_stream_config(int fmt, int d, int nd, int mode) {
+  StreamConfig cfg{stream_block_init(d), 1, 1};
+  if (mode == 0) {
+    StreamConfig v[16];
+    const int nv = stream_variants(d, v, 16);
+    // Default: the largest panel with at most 12 rows (24 for the 1- and
+    // 2-byte formats, whose X slice per load is wider), one vector per row per
+    // iteration; FP32 at d = 3 takes two (measured best at n = 20000).
+    // Environment overrides select any compiled variant.
+    const int max_rows = (fmt == NSRGS_A_BF16 || fmt == NSRGS_A_FP8_E4M3) ? 24 : 12;
+    for (int i = 0; i < nv; ++i)
+      if (v[i].unroll == 1 && v[i].blocks_per_panel * d <= max_rows &&
+          v[i].blocks_per_panel > cfg.blocks_per_panel)
+        cfg.blocks_per_panel = v[i].blocks_per_panel;
+    if (fmt == NSRGS_A_F32 && d == 3) cfg.unroll = 2;
+    const int fb = env_int("NSRGS_STEP_B", 0), fu = env_int("NSRGS_STEP_U", 0);
+    if (fb > 0 || fu > 0) {
+      const int wb = fb > 0 ? fb : cfg.blocks_per_panel, wu = fu > 0 ? fu : cfg.unroll;
+      for (int i = 0; i < nv; ++i)
+        if (v[i].blocks_per_panel == wb && v[i].unroll == wu) {
+          cfg.blocks_per_panel = wb;
+          cfg.unroll = wu;
+        }
+    }
+  }
+  const int R = cfg.blocks_per_panel * d;
+  const int panels = (nd + R - 1) / R;
+  // Enough waves to cover 256 CUs several times over, while every wave keeps
+  // a few column groups of work.
+  const int V = fmt == NSRGS_A_F64 ? 2 : fmt == NSRGS_A_F32 ? 4 : fmt == NSRGS_A_FP8_E4M3 ? 16 : 8;
+  const int group = 64 * V * cfg.unroll;
+  const int groups = (nd + group - 1) / group;
+  int W = 1;
+  while (W < kMaxWaves && (int64_t)panels * W < 8192 && groups / (2 * W) >= 4) W *= 2;
+  const int forced_w = env_int("NSRGS_STEP_W", 0);
+  if (forced_w >= 1 && forced_w <= kMaxWaves) W = forced_w;
+  cfg.waves = W;
+  return cfg;
+}
+
+static StreamArgs make_args(const nsrgs_matrix *A, int n, int d, const StreamConfig &cfg) {
+  StreamArgs a{};
+  a.A = A->data;
+  a.A_lo = A->fmt == NSRGS_A_BF16_SPLIT ? A->data_lo : nullptr;
+  a.scale = A->fmt == NSRGS_A_FP8_E4M3 ? A->row_scale : nullptr;
+  a.ld = A->ld;
+  a.n = n;
+  a.d = d;
+  a.nd = n * d;
+  const int R = cfg.blocks_per_panel * d;
+  a.num_panels = (a.nd + R - 1) / R;
+  return a;
+}
+
+}  // namespace nsrgs
+
+using namespace nsrgs;
+
+extern "C" {
+
+const char *nsrgs_status_string(int status) {
+  switch (status) {
+    case NSRGS_OK: return "ok";
+    case NSRGS_ERR_INVALID_ARG: return "invalid argument";
+    case NSRGS_ERR_UNSUPPORTED: return "unsupported";
+    case NSRGS_ERR_OUT_OF_MEMORY: return "out of memory";
+    case NSRGS_ERR_DEVICE: return "device error";
+    case NSRGS_ERR_NOT_CONVERGED: return "not converged";
+    case NSRGS_ERR_NONFINITE: return "non-finite iterate";
+    default: return "unknown status";
+  }
+}
+
+const char *nsrgs_last_error(void) { return g_last_error.c_str(); }
+
+int nsrgs_version(void) { return NSRGS_VERSION; }
+
+size_t sync_workspace_bytes(int n, int d, int fmt) {
+  if (n < 2 || d < 1 || d > kMaxD || !valid_fmt(fmt)) return 0;
+  return layout(n, d, fmt).total;
+}
+
+int sync_workspace_init(void *ws, size_t ws_bytes, void *stream) {
+  if (!ws || ((uintptr_t)ws & 255u)) return fail(NSRGS_ERR_INVALID_ARG, "workspace must be non-NULL and 256-byte aligned");
+  if (ws_bytes < sizeof(DevCtl)) return fail(NSRGS_ERR_OUT_OF_MEMORY, "workspace too small");
+  NSRGS_HIP(launch_ctl_reset(static_cast<DevCtl *>(ws), 0, (hipStream_t)stream), "ctl reset");
+  return NSRGS_OK;
+}
+
+static int step_impl(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps,
+                     const void *X_in, void *X_out, void *ws, hipStream_t s, int iter,
+                     double tol, bool check_done) {
+  const StreamConfig cfg = choose_stream_config(A->fmt, d, n * d, 0);
+  StreamArgs a = make_args(A, n, d, cfg);
+  const WsLayout L = layout(n, d, A->fmt);
+  a.X_in = X_in;
+  a.X_out = X_out;
+  a.mu = mu > 0.0 ? mu : 1.0 / n;
+  a.ns_steps = ns_steps;
+  a.partials = static_cast<char *>(ws) + L.stats;
+  a.ctl = static_cast<DevCtl *>(ws);
+  a.iter = iter;
+  a.tol = tol;
+  a.stop_flag = check_done ? &a.ctl->done : nullptr;
+  NSRGS_HIP(launch_stream(0, A->fmt, cfg, a, s), "step launch");
+  return NSRGS_OK;
+}
+
+int sync_step(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
+              void *X_out, void *ws, size_t ws_bytes, void *stream) {
+  int st;
+  if ((st = check_common(n, d))) return st;
+  if ((st = check_matrix(A, n, d))) return st;
+  if ((st = check_ws(ws, ws_bytes, n, d, A->fmt))) return st;
+  if (!X_in || !X_out) return fail(NSRGS_ERR_INVALID_ARG, "X_in / X_out is NULL");
+  if (!aligned16(X_in) || !aligned16(X_out)) return fail(NSRGS_ERR_INVALID_ARG, "X buffers must be 16-byte aligned");
+  if (ns_steps < 0 || ns_steps > 64) return fail(NSRGS_ERR_INVALID_ARG, "ns_steps must be in [0, 64]");
+  if (!std::isfinite(mu)) return fail(NSRGS_ERR_INVALID_ARG, "mu must be finite");
+  const size_t xb = (size_t)n * d * d * xbytes(A->fmt);
+  if (overlap(X_in, X_out, xb)) return fail(NSRGS_ERR_INVALID_ARG, "X_in and X_out overlap");
+  return step_impl(A, n, d, mu, ns_steps, X_in, X_out, ws, (hipStream_t)stream, 0, 0.0, false);
+}
+
+static void fill_info(const DevCtl &c, int d, nsrgs_info *info, int status) {
+  if (!info) return;
+  memset(info, 0, sizeof(*info));
+  info->iters = c.iters;
+  info->nonfinite = c.nonfinite;
+  info->converged = c.converged;
+  info->status = status;
+  info->rel_change = c.rel_change;
+  info->max_orth_defect = c.max_defect;
+  info->init_residual = c.init_res;
+  for (int i = 0; i < d && i < 16; ++i) info->ritz[i] = c.ritz[i];
+  info->ritz_next = NAN;
+}
+
+static int read_ctl(const void *ws, DevCtl *host, hipStream_t s) {
+  NSRGS_HIP(hipMemcpyAsync(host, ws, sizeof(DevCtl), hipMemcpyDeviceToHost, s), "ctl readback");
+  NSRGS_HIP(hipStreamSynchronize(s), "stream sync");
+  return NSRGS_OK;
+}
+
+int sync_read_info(const void *ws, size_t ws_bytes, int n, int d, int fmt, nsrgs_info *info,
+                   void *stream) {
+  int st;
+  if ((st = check_common(n, d))) return st;
+  if (!valid_fmt(fmt)) return fail(NSRGS_ERR_INVALID_ARG, "unknown format");
+  if ((st = check_ws(ws, ws_bytes, n, d, fmt))) return st;
+  if (!info) return fail(NSRGS_ERR_INVALID_ARG, "info is NULL");
+  DevCtl c;
+  if ((st = read_ctl(ws, &c, (hipStream_t)stream))) return st;
+  fill_info(c, d, info, NSRGS_OK);
+  info->iters = c.iters ? c.iters : c.init_iters;
+  return NSRGS_OK;
+}
+
+static int init_impl(const nsrgs_matrix *A, int n, int d, void *X0, int max_iters, double tol,
+                     void *ws, hipStream_t s, DevCtl *out_ctl) {
+  const int nd = n * d;
+  const WsLayout L = layout(n, d, A->fmt);
+  char *base = static_cast<char *>(ws);
+  DevCtl *ctl = static_cast<DevCtl *>(ws);
+  void *Y[2] = {base + L.y0, base + L.y1};
+  void *W = base + L.w;
+  if (max_iters <= 0) max_iters = 60;
+  if (!(tol > 0.0)) tol = A->fmt == NSRGS_A_F64 ? 1e-13 : 1e-5;
+  NSRGS_HIP(launch_ctl_reset(ctl, 2, s), "ctl reset");
+  NSRGS_HIP(launch_init_random(A->fmt, Y[0], nd, d, 0x5eed5eedULL, s), "init random");
+  const StreamConfig cfg = choose_stream_config(A->fmt, d, nd, 1);
+  StreamArgs a = make_args(A, n, d, cfg);
+  a.mu = 0.0;
+  a.ns_steps = 0;
+  a.partials = base + L.parts;
+  a.ctl = ctl;
+  a.tol = 0.0;
+  a.stop_flag = &ctl->init_done;
+  InitArgs ia{};
+  ia.W = W;
+  ia.nd = nd;
+  ia.d = d;
+  ia.partials = base + L.stats;
+  ia.num_groups = (nd + 255) / 256;
+  ia.ctl = ctl;
+  ia.tol = tol;
+  // The stats area holds the apply partials: 2 doubles per 256 rows <= n * 32 bytes.
+  DevCtl host{};
+  int k = 0;
+  const int chunk = 4;
+  while (k < max_iters) {
+    const int kend = std::min(max_iters, k + chunk);
+    for (; k < kend; ++k) {
+      a.X_in = Y[k & 1];
+      a.X_out = W;
+      a.iter = k;
+      // Launches enqueued after the residual test has passed return at once
+      // (they watch init_done), so W, T and Y keep the converged iteration.
+      NSRGS_HIP(launch_stream(1, A->fmt, cfg, a, s), "init product");
+      ia.Y = Y[k & 1];
+      ia.Y_next = Y[(k + 1) & 1];
+      ia.iter = k;
+      NSRGS_HIP(launch_init_apply(A->fmt, ia, s), "init apply");
+    }
+    int st;
+    if ((st = read_ctl(ws, &host, s))) return st;
+    if (host.init_done) break;
+  }
+  // The basis of the last completed apply is in Y[init_iters & 1].
+  const int done_iters = host.init_iters;
+  NSRGS_HIP(launch_init_polar(A->fmt, Y[done_iters & 1], X0, n, d, ctl, s), "init polar");
+  NSRGS_HIP(launch_init_finish(ctl, d, s), "init finish");
+  int st;
+  if ((st = read_ctl(ws, &host, s))) return st;
+  if (out_ctl) *out_ctl = host;
+  if (host.init_bad) return fail(NSRGS_ERR_NONFINITE, "spectral init broke down (Cholesky/polar)");
+  if (!host.init_done) return NSRGS_ERR_NOT_CONVERGED;
+  return NSRGS_OK;
+}
+
+int sync_init_spectral(const nsrgs_matrix *A, int n, int d, void *X0, int max_iters, double tol,
+                       void *ws, size_t ws_bytes, void *stream, nsrgs_info *info) {
+  int st;
+  if ((st = check_common(n, d))) return st;
+  if ((st = check_matrix(A, n, d))) return st;
+  if ((st = check_ws(ws, ws_bytes, n, d, A->fmt))) return st;
+  if (!X0 || !aligned16(X0)) return fail(NSRGS_ERR_INVALID_ARG, "X0 must be non-NULL and 16-byte aligned");
+  DevCtl c{};
+  st = init_impl(A, n, d, X0, max_iters, tol, ws, (hipStream_t)stream, &c);
+  if (info) {
+    fill_info(c, d, info, st);
+    info->iters = c.init_iters;
+    info->converged = c.init_done && !c.init_bad;
+  }
+  return st;
+}
+
+int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, int max_iters,
+               double tol, void *X, void *ws, size_t ws_bytes, void *stream,
+               const nsrgs_solve_opts *opts, nsrgs_info *info) {
+  int st;
+  if ((st = check_common(n, d))) return st;
+  if ((st = check_matrix(A, n, d))) return st;
+  if ((st = check_ws(ws, ws_bytes, n, d, A->fmt))) return st;
+  if (!X || !aligned16(X)) return fail(NSRGS_ERR_INVALID_ARG, "X must be non-NULL and 16-byte aligned");
+  if (ns_steps < 0 || ns_steps > 64) return fail(NSRGS_ERR_INVALID_ARG, "ns_steps must be in [0, 64]");
+  if (max_iters < 0) return fail(NSRGS_ERR_INVALID_ARG, "max_iters must be >= 0");
+  if (!std::isfinite(mu)) return fail(NSRGS_ERR_INVALID_ARG, "mu must be finite");
+  nsrgs_solve_opts o{1, 60, 0.0, 0, nullptr, 16};
+  if (opts) o = *opts;
+  if (o.check_every <= 0) o.check_every = 16;
+  int refine = 0;
+  if (o.refine_iters > 0 && o.A_refine) {
+    if ((st = check_matrix(o.A_refine, n, d))) return st;
+    if (xbytes(o.A_refine->fmt) != xbytes(A->fmt))
+      return fail(NSRGS_ERR_INVALID_ARG, "A_refine must use the same iterate precision as A");
+    if ((st = check_ws(ws, ws_bytes, n, d, o.A_refine->fmt))) return st;
+    refine = std::min(o.refine_iters, max_iters);
+  } else if (o.refine_iters > 0) {
+    return fail(NSRGS_ERR_INVALID_ARG, "refine_iters > 0 needs A_refine");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const WsLayout L = layout(n, d, A->fmt);
+  void *buf[2] = {X, static_cast<char *>(ws) + L.xalt};
+  DevCtl host{};
+  int init_status = NSRGS_OK;
+  if (o.init) {
+    init_status = init_impl(A, n, d, X, o.init_iters, o.init_tol, ws, s, &host);
+    if (init_status != NSRGS_OK && init_status != NSRGS_ERR_NOT_CONVERGED) {
+      if (info) fill_info(host, d, info, init_status);
+      return init_status;
+    }
+  }
+  NSRGS_HIP(launch_ctl_reset(static_cast<DevCtl *>(ws), 1, s), "ctl reset");
+  // Phase 1 on A (early stop allowed), phase 2 on A_refine (fixed count).
+  const int phase1 = max_iters - refine;
+  int t = 0;
+  while (t < phase1) {
+    const int tend = std::min(phase1, t + o.check_every);
+    for (; t < tend; ++t)
+      if ((st = step_impl(A, n, d, mu, ns_steps, buf[t & 1], buf[(t + 1) & 1], ws, s, t,
+                          tol, true)))
+        return st;
+    if ((st = read_ctl(ws, &host, s))) return st;
+    if (host.done) break;
+  }
+  if ((st = read_ctl(ws, &host, s))) return st;
+  int done_iters = host.iters;
+  const bool stopped_nonfinite = host.nonfinite != 0;
+  if (refine > 0 && !stopped_nonfinite) {
+    NSRGS_HIP(launch_ctl_reset(static_cast<DevCtl *>(ws), 1, s), "ctl reset");
+    for (int r = 0; r < refine; ++r) {
+      const int tt = done_iters + r;
+      if ((st = step_impl(o.A_refine, n, d, mu, ns_steps, buf[tt & 1], buf[(tt + 1) & 1], ws, s,
+                          tt, 0.0, true)))
+        return st;
+    }
+    const int conv = host.converged;
+    if ((st = read_ctl(ws, &host, s))) return st;
+    done_iters = host.iters;
+    host.converged = conv;
+  }
+  if (done_iters & 1)
+    NSRGS_HIP(hipMemcpyAsync(X, buf[1], (size_t)n * d * d * xbytes(A->fmt),
+                             hipMemcpyDeviceToDevice, s), "result copy");
+  NSRGS_HIP(hipStreamSynchronize(s), "stream sync");
+  int result = NSRGS_OK;
+  if (host.nonfinite) result = fail(NSRGS_ERR_NONFINITE, "non-finite iterate at iteration %d", done_iters);
+  else if (tol > 0.0 && !host.converged) result = NSRGS_ERR_NOT_CONVERGED;
+  if (info) {
+    fill_info(host, d, info, result);
+    info->iters = done_iters;
+    info->init_residual = host.init_res;
+  }
+  (void)init_status;
+  return result;
+}
+
+int nsrgs_generate_measurement(const double *Z, int n, int d, double sigma, uint64_t seed,
+                               int zero_diag_blocks, double p, int fmt, void *A, int64_t ld,
+                               void *stream) {
+  int st;
+  if ((st = check_common(n, d))) return st;
+  if (fmt != NSRGS_A_F64 && fmt != NSRGS_A_F32)
+    return fail(NSRGS_ERR_INVALID_ARG, "generator writes F64 or F32 only");
+  if (!Z || !A) return fail(NSRGS_ERR_INVALID_ARG, "Z / A is NULL");
+  if (ld < (int64_t)n * d) return fail(NSRGS_ERR_INVALID_ARG, "ld < n*d");
+  if (!std::isfinite(sigma) || !(p > 0.0) || p > 1.0) return fail(NSRGS_ERR_INVALID_ARG, "bad sigma or p");
+  NSRGS_HIP(launch_generate(Z, n, d, sigma, seed, zero_diag_blocks, p, fmt, A, ld, (hipStream_t)stream),
+            "generate");
+  return NSRGS_OK;
+}
+
+int nsrgs_convert(const float *A32, int nd, int64_t ld, const nsrgs_matrix *out, void *stream) {
+  if (!A32 || !out || !out->data) return fail(NSRGS_ERR_INVALID_ARG, "NULL argument");
+  if (nd < 1 || ld < nd) return fail(NSRGS_ERR_INVALID_ARG, "bad nd / ld");
+  if (out->ld != ld) return fail(NSRGS_ERR_INVALID_ARG, "out->ld must equal ld");
+  if (out->fmt == NSRGS_A_BF16_SPLIT && !out->data_lo) return fail(NSRGS_ERR_INVALID_ARG, "data_lo is NULL");
+  if (out->fmt == NSRGS_A_FP8_E4M3 && !out->row_scale) return fail(NSRGS_ERR_INVALID_ARG, "row_scale is NULL");
+  if (out->fmt != NSRGS_A_BF16 && out->fmt != NSRGS_A_BF16_SPLIT && out->fmt != NSRGS_A_FP8_E4M3)
+    return fail(NSRGS_ERR_INVALID_ARG, "conversion target must be BF16, BF16_SPLIT or FP8_E4M3");
+  NSRGS_HIP(launch_convert(A32, nd, ld, *out, (hipStream_t)stream), "convert");
+  return NSRGS_OK;
+}
+
+}  // extern "C"

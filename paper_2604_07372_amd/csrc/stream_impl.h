@@ -1,0 +1,488 @@
+// The streaming kernel of NS-RGS: one pass over A per iteration.
+//
+// Mode 0 (sync_step, Algorithm 2 of the paper, Sec. 2.2): for a panel of
+// R = B d rows (B whole blocks) a workgroup forms
+//     C_i = sum_{j != i} A_ij X_j                   (rows of the panel)
+// with the diagonal blocks excluded inside the stream, then, on chip,
+//     G_i = (n - 1) X_i - C_i
+//     F_i = X_i - mu (G_i - X_i G_i^T X_i) / 2
+//     X_i <- Newton-Schulz^{Ts}(F_i),  S <- 1.5 S - 0.5 S (S^T S)   (Alg. 1)
+// and writes X^{t+1} plus per-panel monitors.  C, G and F never reach memory.
+//
+// Mode 1 (spectral initialization): the same stream computes W = A Y for the
+// panel (no exclusion) and per-panel partial Grams Y^T W and W^T W; the last
+// workgroup reduces them in FP64 and factors W^T W = R^T R (Cholesky-QR).
+//
+// Data layout: A row-major (16-byte vectors along a row: lane l of a wave reads
+// columns [c, c + V) of every panel row, consecutive lanes consecutive vectors,
+// so a wave's loads of one row are 1 KB contiguous).  X is nd x d row-major;
+// a lane reads the V x d slice of X matching its columns once per column group
+// and reuses it for all R rows of the panel.  The W waves of a workgroup split
+// the column groups round-robin; partial sums meet in LDS.
+#pragma once
+#include "device.h"
+#include "kernels.h"
+
+namespace nsrgs {
+
+template <typename T>
+__device__ __forceinline__ T fmaT(T a, T b, T c) {
+  if constexpr (sizeof(T) == 8) return __builtin_fma(a, b, c);
+  else return __builtin_fmaf(a, b, c);
+}
+
+template <int FMT>
+constexpr int elem_bytes() {
+  return FMT == NSRGS_A_F64 ? 8 : FMT == NSRGS_A_F32 ? 4
+       : (FMT == NSRGS_A_BF16 || FMT == NSRGS_A_BF16_SPLIT) ? 2 : 1;
+}
+
+// Accumulate one column vector [c, c + V) of every panel row.
+// MASK: apply the matrix tail (columns >= nd) and, in mode 0, the exclusion of
+// each row's own diagonal block.
+template <int FMT, int D, int R, bool MASK, bool EXCL>
+__device__ __forceinline__ void accum(typename Fmt<FMT>::acc_t (&acc)[R][D],
+                                      const char *__restrict__ Ab,
+                                      const char *__restrict__ Alo,
+                                      const int64_t (&rowoff)[R],
+                                      const typename Fmt<FMT>::acc_t *__restrict__ X,
+                                      int c, int nd, int row0) {
+  using T = typename Fmt<FMT>::acc_t;
+  constexpr int V = Fmt<FMT>::V;
+  constexpr int EB = elem_bytes<FMT>();
+  T xv[V * D];
+  if constexpr (!MASK) {
+    constexpr int NQ = V * D * (int)sizeof(T) / 16;
+    const uint4 *xp = reinterpret_cast<const uint4 *>(X + (int64_t)c * D);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      uint4 u = xp[q];
+      if constexpr (sizeof(T) == 4) {
+        xv[4 * q + 0] = __uint_as_float(u.x);
+        xv[4 * q + 1] = __uint_as_float(u.y);
+        xv[4 * q + 2] = __uint_as_float(u.z);
+        xv[4 * q + 3] = __uint_as_float(u.w);
+      } else {
+        xv[2 * q + 0] = __hiloint2double((int)u.y, (int)u.x);
+        xv[2 * q + 1] = __hiloint2double((int)u.w, (int)u.z);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+        xv[v * D + k] = (c + v < nd) ? X[(int64_t)(c + v) * D + k] : T(0);
+  }
+  uint4 raw[R];
+  uint4 rawlo[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    raw[r] = ld16_stream(Ab + rowoff[r] + (int64_t)c * EB);
+    if constexpr (FMT == NSRGS_A_BF16_SPLIT)
+      rawlo[r] = ld16_stream(Alo + rowoff[r] + (int64_t)c * EB);
+    else
+      rawlo[r] = raw[r];
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    T a[V];
+    expand<FMT>(raw[r], rawlo[r], a);
+    if constexpr (MASK) {
+      const int blk = (row0 + r) / D;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        bool ok = (c + v) < nd;
+        if constexpr (EXCL) ok = ok && ((c + v) / D != blk);
+        a[v] = ok ? a[v] : T(0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int k = 0; k < D; ++k) acc[r][k] = fmaT(a[v], xv[v * D + k], acc[r][k]);
+  }
+}
+
+// Unmasked accumulation of U column vectors per row: vector u of this lane
+// starts at column c0 + u * 64 V, so each load instruction of the wave reads
+// 1 KB of one row contiguously.  All R x U loads are issued before the
+// first FMA.
+template <int FMT, int D, int R, int U>
+__device__ __forceinline__ void accum_full(typename Fmt<FMT>::acc_t (&acc)[R][D],
+                                           const char *__restrict__ Ab,
+                                           const char *__restrict__ Alo,
+                                           const int64_t (&rowoff)[R],
+                                           const typename Fmt<FMT>::acc_t *__restrict__ X,
+                                           int c0) {
+  using T = typename Fmt<FMT>::acc_t;
+  constexpr int V = Fmt<FMT>::V;
+  constexpr int EB = elem_bytes<FMT>();
+  constexpr int NQ = V * D * (int)sizeof(T) / 16;
+  uint4 xr[U][NQ];
+  uint4 raw[U][R];
+  uint4 rawlo[U][R];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int c = c0 + u * kWave * V;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      raw[u][r] = ld16_stream(Ab + rowoff[r] + (int64_t)c * EB);
+      if constexpr (FMT == NSRGS_A_BF16_SPLIT)
+        rawlo[u][r] = ld16_stream(Alo + rowoff[r] + (int64_t)c * EB);
+      else
+        rawlo[u][r] = raw[u][r];
+    }
+    const uint4 *xp = reinterpret_cast<const uint4 *>(X + (int64_t)c * D);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) xr[u][q] = xp[q];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    T xv[V * D];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      if constexpr (sizeof(T) == 4) {
+        xv[4 * q + 0] = __uint_as_float(xr[u][q].x);
+        xv[4 * q + 1] = __uint_as_float(xr[u][q].y);
+        xv[4 * q + 2] = __uint_as_float(xr[u][q].z);
+        xv[4 * q + 3] = __uint_as_float(xr[u][q].w);
+      } else {
+        xv[2 * q + 0] = __hiloint2double((int)xr[u][q].y, (int)xr[u][q].x);
+        xv[2 * q + 1] = __hiloint2double((int)xr[u][q].w, (int)xr[u][q].z);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      T a[V];
+      expand<FMT>(raw[u][r], rawlo[u][r], a);
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[r][k] = fmaT(a[v], xv[v * D + k], acc[r][k]);
+    }
+  }
+}
+
+template <int FMT, int D, int B, int U, int MODE>
+__global__ void __launch_bounds__(kWave * kMaxWaves)
+stream_kernel(StreamArgs args) {
+  using T = typename Fmt<FMT>::acc_t;
+  constexpr int V = Fmt<FMT>::V;
+  constexpr int R = B * D;
+  constexpr int NE = R * D;              // panel entries of C (= B blocks of d x d)
+  constexpr int GROUP = kWave * V * U;   // columns per wave per loop iteration
+  constexpr int EB = elem_bytes<FMT>();
+  constexpr bool EXCL = (MODE == 0);
+
+  __shared__ T s_red[kMaxWaves][NE];
+  __shared__ T sX[NE], sC[NE], sG[NE], sT[NE], sF[NE], sM[NE];
+  __shared__ double s_scr[kMaxWaves];
+  __shared__ int s_last;
+
+  DevCtl *ctl = args.ctl;
+  if (args.stop_flag) {
+    if (__atomic_load_n(args.stop_flag, __ATOMIC_RELAXED)) return;   // uniform
+  }
+
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
+  const int nw = blockDim.x / kWave;
+  const int nd = args.nd;
+  const int panel = blockIdx.x;
+  const int row0 = panel * R;
+  const T *__restrict__ X = static_cast<const T *>(args.X_in);
+  const char *__restrict__ Ab = static_cast<const char *>(args.A);
+  const char *__restrict__ Alo = static_cast<const char *>(args.A_lo);
+
+  int64_t rowoff[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int row = (row0 + r < nd) ? row0 + r : nd - 1;   // clamp: tail rows unused
+    rowoff[r] = (int64_t)row * args.ld * EB;
+  }
+
+  T acc[R][D];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc[r][k] = T(0);
+
+  // Column groups go round-robin to the waves.  The groups that hold this
+  // panel's diagonal blocks (mode 0) and the ragged last group are taken out
+  // of the main loop (a wave-uniform test) and done with masks afterwards.
+  const int ngroups = (nd + GROUP - 1) / GROUP;
+  const int nfull = nd / GROUP;
+  int gd0 = -1, gd1 = -1;
+  if constexpr (EXCL) {
+    gd0 = row0 / GROUP;
+    gd1 = min(row0 + R - 1, nd - 1) / GROUP;
+  }
+  for (int g = wave; g < nfull; g += nw) {
+    if (g == gd0 || g == gd1) continue;
+    accum_full<FMT, D, R, U>(acc, Ab, Alo, rowoff, X, g * GROUP + lane * V);
+  }
+  const int gt = nfull < ngroups ? nfull : -1;
+  for (int q = 0; q < 3; ++q) {
+    const int g = q == 0 ? gd0 : q == 1 ? gd1 : gt;
+    if (g < 0 || g % nw != wave) continue;
+    if (q == 1 && g == gd0) continue;
+    if (q == 2 && (g == gd0 || g == gd1)) continue;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = g * GROUP + u * kWave * V + lane * V;
+      if (c < nd) accum<FMT, D, R, true, EXCL>(acc, Ab, Alo, rowoff, X, c, nd, row0);
+    }
+  }
+
+  // ---- reduce the panel sums over lanes, then over waves -----------------
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      T v = wave_sum(acc[r][k]);
+      if (lane == 0) s_red[wave][r * D + k] = v;
+    }
+  __syncthreads();
+  for (int e = tid; e < NE; e += blockDim.x) {
+    T s = s_red[0][e];
+    for (int w = 1; w < nw; ++w) s += s_red[w][e];
+    const int row = row0 + e / D;
+    if constexpr (FMT == NSRGS_A_FP8_E4M3) s *= (row < nd) ? args.scale[row] : 0.0f;
+    sC[e] = s;
+    sX[e] = (row < nd) ? X[(int64_t)row * D + (e % D)] : T(0);
+  }
+  __syncthreads();
+
+  if constexpr (MODE == 0) {
+    // ---- fused per-block Riemannian step and Newton-Schulz retraction ----
+    const T nm1 = T(args.n - 1);
+    const T mu = T(args.mu);
+    for (int e = tid; e < NE; e += blockDim.x) sG[e] = nm1 * sX[e] - sC[e];
+    __syncthreads();
+    // sT = G^T X  (per block)
+    for (int e = tid; e < NE; e += blockDim.x) {
+      const int bb = (e / (D * D)) * D * D, a = (e / D) % D, k = e % D;
+      T s = 0;
+#pragma unroll
+      for (int m = 0; m < D; ++m) s = fmaT(sG[bb + m * D + a], sX[bb + m * D + k], s);
+      sT[e] = s;
+    }
+    __syncthreads();
+    // F = X - mu (G - X (G^T X)) / 2
+    for (int e = tid; e < NE; e += blockDim.x) {
+      const int bb = (e / (D * D)) * D * D, a = (e / D) % D, k = e % D;
+      T s = 0;
+#pragma unroll
+      for (int m = 0; m < D; ++m) s = fmaT(sX[bb + a * D + m], sT[bb + m * D + k], s);
+      const T P = T(0.5) * (sG[e] - s);
+      sF[e] = sX[e] - mu * P;
+    }
+    __syncthreads();
+    T *cur = sF;
+    T *nxt = sT;
+    const int steps = args.ns_steps;
+    for (int st = 0; st < (steps > 0 ? steps : 1); ++st) {
+      // M = S^T S
+      for (int e = tid; e < NE; e += blockDim.x) {
+        const int bb = (e / (D * D)) * D * D, a = (e / D) % D, k = e % D;
+        T s = 0;
+#pragma unroll
+        for (int m = 0; m < D; ++m) s = fmaT(cur[bb + m * D + a], cur[bb + m * D + k], s);
+        sM[e] = s;
+        if (st == 0) {
+          const T dlt = (a == k ? T(1) : T(0)) - s;
+          sC[e] = dlt * dlt;                       // defect terms of F^T F
+        }
+      }
+      __syncthreads();
+      if (st < steps) {
+        // S <- 1.5 S - 0.5 S M
+        for (int e = tid; e < NE; e += blockDim.x) {
+          const int bb = (e / (D * D)) * D * D, a = (e / D) % D, k = e % D;
+          T s = 0;
+#pragma unroll
+          for (int m = 0; m < D; ++m) s = fmaT(cur[bb + a * D + m], sM[bb + m * D + k], s);
+          nxt[e] = T(1.5) * cur[e] - T(0.5) * s;
+        }
+        __syncthreads();
+        T *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+      }
+    }
+    // ---- write X^{t+1} and the panel monitors ------------------------------
+    T *__restrict__ Xo = static_cast<T *>(args.X_out);
+    double dx2 = 0.0, x2 = 0.0, dmax = 0.0;
+    int nonfin = 0;
+    for (int e = tid; e < NE; e += blockDim.x) {
+      const int row = row0 + e / D;
+      if (row < nd) {
+        const T v = cur[e];
+        Xo[(int64_t)row * D + (e % D)] = v;
+        const double dv = (double)v - (double)sX[e];
+        dx2 += dv * dv;
+        x2 += (double)sX[e] * (double)sX[e];
+        nonfin |= !isfinite(v);
+      }
+    }
+    for (int b = tid; b < B; b += blockDim.x) {
+      if (row0 + b * D < nd) {
+        double s = 0.0;
+        for (int j = 0; j < D * D; ++j) s += (double)sC[b * D * D + j];
+        const double df = sqrt(s);
+        dmax = df > dmax ? df : dmax;
+        nonfin |= !isfinite(df);
+      }
+    }
+    dx2 = block_sum(dx2, s_scr);
+    x2 = block_sum(x2, s_scr);
+    dmax = block_max(dmax, s_scr);
+    const double nf = block_max((double)nonfin, s_scr);
+    PanelStat *part = static_cast<PanelStat *>(args.partials);
+    if (tid == 0) part[panel] = PanelStat{dx2, x2, dmax, nf};
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_last = (atomicAdd(&ctl->arrive, 1u) == (unsigned)args.num_panels - 1u);
+    __syncthreads();
+    if (s_last) {
+      __threadfence();
+      double a = 0.0, bsum = 0.0, m = 0.0, f = 0.0;
+      for (int p = tid; p < args.num_panels; p += blockDim.x) {
+        const PanelStat q = part[p];
+        a += q.dx2;
+        bsum += q.x2;
+        m = q.dmax > m ? q.dmax : m;
+        f = q.nonfinite > f ? q.nonfinite : f;
+      }
+      a = block_sum(a, s_scr);
+      bsum = block_sum(bsum, s_scr);
+      m = block_max(m, s_scr);
+      f = block_max(f, s_scr);
+      if (tid == 0) {
+        const double rel = bsum > 0.0 ? sqrt(a / bsum) : 0.0;
+        ctl->sum_dx2 = a;
+        ctl->sum_x2 = bsum;
+        ctl->rel_change = rel;
+        ctl->max_defect = m;
+        ctl->nonfinite = f != 0.0;
+        ctl->iters = args.iter + 1;
+        if (f != 0.0 || !isfinite(rel)) {
+          ctl->nonfinite = 1;
+          ctl->done = 1;
+        } else if (args.tol > 0.0 && rel <= args.tol) {
+          ctl->converged = 1;
+          ctl->done = 1;
+        }
+        ctl->arrive = 0u;
+      }
+    }
+  } else {
+    // ---- mode 1: W = A Y for the panel rows; partial Grams Y^T W, W^T W ----
+    T *__restrict__ Wo = static_cast<T *>(args.X_out);
+    for (int e = tid; e < NE; e += blockDim.x) {
+      const int row = row0 + e / D;
+      if (row < nd) Wo[(int64_t)row * D + (e % D)] = sC[e];
+    }
+    T *part = static_cast<T *>(args.partials) + (int64_t)panel * 2 * D * D;
+    for (int e = tid; e < D * D; e += blockDim.x) {
+      const int a = e / D, k = e % D;
+      T g1 = 0, g2 = 0;
+      for (int r = 0; r < R; ++r) {
+        if (row0 + r < nd) {
+          g1 = fmaT(sX[r * D + a], sC[r * D + k], g1);
+          g2 = fmaT(sC[r * D + a], sC[r * D + k], g2);
+        }
+      }
+      part[e] = g1;
+      part[D * D + e] = g2;
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_last = (atomicAdd(&ctl->arrive2, 1u) == (unsigned)args.num_panels - 1u);
+    __syncthreads();
+    if (s_last) {
+      __threadfence();
+      __shared__ double G1[kMaxD * kMaxD], G2[kMaxD * kMaxD], Rm[kMaxD * kMaxD];
+      const T *all = static_cast<const T *>(args.partials);
+      for (int e = tid; e < 2 * D * D; e += blockDim.x) {
+        double s = 0.0;
+        for (int p = 0; p < args.num_panels; ++p) s += (double)all[(int64_t)p * 2 * D * D + e];
+        if (e < D * D) G1[e] = s; else G2[e - D * D] = s;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        // Rayleigh quotient T = Y^T A Y (symmetrised) and Cholesky W^T W = R^T R.
+        int bad = 0;
+        for (int a = 0; a < D; ++a)
+          for (int k = 0; k < D; ++k) ctl->T[a * D + k] = 0.5 * (G1[a * D + k] + G1[k * D + a]);
+        for (int j = 0; j < D * D; ++j) Rm[j] = 0.0;
+        for (int j = 0; j < D; ++j) {
+          double s = G2[j * D + j];
+          for (int q = 0; q < j; ++q) s -= Rm[q * D + j] * Rm[q * D + j];
+          if (!(s > 0.0) || !isfinite(s)) { bad = 1; s = 1.0; }
+          const double rjj = sqrt(s);
+          Rm[j * D + j] = rjj;
+          for (int k = j + 1; k < D; ++k) {
+            double t = G2[j * D + k];
+            for (int q = 0; q < j; ++q) t -= Rm[q * D + j] * Rm[q * D + k];
+            Rm[j * D + k] = t / rjj;
+          }
+        }
+        // Rinv = R^{-1} (upper triangular), column by column.
+        for (int j = 0; j < D * D; ++j) ctl->Rinv[j] = 0.0;
+        for (int k = 0; k < D; ++k) {
+          ctl->Rinv[k * D + k] = 1.0 / Rm[k * D + k];
+          for (int i = k - 1; i >= 0; --i) {
+            double s = 0.0;
+            for (int q = i + 1; q <= k; ++q) s += Rm[i * D + q] * ctl->Rinv[q * D + k];
+            ctl->Rinv[i * D + k] = -s / Rm[i * D + i];
+          }
+        }
+        if (bad) ctl->init_bad = 1;
+        ctl->arrive2 = 0u;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Instantiation table: (d, B) pairs, R = B d rows per panel.  Mode 1 (the
+// spectral-initialization product) uses only the first entry of each d.
+// ---------------------------------------------------------------------------
+#define NSRGS_BOPTS(X)                                                                    \
+  X(1, 8, 1) X(1, 16, 1) X(1, 8, 2) X(2, 4, 1) X(2, 8, 1) X(2, 4, 2)                       \
+  X(3, 4, 1) X(3, 2, 1) X(3, 8, 1) X(3, 2, 2) X(3, 4, 2) X(3, 1, 2) X(3, 1, 4) X(3, 2, 4) \
+  X(4, 2, 1) X(4, 4, 1) X(4, 2, 2) X(4, 1, 2)                                              \
+  X(5, 1, 1) X(5, 2, 1) X(6, 1, 1) X(6, 2, 1) X(7, 1, 1) X(7, 2, 1) X(8, 1, 1) X(8, 2, 1) \
+  X(9, 1, 1) X(10, 1, 1) X(11, 1, 1) X(12, 1, 1) X(13, 1, 1) X(14, 1, 1) X(15, 1, 1)       \
+  X(16, 1, 1)
+
+#define NSRGS_BOPTS_INIT(X)                                                   \
+  X(1, 8, 1) X(2, 4, 1) X(3, 4, 1) X(4, 2, 1) X(5, 1, 1) X(6, 1, 1) X(7, 1, 1) \
+  X(8, 1, 1) X(9, 1, 1) X(10, 1, 1) X(11, 1, 1) X(12, 1, 1) X(13, 1, 1)        \
+  X(14, 1, 1) X(15, 1, 1) X(16, 1, 1)
+
+template <int MODE, int FMT, int D, int B, int U>
+hipError_t launch_one(const StreamConfig &cfg, const StreamArgs &args, hipStream_t s) {
+  const dim3 grid(args.num_panels), block(kWave * cfg.waves);
+  hipLaunchKernelGGL((stream_kernel<FMT, D, B, U, MODE>), grid, block, 0, s, args);
+  return hipGetLastError();
+}
+
+template <int MODE, int FMT>
+hipError_t launch_fmt_impl(const StreamConfig &cfg, const StreamArgs &args, hipStream_t s) {
+#define NSRGS_CASE(DD, BB, UU)                                                        \
+  if (args.d == DD && cfg.blocks_per_panel == BB && cfg.unroll == UU)                   \
+    return launch_one<MODE, FMT, DD, BB, UU>(cfg, args, s);
+  if constexpr (MODE == 0) {
+    NSRGS_BOPTS(NSRGS_CASE)
+  } else {
+    NSRGS_BOPTS_INIT(NSRGS_CASE)
+  }
+#undef NSRGS_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace nsrgs

@@ -1,0 +1,111 @@
+"""The C-ABI library loads, exports every declared symbol, and rejects bad
+arguments on the host before touching a device (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2604_07372_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w \*]*?\b(\w+)\s*\(", text, flags=re.M):
+            name = m.group(1)
+            if name not in ("if", "while", "for", "sizeof", "defined"):
+                names.append(name)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert len(names) >= 10
+    L = ctypes.CDLL(P.LIB_PATH)
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_version_and_status_strings():
+    L = P.lib()
+    assert L.nsrgs_version() == 100
+    for st in range(7):
+        assert L.nsrgs_status_string(st)
+
+
+def _mat(fmt=P.F32, ld=304, data=16):
+    return P._Matrix(fmt, data, None, None, ld)
+
+
+@pytest.mark.parametrize("n,d,msg", [(1, 3, "n must be"), (0, 3, "n must be"), (10, 0, "d must be"),
+                                     (10, 17, "d must be")])
+def test_step_rejects_bad_sizes(n, d, msg):
+    L = P.lib()
+    m = _mat()
+    st = L.sync_step(ctypes.byref(m), n, d, 0.0, 3, 16, 4096, 256, 1 << 30, None)
+    assert st == 1
+    assert msg in L.nsrgs_last_error().decode()
+
+
+def test_step_rejects_bad_matrix_and_buffers():
+    L = P.lib()
+    n, d = 100, 3
+    ws_bytes = L.sync_workspace_bytes(n, d, P.F32)
+    cases = [
+        (_mat(ld=290), "ld"),                # < nd and not a multiple of 16
+        (_mat(ld=308), "multiple of 16"),
+        (_mat(data=8), "aligned"),
+        (P._Matrix(7, 16, None, None, 304), "format"),
+        (P._Matrix(P.BF16_SPLIT, 16, None, None, 304), "data_lo"),
+        (P._Matrix(P.FP8_E4M3, 16, None, None, 304), "row_scale"),
+    ]
+    for m, msg in cases:
+        st = L.sync_step(ctypes.byref(m), n, d, 0.0, 3, 4096, 1 << 20, 256, ws_bytes, None)
+        assert st == 1, msg
+        assert msg in L.nsrgs_last_error().decode()
+    m = _mat()
+    # aliasing input/output
+    st = L.sync_step(ctypes.byref(m), n, d, 0.0, 3, 4096, 4096 + 64, 256, ws_bytes, None)
+    assert st == 1 and "overlap" in L.nsrgs_last_error().decode()
+    # workspace too small
+    st = L.sync_step(ctypes.byref(m), n, d, 0.0, 3, 4096, 1 << 20, 256, ws_bytes - 1, None)
+    assert st == 3
+    # ns_steps out of range, non-finite mu
+    assert L.sync_step(ctypes.byref(m), n, d, 0.0, 65, 4096, 1 << 20, 256, ws_bytes, None) == 1
+    assert L.sync_step(ctypes.byref(m), n, d, float("nan"), 3, 4096, 1 << 20, 256, ws_bytes, None) == 1
+
+
+def test_workspace_size_scales_and_rejects():
+    L = P.lib()
+    assert L.sync_workspace_bytes(1, 3, P.F32) == 0
+    assert L.sync_workspace_bytes(10, 17, P.F32) == 0
+    assert L.sync_workspace_bytes(10, 3, 9) == 0
+    small = L.sync_workspace_bytes(100, 3, P.F32)
+    big = L.sync_workspace_bytes(20000, 3, P.F32)
+    f64 = L.sync_workspace_bytes(100, 3, P.F64)
+    assert 0 < small < big and f64 > small
+    # the workspace is O(n d^2): no nd x nd scratch
+    assert big < 64 * 20000 * 9 * 4
+
+
+def test_solve_and_init_reject_before_device_use():
+    L = P.lib()
+    m = _mat()
+    info = P.Info()
+    assert L.sync_solve(ctypes.byref(m), 1, 3, 0.0, 3, 10, 0.0, 4096, 256, 1 << 30, None, None,
+                        ctypes.byref(info)) == 1
+    assert L.sync_solve(ctypes.byref(m), 100, 3, 0.0, 3, -1, 0.0, 4096, 256, 1 << 30, None, None,
+                        ctypes.byref(info)) == 1
+    assert L.sync_init_spectral(ctypes.byref(m), 100, 3, None, 0, 0.0, 256, 1 << 30, None,
+                                ctypes.byref(info)) == 1
+    assert L.nsrgs_generate_measurement(None, 100, 3, 1.0, 0, 0, 1.0, P.F32, 16, 304, None) == 1
+    assert L.nsrgs_generate_measurement(16, 100, 3, 1.0, 0, 0, 1.0, P.BF16, 16, 304, None) == 1
+    out = P._Matrix(P.F32, 16, None, None, 304)
+    assert L.nsrgs_convert(16, 300, 304, ctypes.byref(out), None) == 1

@@ -1,0 +1,338 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2604_07372_amd as P
+import synth
+from oracle import nsrgs as O
+from oracle import quantize as Q
+
+from gpu_common import (FMT_NAME, device_matrix, host, oracle_matrix, require_gpu,
+                        step_tolerance, to_dev, xdtype)
+
+pytestmark = pytest.mark.gpu
+
+ALL_FMTS = [P.F64, P.F32, P.BF16, P.BF16_SPLIT, P.FP8_E4M3]
+SHAPES = [(2, 1), (2, 3), (5, 2), (37, 3), (341, 3), (700, 3), (100, 4), (61, 5),
+          (33, 10), (20, 16), (130, 1), (47, 7)]
+
+
+def _problem(n, d, c=0.3, seed=0, eps=0.05):
+    Z = synth.haar_blocks(n, d, seed)
+    A64 = synth.measurement_matrix(Z, synth.sigma_for(c, n, d), seed + 1)
+    X = synth.perturbed_start(Z, eps, seed + 2)
+    return Z, A64, X
+
+
+@pytest.mark.parametrize("fmt", ALL_FMTS, ids=lambda f: FMT_NAME[f])
+@pytest.mark.parametrize("n,d", SHAPES)
+def test_step_parity(n, d, fmt):
+    require_gpu()
+    print(f"step parity n={n} d={d} fmt={FMT_NAME[fmt]}", flush=True)
+    Z, A64, X = _problem(n, d, seed=1000 * n + d)
+    Ad = device_matrix(A64, fmt)
+    As = oracle_matrix(A64, fmt)
+    Xin = to_dev(X, xdtype(fmt))
+    Xh = host(Xin)
+    ws = P.workspace(n, d, fmt)
+    Xout = torch.empty_like(Xin)
+    P.step(Ad, n, d, Xin, Xout, ws, mu=0.0, ns_steps=3)
+    torch.cuda.synchronize()
+    ref = O.rgs_step(As, Xh, d, mu=1.0 / n, Ts=3)
+    err = np.abs(host(Xout) - ref.X).max()
+    tol = step_tolerance(As, Xh, n, fmt)
+    assert err <= tol, (err, tol)
+    info = P.read_info(ws)
+    assert abs(info["rel_change"] - ref.rel_change) <= 1e-3 * ref.rel_change + 1e-6
+    assert abs(info["max_orth_defect"] - ref.max_orth_defect) <= 1e-3 * ref.max_orth_defect + 1e-5
+    assert info["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("Ts", [0, 1, 5])
+@pytest.mark.parametrize("mu", [0.0, 0.5, 1.7])
+def test_step_parity_mu_and_ns_steps(Ts, mu):
+    require_gpu()
+    # eps keeps the singular values of F inside (0, sqrt(3)), where Algorithm 1
+    # converges; outside it the iteration diverges and only relative errors
+    # are meaningful (see the defect-monitor test).
+    n, d = 90, 3
+    Z, A64, X = _problem(n, d, seed=7, eps=0.05)
+    for fmt in (P.F64, P.F32):
+        Ad = device_matrix(A64, fmt)
+        As = oracle_matrix(A64, fmt)
+        Xin = to_dev(X, xdtype(fmt))
+        ws = P.workspace(n, d, fmt)
+        Xout = torch.empty_like(Xin)
+        mu_eff = mu / n if mu > 0 else 0.0
+        P.step(Ad, n, d, Xin, Xout, ws, mu=mu_eff, ns_steps=Ts)
+        torch.cuda.synchronize()
+        ref = O.rgs_step(As, host(Xin), d, mu=(mu_eff or 1.0 / n), Ts=Ts)
+        assert np.abs(host(Xout) - ref.X).max() <= step_tolerance(As, host(Xin), n, fmt)
+
+
+@pytest.mark.parametrize("fmt", [P.F32, P.BF16, P.FP8_E4M3], ids=lambda f: FMT_NAME[f])
+@pytest.mark.parametrize("BU", [(4, 1), (2, 1), (8, 1), (2, 2), (4, 2), (1, 2), (1, 4), (2, 4)])
+@pytest.mark.parametrize("W", [1, 2, 4, 8])
+def test_step_launch_shapes_agree(BU, W, fmt, monkeypatch):
+    """Every (blocks per panel, vectors per row, waves per workgroup) variant
+    the launcher can pick gives the oracle's result (ragged panel tail:
+    n = 1365 is not a multiple of B; nd = 4095 leaves a partial column group
+    for every vector width and unroll, and every variant has full groups)."""
+    require_gpu()
+    B, U = BU
+    monkeypatch.setenv("NSRGS_STEP_B", str(B))
+    monkeypatch.setenv("NSRGS_STEP_U", str(U))
+    monkeypatch.setenv("NSRGS_STEP_W", str(W))
+    n, d = 1365, 3
+    Z, A64, X = _problem(n, d, seed=3)
+    Ad = device_matrix(A64, fmt)
+    As = oracle_matrix(A64, fmt)
+    Xin = to_dev(X, xdtype(fmt))
+    ws = P.workspace(n, d, fmt)
+    Xout = torch.empty_like(Xin)
+    P.step(Ad, n, d, Xin, Xout, ws)
+    torch.cuda.synchronize()
+    ref = O.rgs_step(As, host(Xin), d, Ts=3)
+    assert np.abs(host(Xout) - ref.X).max() <= step_tolerance(As, host(Xin), n, fmt)
+
+
+def test_padding_columns_never_read_as_data():
+    """NaN in the padding columns (ld > nd) must not reach the result."""
+    require_gpu()
+    n, d = 37, 3
+    Z, A64, X = _problem(n, d, seed=11)
+    Ad = device_matrix(A64, P.F32)
+    Ad.data[:, n * d:] = float("nan")
+    Xin = to_dev(X, torch.float32)
+    ws = P.workspace(n, d, P.F32)
+    Xout = torch.empty_like(Xin)
+    P.step(Ad, n, d, Xin, Xout, ws)
+    torch.cuda.synchronize()
+    ref = O.rgs_step(oracle_matrix(A64, P.F32), host(Xin), d, Ts=3)
+    assert np.isfinite(host(Xout)).all()
+    assert np.abs(host(Xout) - ref.X).max() <= step_tolerance(A64, host(Xin), n, P.F32)
+
+
+def test_step_is_deterministic_and_needs_no_diag_blocks():
+    """Bitwise repeatable; the diagonal blocks of A do not influence a step."""
+    require_gpu()
+    n, d = 200, 3
+    Z, A64, X = _problem(n, d, seed=5)
+    Ad = device_matrix(A64, P.F32)
+    Xin = to_dev(X, torch.float32)
+    ws = P.workspace(n, d, P.F32)
+    out1, out2, out3 = (torch.empty_like(Xin) for _ in range(3))
+    P.step(Ad, n, d, Xin, out1, ws)
+    P.step(Ad, n, d, Xin, out2, ws)
+    for i in range(n):
+        Ad.data[i * d:(i + 1) * d, i * d:(i + 1) * d] = 1e30
+    P.step(Ad, n, d, Xin, out3, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(out1, out2)
+    assert torch.equal(out1, out3)
+
+
+@pytest.mark.parametrize("fmt", [P.BF16, P.BF16_SPLIT, P.FP8_E4M3], ids=lambda f: FMT_NAME[f])
+def test_conversion_bit_exact(fmt):
+    require_gpu()
+    rng = np.random.default_rng(4)
+    nd, ld = 300, 304
+    a = rng.standard_normal((nd, nd)) * np.exp(rng.uniform(-12, 12, (nd, 1)))
+    a[:, :5] *= np.exp(rng.uniform(-30, 30, (nd, 5)))
+    # exact bf16 ties and e4m3 ties
+    a[0, 10:14] = [1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -(1.0 + 2.0 ** -8), 0.0]
+    a[1, :8] = np.array([448.0, 1.0 + 2 ** -4, 1.0 + 3 * 2 ** -4, 2.0 ** -9 * 1.5, 2.0 ** -9 * 2.5,
+                         -2.0 ** -10, 0.0, 300.0])
+    a32 = a.astype(np.float32)
+    dev = P.upload(a32.astype(np.float64), P.F32)
+    assert np.array_equal(host(dev.data)[:, :nd].astype(np.float32), a32)
+    out = P.convert(dev.data, fmt)
+    torch.cuda.synchronize()
+    if fmt in (P.BF16, P.BF16_SPLIT):
+        got_hi = out.data.cpu().numpy().view(np.uint16)[:, :nd]
+        want_hi, want_lo = Q.bf16_split(a32)
+        assert np.array_equal(got_hi, want_hi)
+        if fmt == P.BF16_SPLIT:
+            assert np.array_equal(out.data_lo.cpu().numpy().view(np.uint16)[:, :nd], want_lo)
+    else:
+        codes, scale = Q.fp8_rowscaled(a32)
+        assert np.array_equal(out.row_scale.cpu().numpy(), scale)
+        assert np.array_equal(out.data.cpu().numpy()[:, :nd], codes)
+
+
+def test_fp8_decode_covers_every_code():
+    """The streaming kernel's FP8 expansion matches the OCP e4m3 table for every
+    finite code: a step with X = block-identity-like input reads codes directly."""
+    require_gpu()
+    n, d = 64, 4
+    nd = n * d
+    rng = np.random.default_rng(9)
+    finite = np.array([c for c in range(256) if c not in (0x7F, 0xFF)], dtype=np.uint8)
+    codes = rng.choice(finite, size=(nd, nd)).astype(np.uint8)
+    codes[0, :len(finite)] = finite
+    scale = rng.uniform(0.5, 2.0, nd).astype(np.float32)
+    ld = P.padded_ld(nd)
+    data = torch.zeros((nd, ld), dtype=torch.uint8, device="cuda")
+    data[:, :nd] = torch.from_numpy(codes).cuda()
+    Ad = P.StoredMatrix(P.FP8_E4M3, data, nd, row_scale=torch.from_numpy(scale).cuda())
+    As = scale.astype(np.float64)[:, None] * Q.e4m3_decode(codes)
+    Z = synth.haar_blocks(n, d, 1)
+    X = synth.perturbed_start(Z, 0.1, 2)
+    Xin = to_dev(X, torch.float32)
+    ws = P.workspace(n, d, P.FP8_E4M3)
+    Xout = torch.empty_like(Xin)
+    P.step(Ad, n, d, Xin, Xout, ws, mu=1e-4, ns_steps=0)
+    torch.cuda.synchronize()
+    ref = O.rgs_step(As, host(Xin), d, mu=1e-4, Ts=0)
+    assert np.abs(host(Xout) - ref.X).max() <= step_tolerance(As, host(Xin), n, P.FP8_E4M3) * 4
+
+
+@pytest.mark.parametrize("fmt", [P.F64, P.F32])
+@pytest.mark.parametrize("zero_diag,p", [(False, 1.0), (True, 1.0), (False, 0.5)])
+def test_generator_matches_host_twin(fmt, zero_diag, p):
+    require_gpu()
+    n, d, sigma, seed = 257, 3, 2.5, 77
+    Z = synth.haar_blocks(n, d, 5)
+    want = synth.measurement_matrix(Z, sigma, seed, zero_diag_blocks=zero_diag, p=p)
+    A = P.generate(to_dev(Z, torch.float64), sigma, seed, fmt=fmt, zero_diag_blocks=zero_diag, p=p)
+    torch.cuda.synchronize()
+    got = host(A)[:, :n * d]
+    if fmt == P.F64:
+        # transcendental functions and the order of the d-term sum may differ by ulps
+        assert np.abs(got - want).max() <= 1e-13 * max(1.0, np.abs(want).max())
+        assert np.array_equal(got == 0, want == 0)
+    else:
+        w32 = want.astype(np.float32)
+        g32 = got.astype(np.float32)
+        diff = g32.view(np.int32).astype(np.int64) - w32.view(np.int32).astype(np.int64)
+        assert np.abs(diff).max() <= 1
+        assert np.count_nonzero(diff) <= 4
+    assert np.array_equal(got, got.T)
+
+
+def test_solve_fp64_small_workload_end_to_end():
+    """n = 100, d = 3, sigma = 2, 100 iterations, 3 NS steps: GPU FP64 vs oracle."""
+    require_gpu()
+    n, d, sigma = 100, 3, 2.0
+    Z = synth.haar_blocks(n, d, 0)
+    A = synth.measurement_matrix(Z, sigma, 0)
+    ref = O.solve(A, d, Ts=3, T=100)
+    ref_polar = O.solve(A, d, Ts=3, T=100, retraction="polar")
+    Ad = device_matrix(A, P.F64)
+    X = torch.empty((n * d, d), dtype=torch.float64, device="cuda")
+    ws = P.workspace(n, d, P.F64)
+    info = P.solve(Ad, n, d, X, ws, ns_steps=3, max_iters=100)
+    Xg = host(X)
+    e_g, e_o = O.alignment_error(Xg, Z), O.alignment_error(ref.X, Z)
+    print("fp64 e_gpu", e_g, "e_oracle", e_o, "init res", info["init_residual"], flush=True)
+    assert abs(e_g - e_o) <= 1e-10
+    assert O.dist_F(Xg, ref.X) / math.sqrt(n) <= 1e-10
+    assert O.dist_F(Xg, ref_polar.X) / math.sqrt(n) <= 1e-10
+    assert info["iters"] == 100
+    assert info["status"] == 0
+
+
+def test_spectral_init_fp64_matches_eigh():
+    require_gpu()
+    n, d = 100, 3
+    Z = synth.haar_blocks(n, d, 0)
+    A = synth.measurement_matrix(Z, 2.0, 0)
+    Y, w, _ = O.spectral_subspace(A, d)
+    X0_ref = O.sgn_blocks(Y, d)
+    X0 = torch.empty((n * d, d), dtype=torch.float64, device="cuda")
+    ws = P.workspace(n, d, P.F64)
+    info = P.init_spectral(device_matrix(A, P.F64), n, d, X0, ws, max_iters=400, tol=1e-13)
+    assert info["converged"] == 1
+    assert O.dist_F(host(X0), X0_ref) / math.sqrt(n) <= 1e-9
+    assert np.allclose(info["ritz"][:d], w, rtol=1e-12)
+
+
+@pytest.mark.parametrize("sigma_c", [None, 0.1, 0.3])
+def test_solve_fp32_mid_workload(sigma_c):
+    """n = 2000, d = 3, sigma in {0.5, 0.1 sqrt(n/d), 0.3 sqrt(n/d)}, 200 iterations:
+    alignment error within 1e-4 relative of the FP64 oracle on the stored matrix."""
+    require_gpu()
+    n, d = 2000, 3
+    sigma = 0.5 if sigma_c is None else synth.sigma_for(sigma_c, n, d)
+    seed = {None: 1, 0.1: 2, 0.3: 3}[sigma_c]
+    Z = synth.haar_blocks(n, d, seed)
+    A = synth.measurement_matrix(Z, sigma, seed)
+    Ad = device_matrix(A, P.F32)
+    As = oracle_matrix(A, P.F32)
+    X = torch.empty((n * d, d), dtype=torch.float32, device="cuda")
+    ws = P.workspace(n, d, P.F32)
+    info = P.solve(Ad, n, d, X, ws, ns_steps=3, max_iters=200)
+    ref = O.solve(As, d, Ts=3, T=200)
+    e_g, e_o = O.alignment_error(host(X), Z), O.alignment_error(ref.X, Z)
+    print(f"sigma={sigma:.3f} e_gpu={e_g:.8f} e_oracle={e_o:.8f} dF={O.dist_F(host(X), ref.X)/math.sqrt(n):.3e}",
+          flush=True)
+    assert abs(e_g - e_o) <= 1e-4 * e_o
+    assert info["iters"] == 200
+
+
+def test_nonfinite_input_is_reported():
+    require_gpu()
+    n, d = 50, 3
+    Z, A64, X = _problem(n, d, seed=21)
+    Ad = device_matrix(A64, P.F32)
+    Ad.data[7, 40] = float("nan")
+    Xd = to_dev(X, torch.float32)
+    ws = P.workspace(n, d, P.F32)
+    info = P.solve(Ad, n, d, Xd, ws, max_iters=20, init=False, check=False)
+    assert info["status"] == 6
+    assert info["nonfinite"] == 1
+    assert info["iters"] == 1
+
+
+def test_large_step_trips_the_defect_monitor():
+    """mu = 50/n puts the NS input outside the region ||I - F^T F|| < 1 (Lemma 2.1)."""
+    require_gpu()
+    n, d = 60, 3
+    Z, A64, X = _problem(n, d, seed=22, eps=0.3)
+    Ad = device_matrix(A64, P.F64)
+    Xin = to_dev(X, torch.float64)
+    ws = P.workspace(n, d, P.F64)
+    Xout = torch.empty_like(Xin)
+    P.step(Ad, n, d, Xin, Xout, ws, mu=50.0 / n, ns_steps=3)
+    info = P.read_info(ws)
+    ref = O.rgs_step(A64, X, d, mu=50.0 / n, Ts=3)
+    assert info["max_orth_defect"] > 1.0
+    assert abs(info["max_orth_defect"] - ref.max_orth_defect) <= 1e-9 * ref.max_orth_defect
+
+
+def test_split_run_equals_straight_run():
+    """The state is (X^t, t): resuming from a saved iterate is bitwise identical."""
+    require_gpu()
+    n, d = 300, 3
+    Z = synth.haar_blocks(n, d, 8)
+    A = synth.measurement_matrix(Z, synth.sigma_for(0.2, n, d), 8)
+    Ad = device_matrix(A, P.F32)
+    ws = P.workspace(n, d, P.F32)
+    X0 = torch.empty((n * d, d), dtype=torch.float32, device="cuda")
+    P.init_spectral(Ad, n, d, X0, ws)
+    Xa = X0.clone()
+    P.solve(Ad, n, d, Xa, ws, max_iters=40, init=False)
+    Xb = X0.clone()
+    P.solve(Ad, n, d, Xb, ws, max_iters=17, init=False)
+    P.solve(Ad, n, d, Xb, ws, max_iters=23, init=False)
+    torch.cuda.synchronize()
+    assert torch.equal(Xa, Xb)
+
+
+def test_tolerance_stop_matches_oracle_iteration_count():
+    require_gpu()
+    n, d = 400, 3
+    Z = synth.haar_blocks(n, d, 12)
+    A = synth.measurement_matrix(Z, synth.sigma_for(0.2, n, d), 12)
+    Ad = device_matrix(A, P.F64)
+    ws = P.workspace(n, d, P.F64)
+    X0 = O.spectral_init(A, d)
+    X = to_dev(X0, torch.float64)
+    info = P.solve(Ad, n, d, X, ws, max_iters=300, tol=1e-6, init=False, check_every=5)
+    ref = O.solve(A, d, Ts=3, T=300, stop="rel_change", tol=1e-6, X0=X0)
+    assert info["converged"] == 1
+    assert abs(info["iters"] - ref.iters) <= 1
+    assert O.dist_F(host(X), ref.X) / math.sqrt(n) <= 1e-6
