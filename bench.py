@@ -81,6 +81,28 @@ def cpu_baseline(budget_s: float = 12.0):
                       f"{dt * 1e3:.2f} ms each, scaled by (60000/6000)^2 = {scale:.0f} to n=20000"}
 
 
+def alignment_error(X, Z) -> float:
+    """min over Q in O(d) of ||X - Z Q||_F / sqrt(n), Q from the SVD of Z^T X."""
+    import numpy as np
+    d = Z.shape[1]
+    U, _, Vt = np.linalg.svd(Z.T @ X)
+    return float(np.linalg.norm(X - Z @ (U @ Vt)) / math.sqrt(Z.shape[0] // d))
+
+
+def copy_calibration(reps: int = 3) -> int:
+    """A plain copy of known size (1 GiB read + 1 GiB written per launch), for
+    scaling the HBM byte counters of a profiler to bytes."""
+    import torch
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": nbytes, "bytes_written": nbytes, "launches": reps}}))
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,7 +111,11 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--formats", default="f32,bf16,bf16_split,fp8")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (counter calibration)")
     a = ap.parse_args(argv)
+    if a.copy_calibration:
+        return copy_calibration()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {a.gpus}); this build has no multi-GPU path.",
               file=sys.stderr)
@@ -145,7 +171,6 @@ def main(argv=None):
 
     solve = {}
     if not a.no_solve:
-        from oracle import nsrgs as O   # metric only: alignment error of the GPU result vs Z
         pred = sigma * math.sqrt(d * (d - 1) / (2.0 * n))
         for name in fmts:
             Am = stores[name]
@@ -158,7 +183,7 @@ def main(argv=None):
             t0 = time.perf_counter()
             info = P.solve(Am, n, d, X, ws, ns_steps=3, max_iters=SOLVE_ITERS, **kw)
             dt = time.perf_counter() - t0
-            e = O.alignment_error(X.cpu().double().numpy(), Z)
+            e = alignment_error(X.cpu().double().numpy(), Z)
             solve[name] = {"solve_s": dt, "align_err": e, "first_order_pred": pred,
                            "iters": info["iters"], "init_residual": info["init_residual"],
                            "refine_iters": kw.get("refine_iters", 0)}
