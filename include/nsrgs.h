@@ -166,6 +166,70 @@ int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps,
                int max_iters, double tol, void *X, void *ws, size_t ws_bytes,
                void *stream, const nsrgs_solve_opts *opts, nsrgs_info *info);
 
+/* ---- batched solves: many problems per launch -----------------------------
+ * Independent problems of uneven size (n, d) share every launch: one grouped
+ * launch runs one iteration of Algorithm 2 for all still-active problems
+ * (each workgroup one panel of B d rows of one problem, B fixed per d), and
+ * the last panel of each problem to finish updates that problem's iteration
+ * count, monitors and stop state on the device.  The host enqueues the
+ * launches back to back and looks at the state only every opts->check_every
+ * launches, so a batch of 512 problems costs max_iters launches, not
+ * 512 x max_iters.  Each problem follows exactly the arithmetic of sync_step
+ * with the same panel shape.  Every problem of a batch uses one storage
+ * format: F64, F32 or BF16, and 1 <= d <= 10 (a batch with a larger d is
+ * refused with NSRGS_ERR_UNSUPPORTED; solve such problems with sync_solve).  Problem memory (A, X) is the caller's; the
+ * workspace holds the unit table, a second iterate buffer per problem and
+ * per-panel monitors.  Waits for the stream. */
+typedef struct {
+  nsrgs_matrix A;          /* this problem's matrix                               */
+  int32_t n, d;
+  double mu;               /* <= 0: 1/n                                           */
+  void *X;                 /* device n*d x d: X^0 on entry (unless opts->init),
+                              the result on return                               */
+  int32_t iters;           /* iteration budget (<= 0: max_iters of the call)      */
+  double tol;              /* > 0: stop after the first iteration whose relative
+                              change ||X^{t+1}-X^t||_F/||X^t||_F is <= tol        */
+} nsrgs_problem;
+
+typedef struct {
+  int32_t iters, converged, nonfinite, status;
+  double rel_change, max_orth_defect;
+} nsrgs_problem_info;
+
+typedef struct {
+  int32_t waves;           /* waves per workgroup [0: tuned]                      */
+  int32_t order;           /* unit order: 0 problem-major, largest first;
+                              1 panels of all problems interleaved [0]            */
+  int32_t init;            /* 1: spectral initialization of each problem first    */
+  int32_t check_every;     /* launches between host looks at the state
+                              [0: 8 if some tol > 0, else max_iters]              */
+  int32_t persistent;      /* 1: ask for a single persistent launch; this build
+                              returns NSRGS_ERR_UNSUPPORTED [0]                   */
+} nsrgs_batch_opts;
+
+/* Workspace bytes for a batch (with_init: include the initialization's). */
+size_t sync_batch_workspace_bytes(const nsrgs_problem *probs, int count, int with_init);
+int sync_solve_batched(const nsrgs_problem *probs, int count, int ns_steps, int max_iters,
+                       void *ws, size_t ws_bytes, void *stream,
+                       const nsrgs_batch_opts *opts /* nullable */,
+                       nsrgs_problem_info *infos /* host, count entries, nullable */);
+
+/* ---- tuning table ---------------------------------------------------------
+ * Launch shapes measured by the autotuner.  kind 0: the single-problem step
+ * (blocks_per_panel B, unroll U column vectors per row, waves W) for storage
+ * format fmt, block size d and n*d in [nd_min, nd_max]; an entry whose (B, U)
+ * is not compiled for d is ignored.  kind 1: waves per workgroup of the
+ * grouped batched launch for format fmt and batches whose largest d is <= d.
+ * The first matching entry wins; entries replace the whole table (count 0
+ * clears it).  Not thread-safe against concurrent launches. */
+typedef struct {
+  int32_t kind, fmt, d;
+  int32_t nd_min, nd_max;
+  int32_t blocks_per_panel, unroll, waves;
+} nsrgs_tune_entry;
+int nsrgs_set_tuning(const nsrgs_tune_entry *entries, int count);
+int nsrgs_get_tuning(nsrgs_tune_entry *entries, int max_count);
+
 /* ---- inputs: measurement generator and format conversion ----------------
  * nsrgs_generate_measurement writes A = Z Z^T + sigma W in F64 or F32
  * (fmt), element (r, c) computed in double and rounded once, where

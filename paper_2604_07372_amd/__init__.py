@@ -16,7 +16,7 @@ __all__ = [
     "F64", "F32", "BF16", "BF16_SPLIT", "FP8_E4M3", "FORMATS", "NsrgsError",
     "lib", "StoredMatrix", "Workspace", "workspace", "step", "read_info",
     "init_spectral", "solve", "generate", "convert", "stored", "padded_ld",
-    "Info",
+    "Info", "solve_batched", "batch_rows_per_panel", "set_tuning", "get_tuning", "TuneEntry",
 ]
 
 F64, F32, BF16, BF16_SPLIT, FP8_E4M3 = 0, 1, 2, 3, 4
@@ -56,6 +56,28 @@ class _SolveOpts(ctypes.Structure):
                 ("A_refine", ctypes.POINTER(_Matrix)), ("check_every", ctypes.c_int32)]
 
 
+class _Problem(ctypes.Structure):
+    _fields_ = [("A", _Matrix), ("n", ctypes.c_int32), ("d", ctypes.c_int32), ("mu", ctypes.c_double),
+                ("X", ctypes.c_void_p), ("iters", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
+class _ProblemInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("nonfinite", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("rel_change", ctypes.c_double),
+                ("max_orth_defect", ctypes.c_double)]
+
+
+class _BatchOpts(ctypes.Structure):
+    _fields_ = [("waves", ctypes.c_int32), ("order", ctypes.c_int32), ("init", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("persistent", ctypes.c_int32)]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("fmt", ctypes.c_int32), ("d", ctypes.c_int32),
+                ("nd_min", ctypes.c_int32), ("nd_max", ctypes.c_int32),
+                ("blocks_per_panel", ctypes.c_int32), ("unroll", ctypes.c_int32), ("waves", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -82,6 +104,11 @@ def lib() -> ctypes.CDLL:
                              ctypes.POINTER(_SolveOpts), ctypes.POINTER(Info)]),
         "nsrgs_generate_measurement": (i32, [vp, i32, i32, dbl, ctypes.c_uint64, i32, dbl, i32, vp, i64, vp]),
         "nsrgs_convert": (i32, [vp, i32, i64, pm, vp]),
+        "nsrgs_set_tuning": (i32, [ctypes.POINTER(TuneEntry), i32]),
+        "nsrgs_get_tuning": (i32, [ctypes.POINTER(TuneEntry), i32]),
+        "sync_batch_workspace_bytes": (sz, [ctypes.POINTER(_Problem), i32, i32]),
+        "sync_solve_batched": (i32, [ctypes.POINTER(_Problem), i32, i32, i32, vp, sz, vp,
+                                     ctypes.POINTER(_BatchOpts), ctypes.POINTER(_ProblemInfo)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -104,6 +131,26 @@ def _stream(device=None) -> int:
 
 def _ptr(t: torch.Tensor | None) -> int | None:
     return None if t is None else t.data_ptr()
+
+
+def set_tuning(entries) -> None:
+    """Install a tuning table (list of dicts with the TuneEntry fields)."""
+    arr = (TuneEntry * max(1, len(entries)))()
+    for i, e in enumerate(entries):
+        arr[i] = TuneEntry(*(int(e[k]) for k, _ in TuneEntry._fields_))
+    _check(lib().nsrgs_set_tuning(arr, len(entries)))
+
+
+def get_tuning() -> list:
+    n = lib().nsrgs_get_tuning(None, 0)
+    arr = (TuneEntry * max(1, n))()
+    lib().nsrgs_get_tuning(arr, n)
+    return [{k: getattr(arr[i], k) for k, _ in TuneEntry._fields_} for i in range(n)]
+
+
+def batch_rows_per_panel(d: int) -> int:
+    """Rows per panel of the batched kernel (whole d x d blocks)."""
+    return d * (8 if d == 1 else 4 if d in (2, 3) else 2 if d == 4 else 1)
 
 
 def padded_ld(nd: int) -> int:
@@ -272,6 +319,34 @@ def convert(A32: torch.Tensor, fmt: int) -> StoredMatrix:
     m = out.c()
     _check(lib().nsrgs_convert(A32.data_ptr(), nd, ld, ctypes.byref(m), _stream()))
     return out
+
+
+def solve_batched(problems, ns_steps: int = 3, max_iters: int = 100, init: bool = False, waves: int = 0,
+                  order: int = 0, check_every: int = 0, persistent: bool = False, check: bool = True):
+    """Many problems in one persistent launch (sync_solve_batched).
+
+    problems: sequence of dicts with keys A (StoredMatrix), n, d, X (device tensor,
+    X^0 on entry unless init, result on return) and optional mu, iters, tol.
+    Returns (status, list of per-problem info dicts)."""
+    count = len(problems)
+    arr = (_Problem * count)()
+    for k, p in enumerate(problems):
+        _check_x(p["X"], p["n"] * p["d"], p["d"], p["A"].fmt, f"problems[{k}].X")
+        arr[k] = _Problem(p["A"].c(), int(p["n"]), int(p["d"]), float(p.get("mu", 0.0)), p["X"].data_ptr(),
+                          int(p.get("iters", 0)), float(p.get("tol", 0.0)))
+    nbytes = lib().sync_batch_workspace_bytes(arr, count, int(init))
+    if nbytes == 0:
+        _check(1)
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=problems[0]["X"].device)
+    off = (-buf.data_ptr()) % 256
+    opts = _BatchOpts(int(waves), int(order), int(init), int(check_every), int(persistent))
+    infos = (_ProblemInfo * count)()
+    st = lib().sync_solve_batched(arr, count, int(ns_steps), int(max_iters), buf.data_ptr() + off, nbytes,
+                                  _stream(), ctypes.byref(opts), infos)
+    if check:
+        _check(st, allow=(5,))
+    out = [{k: getattr(infos[i], k) for k, _ in _ProblemInfo._fields_} for i in range(count)]
+    return st, out
 
 
 def upload(A: "numpy.ndarray", fmt: int = F32, device="cuda") -> StoredMatrix:  # noqa: F821

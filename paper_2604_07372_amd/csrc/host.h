@@ -1,0 +1,54 @@
+// Host-side helpers shared by the C-ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "nsrgs.h"
+
+namespace nsrgs {
+
+// Record an error message for nsrgs_last_error() and return `status`.
+int fail(int status, const char *fmt, ...);
+int dev_fail(hipError_t e, const char *what);
+bool valid_fmt(int fmt);
+size_t xbytes(int fmt);
+size_t align256(size_t v);
+int check_common(int n, int d);
+bool aligned16(const void *p);
+int check_matrix(const nsrgs_matrix *A, int n, int d);
+int env_int(const char *name, int dflt);
+
+#define NSRGS_HIP(call, what)                          \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return dev_fail(e_, what);   \
+  } while (0)
+
+// Results of one problem of a batched launch (host copy of device fields).
+struct BatchResult {
+  int iters, converged, nonfinite, panels;
+  double rel_change, max_defect;
+};
+
+// Grouped launches: one iteration of many problems per launch (batched.hip).
+struct GroupSpec {
+  nsrgs_matrix A;
+  int n, d, iters;
+  void *X0, *X1;          // X^t lives in X0 for even t, X1 for odd t
+  void *stats;            // batch_panels(n, d) PanelStat entries
+  double mu, tol;
+};
+int batch_rows_per_panel(int d);
+int batch_panels(int n, int d);
+size_t group_control_bytes(int count, size_t units);
+int run_grouped(int fmt, const std::vector<GroupSpec> &specs, void *ctl, int launches, int ns_steps,
+                int waves, int order, int check_every, hipStream_t s, std::vector<BatchResult> &out);
+
+// Tuning table (runtime.hip): waves per workgroup of the grouped launch.
+int tuned_batch_waves(int fmt, int dmax);
+
+}  // namespace nsrgs

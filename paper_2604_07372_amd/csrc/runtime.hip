@@ -8,9 +8,12 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "device.h"
+#include "host.h"
 #include "kernels.h"
 #include "nsrgs.h"
 
@@ -18,7 +21,7 @@ namespace nsrgs {
 
 static thread_local std::string g_last_error;
 
-static int fail(int status, const char *fmt, ...) {
+int fail(int status, const char *fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -28,19 +31,14 @@ static int fail(int status, const char *fmt, ...) {
   return status;
 }
 
-static int dev_fail(hipError_t e, const char *what) {
+int dev_fail(hipError_t e, const char *what) {
   return fail(NSRGS_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define NSRGS_HIP(call, what)                 \
-  do {                                        \
-    hipError_t e_ = (call);                   \
-    if (e_ != hipSuccess) return dev_fail(e_, what); \
-  } while (0)
 
-static bool valid_fmt(int fmt) { return fmt >= NSRGS_A_F64 && fmt <= NSRGS_A_FP8_E4M3; }
-static size_t xbytes(int fmt) { return fmt == NSRGS_A_F64 ? 8 : 4; }
-static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+bool valid_fmt(int fmt) { return fmt >= NSRGS_A_F64 && fmt <= NSRGS_A_FP8_E4M3; }
+size_t xbytes(int fmt) { return fmt == NSRGS_A_F64 ? 8 : 4; }
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // ---- workspace layout ------------------------------------------------------
 struct WsLayout {
@@ -65,16 +63,16 @@ static WsLayout layout(int n, int d, int fmt) {
   return L;
 }
 
-static int check_common(int n, int d) {
+int check_common(int n, int d) {
   if (n < 2) return fail(NSRGS_ERR_INVALID_ARG, "n must be >= 2 (got %d)", n);
   if (d < 1 || d > kMaxD) return fail(NSRGS_ERR_INVALID_ARG, "d must be in [1, %d] (got %d)", kMaxD, d);
   if ((int64_t)n * d >= (int64_t)1 << 31) return fail(NSRGS_ERR_INVALID_ARG, "n*d too large");
   return NSRGS_OK;
 }
 
-static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
-static int check_matrix(const nsrgs_matrix *A, int n, int d) {
+int check_matrix(const nsrgs_matrix *A, int n, int d) {
   if (!A) return fail(NSRGS_ERR_INVALID_ARG, "A is NULL");
   if (!valid_fmt(A->fmt)) return fail(NSRGS_ERR_INVALID_ARG, "unknown A format %d", (int)A->fmt);
   if (!A->data) return fail(NSRGS_ERR_INVALID_ARG, "A->data is NULL");
@@ -106,13 +104,45 @@ static bool overlap(const void *a, const void *b, size_t bytes) {
 }
 
 // ---- launch configuration --------------------------------------------------
-static int env_int(const char *name, int dflt) {
+int env_int(const char *name, int dflt) {
   const char *v = getenv(name);
   return (v && *v) ? atoi(v) : dflt;
 }
 
+// ---- tuning table (written by the autotuner, read at every launch) --------
+static std::mutex g_tune_mu;
+static std::vector<nsrgs_tune_entry> g_tune;
+
+static bool tuned_step(int fmt, int d, int nd, StreamConfig *cfg) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  StreamConfig v[16];
+  const int nv = stream_variants(d, v, 16);
+  for (const nsrgs_tune_entry &e : g_tune) {
+    if (e.kind != 0 || e.fmt != fmt || e.d != d || nd < e.nd_min || nd > e.nd_max) continue;
+    for (int i = 0; i < nv; ++i)
+      if (v[i].blocks_per_panel == e.blocks_per_panel && v[i].unroll == e.unroll &&
+          e.waves >= 1 && e.waves <= kMaxWaves) {
+        *cfg = StreamConfig{e.blocks_per_panel, e.waves, e.unroll};
+        return true;
+      }
+  }
+  return false;
+}
+
+int tuned_batch_waves(int fmt, int dmax) {
+  const int forced = env_int("NSRGS_BATCH_W", 0);
+  if (forced >= 1 && forced <= kMaxWaves) return forced;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const nsrgs_tune_entry &e : g_tune)
+    if (e.kind == 1 && e.fmt == fmt && dmax <= e.d && e.waves >= 1 && e.waves <= kMaxWaves) return e.waves;
+  return 1;
+}
+
 StreamConfig choose_stream_config(int fmt, int d, int nd, int mode) {
   StreamConfig cfg{stream_block_init(d), 1, 1};
+  const bool forced = env_int("NSRGS_STEP_B", 0) > 0 || env_int("NSRGS_STEP_U", 0) > 0 ||
+                      env_int("NSRGS_STEP_W", 0) > 0;
+  if (mode == 0 && !forced && tuned_step(fmt, d, nd, &cfg)) return cfg;
   if (mode == 0) {
     StreamConfig v[16];
     const int nv = stream_variants(d, v, 16);
@@ -426,6 +456,20 @@ int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, int
   }
   (void)init_status;
   return result;
+}
+
+int nsrgs_set_tuning(const nsrgs_tune_entry *entries, int count) {
+  if (count < 0 || (count > 0 && !entries)) return fail(NSRGS_ERR_INVALID_ARG, "bad tuning table");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.assign(entries, entries + count);
+  return NSRGS_OK;
+}
+
+int nsrgs_get_tuning(nsrgs_tune_entry *entries, int max_count) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const int n = (int)g_tune.size();
+  for (int i = 0; i < n && i < max_count; ++i) entries[i] = g_tune[i];
+  return n;
 }
 
 int nsrgs_generate_measurement(const double *Z, int n, int d, double sigma, uint64_t seed,

@@ -164,9 +164,35 @@ __device__ __forceinline__ void accum_full(typename Fmt<FMT>::acc_t (&acc)[R][D]
   }
 }
 
+// One panel of R = B d rows: what one workgroup does per column sweep.
+struct PanelJob {
+  const void *A;          // storage of this problem's A
+  const void *A_lo;
+  const float *scale;
+  int64_t ld;
+  const void *X_in;       // X^t (mode 0) or Y (mode 1)
+  void *X_out;            // X^{t+1} (mode 0) or W = A Y (mode 1)
+  int n, nd, panel;
+  double mu;
+  int ns_steps;
+  PanelStat *stat;        // mode 0: where this panel's monitors go
+  void *gram;             // mode 1: where this panel's 2 d^2 partial Grams go
+};
+
+// Stream the panel's rows of A once, reduce the per-lane sums over the
+// workgroup, then (mode 0) run the per-block Riemannian step and
+// Newton-Schulz retraction on chip and write X^{t+1} and the panel monitors,
+// or (mode 1) write W = A Y and the panel's partial Grams.  Every thread of
+// the workgroup must call it; it ends with a barrier, so LDS can be reused.
+// LDS bytes panel_compute needs for a panel of B blocks of d x d.
+template <int FMT, int D, int B>
+constexpr int panel_lds_bytes() {
+  using T = typename Fmt<FMT>::acc_t;
+  return (int)(sizeof(double) * kMaxWaves + sizeof(T) * (kMaxWaves + 6) * B * D * D);
+}
+
 template <int FMT, int D, int B, int U, int MODE>
-__global__ void __launch_bounds__(kWave * kMaxWaves)
-stream_kernel(StreamArgs args) {
+__device__ __forceinline__ void panel_compute(const PanelJob &job, char *lds) {
   using T = typename Fmt<FMT>::acc_t;
   constexpr int V = Fmt<FMT>::V;
   constexpr int R = B * D;
@@ -175,32 +201,27 @@ stream_kernel(StreamArgs args) {
   constexpr int EB = elem_bytes<FMT>();
   constexpr bool EXCL = (MODE == 0);
 
-  __shared__ T s_red[kMaxWaves][NE];
-  __shared__ T sX[NE], sC[NE], sG[NE], sT[NE], sF[NE], sM[NE];
-  __shared__ double s_scr[kMaxWaves];
-  __shared__ int s_last;
-
-  DevCtl *ctl = args.ctl;
-  if (args.stop_flag) {
-    if (__atomic_load_n(args.stop_flag, __ATOMIC_RELAXED)) return;   // uniform
-  }
+  // LDS carve-up (caller-provided, panel_lds_bytes<FMT, D, B>() bytes, 8-aligned)
+  double *s_scr = reinterpret_cast<double *>(lds);
+  T (*s_red)[NE] = reinterpret_cast<T (*)[NE]>(lds + sizeof(double) * kMaxWaves);
+  T *sX = reinterpret_cast<T *>(lds + sizeof(double) * kMaxWaves) + kMaxWaves * NE;
+  T *sC = sX + NE, *sG = sC + NE, *sT = sG + NE, *sF = sT + NE, *sM = sF + NE;
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
   const int nw = blockDim.x / kWave;
-  const int nd = args.nd;
-  const int panel = blockIdx.x;
-  const int row0 = panel * R;
-  const T *__restrict__ X = static_cast<const T *>(args.X_in);
-  const char *__restrict__ Ab = static_cast<const char *>(args.A);
-  const char *__restrict__ Alo = static_cast<const char *>(args.A_lo);
+  const int nd = job.nd;
+  const int row0 = job.panel * R;
+  const T *__restrict__ X = static_cast<const T *>(job.X_in);
+  const char *__restrict__ Ab = static_cast<const char *>(job.A);
+  const char *__restrict__ Alo = static_cast<const char *>(job.A_lo);
 
   int64_t rowoff[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int row = (row0 + r < nd) ? row0 + r : nd - 1;   // clamp: tail rows unused
-    rowoff[r] = (int64_t)row * args.ld * EB;
+    rowoff[r] = (int64_t)row * job.ld * EB;
   }
 
   T acc[R][D];
@@ -249,7 +270,7 @@ stream_kernel(StreamArgs args) {
     T s = s_red[0][e];
     for (int w = 1; w < nw; ++w) s += s_red[w][e];
     const int row = row0 + e / D;
-    if constexpr (FMT == NSRGS_A_FP8_E4M3) s *= (row < nd) ? args.scale[row] : 0.0f;
+    if constexpr (FMT == NSRGS_A_FP8_E4M3) s *= (row < nd) ? job.scale[row] : 0.0f;
     sC[e] = s;
     sX[e] = (row < nd) ? X[(int64_t)row * D + (e % D)] : T(0);
   }
@@ -257,8 +278,8 @@ stream_kernel(StreamArgs args) {
 
   if constexpr (MODE == 0) {
     // ---- fused per-block Riemannian step and Newton-Schulz retraction ----
-    const T nm1 = T(args.n - 1);
-    const T mu = T(args.mu);
+    const T nm1 = T(job.n - 1);
+    const T mu = T(job.mu);
     for (int e = tid; e < NE; e += blockDim.x) sG[e] = nm1 * sX[e] - sC[e];
     __syncthreads();
     // sT = G^T X  (per block)
@@ -282,7 +303,7 @@ stream_kernel(StreamArgs args) {
     __syncthreads();
     T *cur = sF;
     T *nxt = sT;
-    const int steps = args.ns_steps;
+    const int steps = job.ns_steps;
     for (int st = 0; st < (steps > 0 ? steps : 1); ++st) {
       // M = S^T S
       for (int e = tid; e < NE; e += blockDim.x) {
@@ -313,7 +334,7 @@ stream_kernel(StreamArgs args) {
       }
     }
     // ---- write X^{t+1} and the panel monitors ------------------------------
-    T *__restrict__ Xo = static_cast<T *>(args.X_out);
+    T *__restrict__ Xo = static_cast<T *>(job.X_out);
     double dx2 = 0.0, x2 = 0.0, dmax = 0.0;
     int nonfin = 0;
     for (int e = tid; e < NE; e += blockDim.x) {
@@ -340,52 +361,15 @@ stream_kernel(StreamArgs args) {
     x2 = block_sum(x2, s_scr);
     dmax = block_max(dmax, s_scr);
     const double nf = block_max((double)nonfin, s_scr);
-    PanelStat *part = static_cast<PanelStat *>(args.partials);
-    if (tid == 0) part[panel] = PanelStat{dx2, x2, dmax, nf};
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) s_last = (atomicAdd(&ctl->arrive, 1u) == (unsigned)args.num_panels - 1u);
-    __syncthreads();
-    if (s_last) {
-      __threadfence();
-      double a = 0.0, bsum = 0.0, m = 0.0, f = 0.0;
-      for (int p = tid; p < args.num_panels; p += blockDim.x) {
-        const PanelStat q = part[p];
-        a += q.dx2;
-        bsum += q.x2;
-        m = q.dmax > m ? q.dmax : m;
-        f = q.nonfinite > f ? q.nonfinite : f;
-      }
-      a = block_sum(a, s_scr);
-      bsum = block_sum(bsum, s_scr);
-      m = block_max(m, s_scr);
-      f = block_max(f, s_scr);
-      if (tid == 0) {
-        const double rel = bsum > 0.0 ? sqrt(a / bsum) : 0.0;
-        ctl->sum_dx2 = a;
-        ctl->sum_x2 = bsum;
-        ctl->rel_change = rel;
-        ctl->max_defect = m;
-        ctl->nonfinite = f != 0.0;
-        ctl->iters = args.iter + 1;
-        if (f != 0.0 || !isfinite(rel)) {
-          ctl->nonfinite = 1;
-          ctl->done = 1;
-        } else if (args.tol > 0.0 && rel <= args.tol) {
-          ctl->converged = 1;
-          ctl->done = 1;
-        }
-        ctl->arrive = 0u;
-      }
-    }
+    if (tid == 0) *job.stat = PanelStat{dx2, x2, dmax, nf};
   } else {
     // ---- mode 1: W = A Y for the panel rows; partial Grams Y^T W, W^T W ----
-    T *__restrict__ Wo = static_cast<T *>(args.X_out);
+    T *__restrict__ Wo = static_cast<T *>(job.X_out);
     for (int e = tid; e < NE; e += blockDim.x) {
       const int row = row0 + e / D;
       if (row < nd) Wo[(int64_t)row * D + (e % D)] = sC[e];
     }
-    T *part = static_cast<T *>(args.partials) + (int64_t)panel * 2 * D * D;
+    T *part = static_cast<T *>(job.gram);
     for (int e = tid; e < D * D; e += blockDim.x) {
       const int a = e / D, k = e % D;
       T g1 = 0, g2 = 0;
@@ -398,52 +382,127 @@ stream_kernel(StreamArgs args) {
       part[e] = g1;
       part[D * D + e] = g2;
     }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) s_last = (atomicAdd(&ctl->arrive2, 1u) == (unsigned)args.num_panels - 1u);
-    __syncthreads();
-    if (s_last) {
-      __threadfence();
-      __shared__ double G1[kMaxD * kMaxD], G2[kMaxD * kMaxD], Rm[kMaxD * kMaxD];
-      const T *all = static_cast<const T *>(args.partials);
-      for (int e = tid; e < 2 * D * D; e += blockDim.x) {
-        double s = 0.0;
-        for (int p = 0; p < args.num_panels; ++p) s += (double)all[(int64_t)p * 2 * D * D + e];
-        if (e < D * D) G1[e] = s; else G2[e - D * D] = s;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        // Rayleigh quotient T = Y^T A Y (symmetrised) and Cholesky W^T W = R^T R.
-        int bad = 0;
-        for (int a = 0; a < D; ++a)
-          for (int k = 0; k < D; ++k) ctl->T[a * D + k] = 0.5 * (G1[a * D + k] + G1[k * D + a]);
-        for (int j = 0; j < D * D; ++j) Rm[j] = 0.0;
-        for (int j = 0; j < D; ++j) {
-          double s = G2[j * D + j];
-          for (int q = 0; q < j; ++q) s -= Rm[q * D + j] * Rm[q * D + j];
-          if (!(s > 0.0) || !isfinite(s)) { bad = 1; s = 1.0; }
-          const double rjj = sqrt(s);
-          Rm[j * D + j] = rjj;
-          for (int k = j + 1; k < D; ++k) {
-            double t = G2[j * D + k];
-            for (int q = 0; q < j; ++q) t -= Rm[q * D + j] * Rm[q * D + k];
-            Rm[j * D + k] = t / rjj;
-          }
-        }
-        // Rinv = R^{-1} (upper triangular), column by column.
-        for (int j = 0; j < D * D; ++j) ctl->Rinv[j] = 0.0;
-        for (int k = 0; k < D; ++k) {
-          ctl->Rinv[k * D + k] = 1.0 / Rm[k * D + k];
-          for (int i = k - 1; i >= 0; --i) {
-            double s = 0.0;
-            for (int q = i + 1; q <= k; ++q) s += Rm[i * D + q] * ctl->Rinv[q * D + k];
-            ctl->Rinv[i * D + k] = -s / Rm[i * D + i];
-          }
-        }
-        if (bad) ctl->init_bad = 1;
-        ctl->arrive2 = 0u;
+  }
+  __syncthreads();
+}
+
+// Last workgroup of a mode-0 launch: reduce the panel monitors in a fixed
+// order (FP64) into the control block and apply the stop rule.
+__device__ inline void finish_step(const StreamArgs &args, double *s_scr) {
+  const int tid = threadIdx.x;
+  DevCtl *ctl = args.ctl;
+  const PanelStat *part = static_cast<const PanelStat *>(args.partials);
+  double a = 0.0, bsum = 0.0, m = 0.0, f = 0.0;
+  for (int p = tid; p < args.num_panels; p += blockDim.x) {
+    const PanelStat q = part[p];
+    a += q.dx2;
+    bsum += q.x2;
+    m = q.dmax > m ? q.dmax : m;
+    f = q.nonfinite > f ? q.nonfinite : f;
+  }
+  a = block_sum(a, s_scr);
+  bsum = block_sum(bsum, s_scr);
+  m = block_max(m, s_scr);
+  f = block_max(f, s_scr);
+  if (tid == 0) {
+    const double rel = bsum > 0.0 ? sqrt(a / bsum) : 0.0;
+    ctl->sum_dx2 = a;
+    ctl->sum_x2 = bsum;
+    ctl->rel_change = rel;
+    ctl->max_defect = m;
+    ctl->nonfinite = f != 0.0;
+    ctl->iters = args.iter + 1;
+    if (f != 0.0 || !isfinite(rel)) {
+      ctl->nonfinite = 1;
+      ctl->done = 1;
+    } else if (args.tol > 0.0 && rel <= args.tol) {
+      ctl->converged = 1;
+      ctl->done = 1;
+    }
+    ctl->arrive = 0u;
+  }
+}
+
+// Last workgroup of a mode-1 launch: FP64 reduction of the partial Grams,
+// the Rayleigh quotient T = Y^T A Y and the Cholesky factor of W^T W.
+template <typename T, int D>
+__device__ inline void finish_gram(const StreamArgs &args) {
+  __shared__ double G1[kMaxD * kMaxD], G2[kMaxD * kMaxD], Rm[kMaxD * kMaxD];
+  const int tid = threadIdx.x;
+  DevCtl *ctl = args.ctl;
+  const T *all = static_cast<const T *>(args.partials);
+  for (int e = tid; e < 2 * D * D; e += blockDim.x) {
+    double s = 0.0;
+    for (int p = 0; p < args.num_panels; ++p) s += (double)all[(int64_t)p * 2 * D * D + e];
+    if (e < D * D) G1[e] = s; else G2[e - D * D] = s;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int bad = 0;
+    for (int a = 0; a < D; ++a)
+      for (int k = 0; k < D; ++k) ctl->T[a * D + k] = 0.5 * (G1[a * D + k] + G1[k * D + a]);
+    for (int j = 0; j < D * D; ++j) Rm[j] = 0.0;
+    for (int j = 0; j < D; ++j) {
+      double s = G2[j * D + j];
+      for (int q = 0; q < j; ++q) s -= Rm[q * D + j] * Rm[q * D + j];
+      if (!(s > 0.0) || !isfinite(s)) { bad = 1; s = 1.0; }
+      const double rjj = sqrt(s);
+      Rm[j * D + j] = rjj;
+      for (int k = j + 1; k < D; ++k) {
+        double t = G2[j * D + k];
+        for (int q = 0; q < j; ++q) t -= Rm[q * D + j] * Rm[q * D + k];
+        Rm[j * D + k] = t / rjj;
       }
     }
+    // Rinv = R^{-1} (upper triangular), column by column.
+    for (int j = 0; j < D * D; ++j) ctl->Rinv[j] = 0.0;
+    for (int k = 0; k < D; ++k) {
+      ctl->Rinv[k * D + k] = 1.0 / Rm[k * D + k];
+      for (int i = k - 1; i >= 0; --i) {
+        double s = 0.0;
+        for (int q = i + 1; q <= k; ++q) s += Rm[i * D + q] * ctl->Rinv[q * D + k];
+        ctl->Rinv[i * D + k] = -s / Rm[i * D + i];
+      }
+    }
+    if (bad) ctl->init_bad = 1;
+    ctl->arrive2 = 0u;
+  }
+}
+
+template <int FMT, int D, int B, int U, int MODE>
+__global__ void __launch_bounds__(kWave * kMaxWaves)
+stream_kernel(StreamArgs args) {
+  using T = typename Fmt<FMT>::acc_t;
+  __shared__ double s_scr[kMaxWaves];
+  __shared__ int s_last;
+  __shared__ __attribute__((aligned(16))) char lds[panel_lds_bytes<FMT, D, B>()];
+  if (args.stop_flag) {
+    if (__atomic_load_n(args.stop_flag, __ATOMIC_RELAXED)) return;   // uniform
+  }
+  PanelJob job;
+  job.A = args.A;
+  job.A_lo = args.A_lo;
+  job.scale = args.scale;
+  job.ld = args.ld;
+  job.X_in = args.X_in;
+  job.X_out = args.X_out;
+  job.n = args.n;
+  job.nd = args.nd;
+  job.panel = blockIdx.x;
+  job.mu = args.mu;
+  job.ns_steps = args.ns_steps;
+  job.stat = static_cast<PanelStat *>(args.partials) + blockIdx.x;
+  job.gram = static_cast<T *>(args.partials) + (int64_t)blockIdx.x * 2 * D * D;
+  panel_compute<FMT, D, B, U, MODE>(job, lds);
+  // The last workgroup to arrive reduces the per-panel results.
+  __threadfence();
+  unsigned *arrive = MODE == 0 ? &args.ctl->arrive : &args.ctl->arrive2;
+  if (threadIdx.x == 0) s_last = (atomicAdd(arrive, 1u) == (unsigned)args.num_panels - 1u);
+  __syncthreads();
+  if (s_last) {
+    __threadfence();
+    if constexpr (MODE == 0) finish_step(args, s_scr);
+    else finish_gram<T, D>(args);
   }
 }
 
