@@ -81,6 +81,106 @@ def cpu_baseline(budget_s: float = 12.0):
                       f"{dt * 1e3:.2f} ms each, scaled by (60000/6000)^2 = {scale:.0f} to n=20000"}
 
 
+def batched_bench(iters: int = 100, base_iters: int = 10, count: int = 512, seed0: int = 1000):
+    """512 independent problems: n log-uniform in [50, 3000], d uniform in
+    {2, 3, 4, 10}, sigma = 0.2 sqrt(n/d), dense FP32 A generated on the device.
+    Times `iters` iterations through grouped launches (one launch per iteration
+    for all problems) and `base_iters` iterations as one sync_step launch per
+    problem per iteration.  Every problem starts from its ground truth with a
+    0.05 perturbation (the initialization is not part of the timed loop)."""
+    import numpy as np
+    import torch
+    import paper_2604_07372_amd as P
+    import synth
+    rng = np.random.default_rng(seed0)
+    probs, a_bytes = [], 0
+    for k in range(count):
+        n = int(np.floor(np.exp(rng.uniform(np.log(50), np.log(3000)))))
+        d = int(rng.choice([2, 3, 4, 10]))
+        Z = synth.haar_blocks(n, d, seed0 + k)
+        A = P.generate(torch.from_numpy(Z).cuda(), synth.sigma_for(C_NOISE, n, d), seed0 + k, fmt=P.F32)
+        X0 = torch.from_numpy(synth.perturbed_start(Z, 0.05, seed0 + 7 * k + 1)).cuda().float()
+        probs.append({"A": P.stored(A, P.F32), "n": n, "d": d, "X": X0.clone(), "X0": X0})
+        a_bytes += (n * d) ** 2 * 4
+    torch.cuda.synchronize()
+    print(f"[bench] batched: {count} problems, {a_bytes / 1e9:.1f} GB of A", file=sys.stderr, flush=True)
+    P.solve_batched(probs, max_iters=2)                          # warm-up
+    for p in probs:
+        p["X"].copy_(p["X0"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, infos = P.solve_batched(probs, ns_steps=3, max_iters=iters)
+    torch.cuda.synchronize()
+    t_group = time.perf_counter() - t0
+    wss = [P.workspace(p["n"], p["d"], P.F32) for p in probs]
+    outs = [torch.empty_like(p["X0"]) for p in probs]
+    for p, w, o in zip(probs, wss, outs):
+        P.step(p["A"], p["n"], p["d"], p["X0"], o, w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(base_iters):
+        for p, w, o in zip(probs, wss, outs):
+            P.step(p["A"], p["n"], p["d"], p["X0"], o, w)
+    torch.cuda.synchronize()
+    t_base = (time.perf_counter() - t0) * iters / base_iters
+    res = {"problems": count, "iters": iters, "a_bytes_per_iter": a_bytes,
+           "grouped_s": t_group, "grouped_problem_iters_per_s": count * iters / t_group,
+           "grouped_GBps": a_bytes * iters / t_group / 1e9,
+           "per_problem_launch_s_scaled": t_base,
+           "per_problem_launch_problem_iters_per_s": count * iters / t_base,
+           "speedup_vs_per_problem_launches": t_base / t_group,
+           "status": st, "all_iters_done": all(i["iters"] == iters for i in infos)}
+    print(f"[bench] batched: grouped {t_group:.3f} s ({res['grouped_GBps']:.0f} GB/s), per-problem launches "
+          f"{t_base:.3f} s -> {res['speedup_vs_per_problem_launches']:.2f}x", file=sys.stderr, flush=True)
+    del probs, wss, outs
+    torch.cuda.empty_cache()
+    return res
+
+
+def serving_bench(window_s: float = 10.0, rate: float = 50.0, seed0: int = 5000):
+    """Poisson arrivals at `rate` requests/s for `window_s` seconds; each request:
+    n log-uniform in [100, 20000], d in {3, 4}, sigma = 0.2 sqrt(n/d), Haar ground
+    truth, A generated on the device and stored in BF16, stop at relative change
+    1e-6 or 300 iterations.  Reports p50/p99 latency (submit to result) and solves/s."""
+    import numpy as np
+    import paper_2604_07372_amd as P
+    import synth
+    rng = np.random.default_rng(42)
+    arrivals, reqs = [], []
+    t = 0.0
+    k = 0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > window_s:
+            break
+        n = int(np.floor(np.exp(rng.uniform(np.log(100), np.log(20000)))))
+        d = int(rng.choice([3, 4]))
+        reqs.append((synth.haar_blocks(n, d, seed0 + k), synth.sigma_for(C_NOISE, n, d), seed0 + k))
+        arrivals.append(t)
+        k += 1
+    print(f"[bench] serving: {len(reqs)} requests over {window_s:.0f} s", file=sys.stderr, flush=True)
+    with P.Server(fmt=P.BF16) as srv:
+        base = srv.clock()
+        for (Z, sigma, seed), ta in zip(reqs, arrivals):
+            while srv.clock() - base < ta:
+                time.sleep(0.0002)
+            srv.submit(Z, sigma, seed, tol=1e-6, max_iters=300)
+        srv.wait_idle(300.0)
+        res = srv.poll(len(reqs) + 8)
+        st = srv.stats()
+    iters = [r["iters"] for r in res]
+    out = {"requests": len(reqs), "rate_per_s": rate, "window_s": window_s,
+           "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
+           "mean_latency_s": st["mean_latency_s"], "solves_per_s": st["solves_per_s"],
+           "completed": st["completed"], "rejected": st["rejected"],
+           "converged": sum(r["converged"] for r in res), "max_active_seen": st["max_active_seen"],
+           "mean_iters": float(np.mean(iters)) if iters else 0.0,
+           "pool_peak_GB": st["pool_peak_bytes"] / 1e9}
+    print(f"[bench] serving: p50 {out['p50_latency_s'] * 1e3:.1f} ms, p99 {out['p99_latency_s'] * 1e3:.1f} ms, "
+          f"{out['solves_per_s']:.1f} solves/s", file=sys.stderr, flush=True)
+    return out
+
+
 def alignment_error(X, Z) -> float:
     """min over Q in O(d) of ||X - Z Q||_F / sqrt(n), Q from the SVD of Z^T X."""
     import numpy as np
@@ -111,6 +211,9 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--formats", default="f32,bf16,bf16_split,fp8")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-window", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (counter calibration)")
     a = ap.parse_args(argv)
@@ -194,6 +297,12 @@ def main(argv=None):
             for name in solve:
                 solve[name]["align_err_rel_vs_f32"] = abs(solve[name]["align_err"] - ref) / ref
 
+    stores.clear()
+    Am = A32 = None
+    torch.cuda.empty_cache()
+    batched = None if a.no_batched else batched_bench()
+    serving = None if a.no_serving else serving_bench(window_s=a.serving_window)
+
     f32 = results["f32"]
     roof = {"bound": "hbm", "achieved": f32["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": f32["alg_GBps"] / HBM_PEAK_GBS, "traffic": traffic_from_profile(),
@@ -224,6 +333,8 @@ def main(argv=None):
                     for k, r in results.items()},
         "speedup_vs_f32": {k: results["f32"]["ms_per_step"] / r["ms_per_step"] for k, r in results.items()},
         "solve": solve,
+        "batched": batched,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -214,6 +214,76 @@ int sync_solve_batched(const nsrgs_problem *probs, int count, int ns_steps, int 
                        const nsrgs_batch_opts *opts /* nullable */,
                        nsrgs_problem_info *infos /* host, count entries, nullable */);
 
+/* ---- serving: a request loop with continuous batching --------------------
+ * A server owns a device memory pool (one allocation at creation), a
+ * scheduler thread and ingest worker threads.  Requests describe a synthetic
+ * measurement problem (n, d <= 10, sigma, seed, ground truth Z on the host);
+ * they are admitted in arrival order when their footprint (A in the server's
+ * storage format, two iterates, monitors, and transient ingest buffers) fits
+ * the pool and a solve slot is free (a request that does not fit yet does
+ * not block later, smaller ones).  On admission an ingest worker generates
+ * A on the device (nsrgs_generate_measurement's element rule, in FP32 row
+ * chunks converted to the storage format) and runs sync_init_spectral on the
+ * worker's own stream.  The scheduler thread runs ticks of `iters_per_tick` grouped
+ * launches over all ready requests (sync_solve_batched's kernel), each
+ * request at its own iteration count, stopping a request at relative change
+ * <= tol or after max_iters iterations; finished requests copy their result to
+ * X_out, free their memory and post an nsrgs_result.  A request's result does
+ * not depend on what else is being served.  All calls are thread-safe. */
+typedef struct nsrgs_server nsrgs_server;
+
+typedef struct {
+  int32_t fmt;              /* NSRGS_A_BF16 or NSRGS_A_F32 (must be set when opts
+                               is given; NULL opts: BF16)                         */
+  int32_t max_active;       /* solve slots [0: 64]                                */
+  int32_t iters_per_tick;   /* grouped launches per scheduler tick [0: 4]         */
+  int32_t ns_steps;         /* Newton-Schulz steps [0: 3]                          */
+  int32_t waves;            /* waves per workgroup [0: tuned]                      */
+  int32_t ingest_workers;   /* threads (one stream each) preparing requests [0: 4] */
+  uint64_t pool_bytes;      /* device memory for requests [0: half of free]       */
+} nsrgs_server_opts;
+
+typedef struct {
+  int32_t n, d;
+  double sigma;
+  uint64_t seed;            /* generator seed of W                                 */
+  const double *Z;          /* host n*d x d ground truth, copied at submit         */
+  double tol;               /* relative-change stop [<= 0: 1e-6]                   */
+  int32_t max_iters;        /* [<= 0: 300]                                         */
+  float *X_out;             /* host n*d x d result buffer (nullable); must stay
+                               valid until the request's result is posted         */
+} nsrgs_request;
+
+typedef struct {
+  int64_t id;
+  int32_t status, iters, converged, pad;
+  double t_submit, t_admit, t_start, t_done;   /* seconds on the server clock */
+  double rel_change;
+} nsrgs_result;
+
+typedef struct {
+  int64_t submitted, completed, rejected;
+  int32_t active, max_active_seen;
+  double p50_latency_s, p99_latency_s, mean_latency_s;   /* submit -> result */
+  double solves_per_s;     /* completed / (last result - first submit)        */
+  uint64_t pool_bytes, pool_peak_bytes;
+} nsrgs_server_stats;
+
+int nsrgs_server_create(const nsrgs_server_opts *opts /* nullable */, nsrgs_server **out);
+/* Queue a request; *id (nullable) receives its id.  A request larger than the
+ * whole pool is accepted and immediately posted with NSRGS_ERR_OUT_OF_MEMORY. */
+int nsrgs_server_submit(nsrgs_server *server, const nsrgs_request *req, int64_t *id);
+/* Up to max posted results, oldest first; *count receives how many. */
+int nsrgs_server_poll(nsrgs_server *server, nsrgs_result *results, int max, int *count);
+/* Wait until nothing is queued, ingesting or iterating (timeout_s <= 0: no
+ * limit; NSRGS_ERR_NOT_CONVERGED on timeout). */
+int nsrgs_server_wait_idle(nsrgs_server *server, double timeout_s);
+int nsrgs_server_get_stats(nsrgs_server *server, nsrgs_server_stats *stats);
+double nsrgs_server_clock(const nsrgs_server *server);   /* seconds since creation */
+/* Stop the threads; requests not finished are posted as NOT_CONVERGED and the
+ * pool is freed. */
+int nsrgs_server_destroy(nsrgs_server *server);
+
 /* ---- tuning table ---------------------------------------------------------
  * Launch shapes measured by the autotuner.  kind 0: the single-problem step
  * (blocks_per_panel B, unroll U column vectors per row, waves W) for storage

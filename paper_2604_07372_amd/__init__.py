@@ -16,7 +16,7 @@ __all__ = [
     "F64", "F32", "BF16", "BF16_SPLIT", "FP8_E4M3", "FORMATS", "NsrgsError",
     "lib", "StoredMatrix", "Workspace", "workspace", "step", "read_info",
     "init_spectral", "solve", "generate", "convert", "stored", "padded_ld",
-    "Info", "solve_batched", "batch_rows_per_panel", "set_tuning", "get_tuning", "TuneEntry",
+    "Info", "solve_batched", "batch_rows_per_panel", "set_tuning", "get_tuning", "TuneEntry", "Server",
 ]
 
 F64, F32, BF16, BF16_SPLIT, FP8_E4M3 = 0, 1, 2, 3, 4
@@ -78,6 +78,33 @@ class TuneEntry(ctypes.Structure):
                 ("blocks_per_panel", ctypes.c_int32), ("unroll", ctypes.c_int32), ("waves", ctypes.c_int32)]
 
 
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("fmt", ctypes.c_int32), ("max_active", ctypes.c_int32), ("iters_per_tick", ctypes.c_int32),
+                ("ns_steps", ctypes.c_int32), ("waves", ctypes.c_int32), ("ingest_workers", ctypes.c_int32),
+                ("pool_bytes", ctypes.c_uint64)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("d", ctypes.c_int32), ("sigma", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("Z", ctypes.c_void_p), ("tol", ctypes.c_double),
+                ("max_iters", ctypes.c_int32), ("X_out", ctypes.c_void_p)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("pad", ctypes.c_int32), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("rel_change", ctypes.c_double)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("active", ctypes.c_int32), ("max_active_seen", ctypes.c_int32),
+                ("p50_latency_s", ctypes.c_double), ("p99_latency_s", ctypes.c_double),
+                ("mean_latency_s", ctypes.c_double), ("solves_per_s", ctypes.c_double),
+                ("pool_bytes", ctypes.c_uint64), ("pool_peak_bytes", ctypes.c_uint64)]
+
+
 _lib = None
 
 
@@ -106,6 +133,13 @@ def lib() -> ctypes.CDLL:
         "nsrgs_convert": (i32, [vp, i32, i64, pm, vp]),
         "nsrgs_set_tuning": (i32, [ctypes.POINTER(TuneEntry), i32]),
         "nsrgs_get_tuning": (i32, [ctypes.POINTER(TuneEntry), i32]),
+        "nsrgs_server_create": (i32, [ctypes.POINTER(_ServerOpts), ctypes.POINTER(vp)]),
+        "nsrgs_server_submit": (i32, [vp, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_int64)]),
+        "nsrgs_server_poll": (i32, [vp, ctypes.POINTER(_Result), i32, ctypes.POINTER(i32)]),
+        "nsrgs_server_wait_idle": (i32, [vp, dbl]),
+        "nsrgs_server_get_stats": (i32, [vp, ctypes.POINTER(_ServerStats)]),
+        "nsrgs_server_clock": (dbl, [vp]),
+        "nsrgs_server_destroy": (i32, [vp]),
         "sync_batch_workspace_bytes": (sz, [ctypes.POINTER(_Problem), i32, i32]),
         "sync_solve_batched": (i32, [ctypes.POINTER(_Problem), i32, i32, i32, vp, sz, vp,
                                      ctypes.POINTER(_BatchOpts), ctypes.POINTER(_ProblemInfo)]),
@@ -347,6 +381,68 @@ def solve_batched(problems, ns_steps: int = 3, max_iters: int = 100, init: bool 
         _check(st, allow=(5,))
     out = [{k: getattr(infos[i], k) for k, _ in _ProblemInfo._fields_} for i in range(count)]
     return st, out
+
+
+class Server:
+    """Continuous-batching solve server (nsrgs_server_*), on the current device.
+
+    submit() takes the problem description and the host ground truth Z; the
+    result lands in a host float32 array that submit() returns (filled when the
+    request's result is posted)."""
+
+    def __init__(self, fmt: int = BF16, pool_bytes: int = 0, max_active: int = 64, iters_per_tick: int = 4,
+                 ns_steps: int = 3, waves: int = 0, ingest_workers: int = 0):
+        opts = _ServerOpts(int(fmt), int(max_active), int(iters_per_tick), int(ns_steps), int(waves),
+                           int(ingest_workers), int(pool_bytes))
+        h = ctypes.c_void_p()
+        _check(lib().nsrgs_server_create(ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, Z, sigma: float, seed: int, tol: float = 1e-6, max_iters: int = 300):
+        import numpy as np
+        Z = np.ascontiguousarray(Z, dtype=np.float64)
+        nd, d = Z.shape
+        out = np.zeros((nd, d), dtype=np.float32)
+        req = _Request(nd // d, d, float(sigma), int(seed), Z.ctypes.data, float(tol), int(max_iters),
+                       out.ctypes.data)
+        rid = ctypes.c_int64()
+        _check(lib().nsrgs_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid)))
+        self._keep[rid.value] = (Z, out)
+        return rid.value, out
+
+    def poll(self, max_results: int = 1024) -> list:
+        arr = (_Result * max_results)()
+        cnt = ctypes.c_int()
+        _check(lib().nsrgs_server_poll(self._h, arr, max_results, ctypes.byref(cnt)))
+        out = []
+        for i in range(cnt.value):
+            r = {k: getattr(arr[i], k) for k, _ in _Result._fields_ if k != "pad"}
+            self._keep.pop(r["id"], None)
+            out.append(r)
+        return out
+
+    def wait_idle(self, timeout_s: float = 0.0) -> int:
+        return _check(lib().nsrgs_server_wait_idle(self._h, float(timeout_s)), allow=(5,))
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        _check(lib().nsrgs_server_get_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in _ServerStats._fields_}
+
+    def clock(self) -> float:
+        return lib().nsrgs_server_clock(self._h)
+
+    def close(self) -> None:
+        if self._h:
+            lib().nsrgs_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def upload(A: "numpy.ndarray", fmt: int = F32, device="cuda") -> StoredMatrix:  # noqa: F821

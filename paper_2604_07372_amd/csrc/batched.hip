@@ -156,8 +156,7 @@ __global__ void __launch_bounds__(kWave * kMaxWaves) grouped_kernel(GroupArgs ar
 __global__ void group_reset_kernel(GroupInst *inst, int count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) {
-    inst[i].t = 0;
-    inst[i].active = inst[i].iters > 0 ? 1 : 0;
+    inst[i].active = inst[i].t < inst[i].iters ? 1 : 0;
     inst[i].arrive = 0u;
     inst[i].converged = 0;
     inst[i].nonfinite = 0;
@@ -220,7 +219,8 @@ size_t group_control_bytes(int count, size_t units) {
   return align256((size_t)count * sizeof(GroupInst)) + align256(units * sizeof(GroupUnit));
 }
 
-// Upload descriptors, then up to `launches` grouped launches (every
+// Upload descriptors (problem k resumes at iteration specs[k].t0, its
+// iterate in X[t0 & 1]), then up to `launches` grouped launches (every
 // `check_every` launches the descriptors are read back and the loop ends early
 // once no problem is active).  Reads the final state into `out`.
 int run_grouped(int fmt, const std::vector<GroupSpec> &specs, void *ctl, int launches, int ns_steps,
@@ -244,6 +244,7 @@ int run_grouped(int fmt, const std::vector<GroupSpec> &specs, void *ctl, int lau
     I.nd = g.n * g.d;
     I.panels = batch_panels(g.n, g.d);
     I.iters = g.iters;
+    I.t = g.t0;
     I.mu = g.mu > 0.0 ? g.mu : 1.0 / g.n;
     I.tol = g.tol;
     host[k] = I;
@@ -288,6 +289,7 @@ int run_grouped(int fmt, const std::vector<GroupSpec> &specs, void *ctl, int lau
     out[k].panels = back[k].panels;
     out[k].rel_change = back[k].rel_change;
     out[k].max_defect = back[k].max_defect;
+    out[k].active = back[k].active;
   }
   return NSRGS_OK;
 }
@@ -405,6 +407,7 @@ int sync_solve_batched(const nsrgs_problem *probs, int count, int ns_steps, int 
     g.stats = base + L.stats_off[k];
     g.mu = P.mu;
     g.tol = P.tol;
+    g.t0 = 0;
     any_tol = any_tol || P.tol > 0.0;
   }
   std::vector<BatchResult> res;

@@ -12,13 +12,13 @@ namespace nsrgs {
 template <typename T>
 __global__ void __launch_bounds__(256)
 generate_kernel(const double *__restrict__ Z, int n, int d, double sigma, uint32_t k0,
-                uint32_t k1, int zero_diag, double p, T *__restrict__ A, int64_t ld) {
+                uint32_t k1, int zero_diag, double p, T *__restrict__ A, int64_t ld, int row0) {
   const int nd = n * d;
-  const int r = blockIdx.x;
+  const int r = row0 + (int)blockIdx.x;     // global row; A points at row row0
   double zr[kMaxD];
   for (int k = 0; k < d; ++k) zr[k] = Z[(int64_t)r * d + k];
   const int br = r / d;
-  T *out = A + (int64_t)r * ld;
+  T *out = A + (int64_t)blockIdx.x * ld;
   for (int c = threadIdx.x; c < nd; c += blockDim.x) {
     double v = 0.0;
     for (int k = 0; k < d; ++k) v = fma(zr[k], Z[(int64_t)c * d + k], v);
@@ -73,9 +73,9 @@ __device__ __forceinline__ uint32_t e4m3_rne_sat(float x) {
 
 __global__ void __launch_bounds__(256)
 convert_bf16_kernel(const float *__restrict__ A, int nd, int64_t ld, uint16_t *__restrict__ hi,
-                    uint16_t *__restrict__ lo) {
-  const int r = blockIdx.x;
-  const float *src = A + (int64_t)r * ld;
+                    uint16_t *__restrict__ lo, int row0) {
+  const int r = row0 + (int)blockIdx.x;             // destination row; A points at row row0
+  const float *src = A + (int64_t)blockIdx.x * ld;
   for (int c = threadIdx.x; c < nd; c += blockDim.x) {
     const float a = src[c];
     const uint32_t h = bf16_rne_bits(a);
@@ -89,10 +89,10 @@ convert_bf16_kernel(const float *__restrict__ A, int nd, int64_t ld, uint16_t *_
 
 __global__ void __launch_bounds__(256)
 convert_fp8_kernel(const float *__restrict__ A, int nd, int64_t ld, uint8_t *__restrict__ q,
-                   float *__restrict__ scale) {
+                   float *__restrict__ scale, int row0) {
   __shared__ float s_scr[kMaxWaves];
-  const int r = blockIdx.x;
-  const float *src = A + (int64_t)r * ld;
+  const int r = row0 + (int)blockIdx.x;             // destination row; A points at row row0
+  const float *src = A + (int64_t)blockIdx.x * ld;
   float m = 0.0f;
   for (int c = threadIdx.x; c < nd; c += blockDim.x) m = fmaxf(m, fabsf(src[c]));
   m = block_max(m, s_scr);
@@ -102,42 +102,55 @@ convert_fp8_kernel(const float *__restrict__ A, int nd, int64_t ld, uint8_t *__r
     q[(int64_t)r * ld + c] = (uint8_t)e4m3_rne_sat(src[c] / s);
 }
 
-hipError_t launch_generate(const double *Z, int n, int d, double sigma, uint64_t seed,
-                           int zero_diag, double p, int fmt, void *A, int64_t ld,
-                           hipStream_t s) {
-  const dim3 grid((unsigned)(n * d)), block(256);
+hipError_t launch_generate_rows(const double *Z, int n, int d, double sigma, uint64_t seed,
+                                int zero_diag, double p, int fmt, void *A_rows, int64_t ld, int row0,
+                                int nrows, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  const dim3 grid((unsigned)nrows), block(256);
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   if (fmt == NSRGS_A_F64)
     hipLaunchKernelGGL(generate_kernel<double>, grid, block, 0, s, Z, n, d, sigma, k0, k1,
-                       zero_diag, p, (double *)A, ld);
+                       zero_diag, p, (double *)A_rows, ld, row0);
   else if (fmt == NSRGS_A_F32)
     hipLaunchKernelGGL(generate_kernel<float>, grid, block, 0, s, Z, n, d, sigma, k0, k1,
-                       zero_diag, p, (float *)A, ld);
+                       zero_diag, p, (float *)A_rows, ld, row0);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t launch_convert(const float *A32, int nd, int64_t ld, const nsrgs_matrix &out,
-                          hipStream_t s) {
-  const dim3 grid((unsigned)nd), block(256);
+hipError_t launch_generate(const double *Z, int n, int d, double sigma, uint64_t seed,
+                           int zero_diag, double p, int fmt, void *A, int64_t ld,
+                           hipStream_t s) {
+  return launch_generate_rows(Z, n, d, sigma, seed, zero_diag, p, fmt, A, ld, 0, n * d, s);
+}
+
+hipError_t launch_convert_rows(const float *A32_rows, int nd, int64_t ld, const nsrgs_matrix &out,
+                               int row0, int nrows, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  const dim3 grid((unsigned)nrows), block(256);
   switch (out.fmt) {
     case NSRGS_A_BF16:
-      hipLaunchKernelGGL(convert_bf16_kernel, grid, block, 0, s, A32, nd, ld,
-                         (uint16_t *)out.data, (uint16_t *)nullptr);
+      hipLaunchKernelGGL(convert_bf16_kernel, grid, block, 0, s, A32_rows, nd, ld,
+                         (uint16_t *)out.data, (uint16_t *)nullptr, row0);
       break;
     case NSRGS_A_BF16_SPLIT:
-      hipLaunchKernelGGL(convert_bf16_kernel, grid, block, 0, s, A32, nd, ld,
-                         (uint16_t *)out.data, (uint16_t *)out.data_lo);
+      hipLaunchKernelGGL(convert_bf16_kernel, grid, block, 0, s, A32_rows, nd, ld,
+                         (uint16_t *)out.data, (uint16_t *)out.data_lo, row0);
       break;
     case NSRGS_A_FP8_E4M3:
-      hipLaunchKernelGGL(convert_fp8_kernel, grid, block, 0, s, A32, nd, ld,
-                         (uint8_t *)out.data, (float *)out.row_scale);
+      hipLaunchKernelGGL(convert_fp8_kernel, grid, block, 0, s, A32_rows, nd, ld,
+                         (uint8_t *)out.data, (float *)out.row_scale, row0);
       break;
     default:
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_convert(const float *A32, int nd, int64_t ld, const nsrgs_matrix &out,
+                          hipStream_t s) {
+  return launch_convert_rows(A32, nd, ld, out, 0, nd, s);
 }
 
 }  // namespace nsrgs

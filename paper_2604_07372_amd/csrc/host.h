@@ -30,14 +30,15 @@ int env_int(const char *name, int dflt);
 
 // Results of one problem of a batched launch (host copy of device fields).
 struct BatchResult {
-  int iters, converged, nonfinite, panels;
+  int iters, converged, nonfinite, panels, active;
   double rel_change, max_defect;
 };
 
 // Grouped launches: one iteration of many problems per launch (batched.hip).
 struct GroupSpec {
   nsrgs_matrix A;
-  int n, d, iters;
+  int n, d, iters;        // iters: total budget (t counts from the first iteration)
+  int t0;                 // iterations already done; X^t0 is in (t0 even ? X0 : X1)
   void *X0, *X1;          // X^t lives in X0 for even t, X1 for odd t
   void *stats;            // batch_panels(n, d) PanelStat entries
   double mu, tol;

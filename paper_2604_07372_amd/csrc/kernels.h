@@ -75,5 +75,12 @@ hipError_t launch_generate(const double *Z, int n, int d, double sigma,
                            void *A, int64_t ld, hipStream_t stream);
 hipError_t launch_convert(const float *A32, int nd, int64_t ld,
                           const nsrgs_matrix &out, hipStream_t stream);
+// Row-chunk variants: rows [row0, row0 + nrows) of A; A_rows / A32_rows point
+// at row row0 of a buffer holding those rows with leading dimension ld.
+hipError_t launch_generate_rows(const double *Z, int n, int d, double sigma, uint64_t seed,
+                                int zero_diag, double p, int fmt, void *A_rows, int64_t ld,
+                                int row0, int nrows, hipStream_t stream);
+hipError_t launch_convert_rows(const float *A32_rows, int nd, int64_t ld, const nsrgs_matrix &out,
+                               int row0, int nrows, hipStream_t stream);
 
 }  // namespace nsrgs

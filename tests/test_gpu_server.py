@@ -1,0 +1,101 @@
+"""GPU tests of the serving loop (continuous batching, admission by footprint)."""
+import math
+import time
+
+import numpy as np
+import pytest
+
+import paper_2604_07372_amd as P
+import synth
+from oracle import nsrgs as O
+from oracle import quantize as Q
+
+from gpu_common import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _req(n, d, seed, c=0.2):
+    return synth.haar_blocks(n, d, seed), synth.sigma_for(c, n, d), seed + 7
+
+
+def _serve(requests, **kw):
+    require_gpu()
+    with P.Server(**kw) as srv:
+        outs = [srv.submit(Z, sigma, seed, tol=1e-6, max_iters=300) for (Z, sigma, seed) in requests]
+        assert srv.wait_idle(120.0) == 0
+        res = {r["id"]: r for r in srv.poll()}
+        stats = srv.stats()
+    return [(res[i], out) for i, out in outs], stats
+
+
+def test_result_is_the_same_alone_and_in_the_mix():
+    target = _req(300, 3, 41)
+    others = [_req(n, d, 100 + k, c=0.35) for k, (n, d) in
+              enumerate([(3000, 4), (1500, 3), (4000, 3), (2500, 4), (3500, 3)])]
+    (alone, x_alone), = _serve([target], fmt=P.BF16, waves=1)[0]
+    mixed, stats = _serve(others[:3] + [target] + others[3:], fmt=P.BF16, waves=1)
+    r_mix, x_mix = mixed[3]
+    print("alone", alone, "\nmixed", r_mix, "\nstats", stats, flush=True)
+    assert alone["status"] == 0 and r_mix["status"] == 0
+    assert stats["max_active_seen"] >= 2
+    assert alone["iters"] == r_mix["iters"]
+    assert np.array_equal(x_alone, x_mix)
+
+
+@pytest.mark.parametrize("fmt", [P.BF16, P.F32])
+def test_served_result_matches_oracle(fmt):
+    n, d = 400, 3
+    Z, sigma, seed = _req(n, d, 5)
+    [(r, X)], _ = _serve([(Z, sigma, seed)], fmt=fmt)
+    print("served", r, flush=True)
+    assert r["status"] == 0 and r["converged"] == 1
+    A = Q.stored_value(synth.measurement_matrix(Z, sigma, seed), "bf16" if fmt == P.BF16 else "f32")
+    ref = O.solve(A, d, Ts=3, T=300, stop="rel_change", tol=1e-6)
+    e_g, e_o = O.alignment_error(X.astype(np.float64), Z), O.alignment_error(ref.X, Z)
+    print(f"served fmt={fmt}: iters {r['iters']} (oracle {ref.iters}), e {e_g:.6f} vs {e_o:.6f}", flush=True)
+    assert abs(e_g - e_o) <= 1e-4 * e_o
+    assert abs(r["iters"] - ref.iters) <= 3
+
+
+def test_admission_by_footprint_and_oversize_rejection():
+    sizes = [(600, 3)] * 5
+    reqs = [_req(n, d, 200 + k) for k, (n, d) in enumerate(sizes)]
+    one = 1800 * 1808 * 2                                  # one BF16 A
+    pool = int(2.5 * one) + (8 << 20)                      # room for two requests and their buffers
+    big = _req(3000, 3, 300)                               # A alone is larger than the pool
+    res, stats = _serve(reqs + [big], fmt=P.BF16, pool_bytes=pool)
+    statuses = [r["status"] for r, _ in res]
+    print("statuses", statuses, "max active", stats["max_active_seen"], "peak", stats["pool_peak_bytes"], flush=True)
+    assert statuses[:5] == [0] * 5
+    assert statuses[5] == 3
+    assert stats["max_active_seen"] <= 2
+    assert stats["pool_peak_bytes"] <= pool
+    assert stats["completed"] == 5 and stats["rejected"] == 1
+
+
+def test_poisson_arrivals_continuous_batching():
+    """Requests arrive while others iterate; every result is posted, latencies are
+    ordered sensibly and several requests overlap on the device."""
+    require_gpu()
+    rng = np.random.default_rng(3)
+    with P.Server(fmt=P.BF16) as srv:
+        outs = []
+        t = 0.0
+        for k in range(24):
+            n = int(np.exp(rng.uniform(np.log(500), np.log(6000))))
+            d = int(rng.choice([3, 4]))
+            Z, sigma, seed = _req(n, d, 500 + k, c=0.35)
+            t += rng.exponential(1 / 200.0)
+            while srv.clock() < t:
+                time.sleep(0.0005)
+            outs.append(srv.submit(Z, sigma, seed))
+        assert srv.wait_idle(120.0) == 0
+        res = srv.poll()
+        st = srv.stats()
+    assert len(res) == 24 and all(r["status"] in (0, 5) for r in res)
+    assert st["completed"] == 24
+    assert 0 < st["p50_latency_s"] <= st["p99_latency_s"]
+    assert st["max_active_seen"] >= 2
+    for r in res:
+        assert r["t_submit"] <= r["t_admit"] <= r["t_start"] <= r["t_done"]
