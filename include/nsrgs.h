@@ -299,6 +299,12 @@ typedef struct {
 } nsrgs_tune_entry;
 int nsrgs_set_tuning(const nsrgs_tune_entry *entries, int count);
 int nsrgs_get_tuning(nsrgs_tune_entry *entries, int max_count);
+/* The (blocks_per_panel, unroll) shapes of the step kernel compiled for block
+ * size d (the choices a kind-0 tuning entry may name).  Writes up to max_count
+ * pairs into the two caller-owned arrays (either may be NULL when max_count is
+ * 0) and returns the number of shapes for d (0 for a d outside 1..16), or -1
+ * (message in nsrgs_last_error) when max_count > 0 and an array is NULL. */
+int nsrgs_step_variants(int d, int32_t *blocks_per_panel, int32_t *unroll, int max_count);
 
 /* ---- inputs: measurement generator and format conversion ----------------
  * nsrgs_generate_measurement writes A = Z Z^T + sigma W in F64 or F32

@@ -27,7 +27,7 @@ import numpy as np
 
 __all__ = [
     "as_blocks", "sgn", "sgn_blocks", "newton_schulz", "offdiag_product",
-    "euclidean_gradient", "tangent_projection", "rgs_step", "StepResult",
+    "euclidean_gradient", "tangent_projection", "rgs_step", "StepResult", "block_step",
     "spectral_subspace", "spectral_init", "solve", "SolveResult", "objective",
     "partial_objective", "procrustes", "dist_F", "alignment_error", "rel_err",
     "mse", "rel_change", "objective_ratio",
@@ -156,6 +156,30 @@ def rgs_step(A: np.ndarray, X: np.ndarray, d: int, mu: float | None = None,
     defect = np.linalg.norm(eye - np.swapaxes(Fb, -1, -2) @ Fb, axis=(1, 2))
     return StepResult(X=Xn, F=F, G=G, max_orth_defect=float(defect.max()),
                       rel_change=rel_change(Xn, X))
+
+
+def block_step(A_rows_i: np.ndarray, X: np.ndarray, d: int, i: int, mu: float | None = None,
+               Ts: int = 3) -> np.ndarray:
+    """X_i^{t+1} of Algorithm 2 for one block i, from the d rows of A that hold
+    the blocks A_i1, ..., A_in (shape (d, n*d)) and the whole iterate X^t.
+
+    The same steps as ``rgs_step``, written for a single i: the gradient sum
+    over j != i (the full row product minus the diagonal-block term, as in
+    ``offdiag_product``), the pseudo projection, the step and Ts Newton-Schulz
+    steps.  Lets a large problem be checked on sampled blocks.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    Xb = as_blocks(X, d)
+    n = Xb.shape[0]
+    if mu is None:
+        mu = 1.0 / n
+    Ai = np.asarray(A_rows_i, dtype=np.float64)                        # [A_i1 ... A_in]
+    s = slice(i * d, (i + 1) * d)
+    C = Ai @ X - Ai[:, s] @ Xb[i]                                      # sum over j != i
+    G = (n - 1) * Xb[i] - C
+    P = 0.5 * (G - Xb[i] @ G.T @ Xb[i])
+    F = Xb[i] - mu * P
+    return newton_schulz(F, Ts)
 
 
 # ---------------------------------------------------------------------------

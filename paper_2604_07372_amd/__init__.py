@@ -17,6 +17,7 @@ __all__ = [
     "lib", "StoredMatrix", "Workspace", "workspace", "step", "read_info",
     "init_spectral", "solve", "generate", "convert", "stored", "padded_ld",
     "Info", "solve_batched", "batch_rows_per_panel", "set_tuning", "get_tuning", "TuneEntry", "Server",
+    "step_variants",
 ]
 
 F64, F32, BF16, BF16_SPLIT, FP8_E4M3 = 0, 1, 2, 3, 4
@@ -133,6 +134,7 @@ def lib() -> ctypes.CDLL:
         "nsrgs_convert": (i32, [vp, i32, i64, pm, vp]),
         "nsrgs_set_tuning": (i32, [ctypes.POINTER(TuneEntry), i32]),
         "nsrgs_get_tuning": (i32, [ctypes.POINTER(TuneEntry), i32]),
+        "nsrgs_step_variants": (i32, [i32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), i32]),
         "nsrgs_server_create": (i32, [ctypes.POINTER(_ServerOpts), ctypes.POINTER(vp)]),
         "nsrgs_server_submit": (i32, [vp, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_int64)]),
         "nsrgs_server_poll": (i32, [vp, ctypes.POINTER(_Result), i32, ctypes.POINTER(i32)]),
@@ -180,6 +182,16 @@ def get_tuning() -> list:
     arr = (TuneEntry * max(1, n))()
     lib().nsrgs_get_tuning(arr, n)
     return [{k: getattr(arr[i], k) for k, _ in TuneEntry._fields_} for i in range(n)]
+
+
+def step_variants(d: int) -> list:
+    """(blocks_per_panel, unroll) shapes of the step kernel compiled for d."""
+    B = (ctypes.c_int32 * 16)()
+    U = (ctypes.c_int32 * 16)()
+    n = lib().nsrgs_step_variants(int(d), B, U, 16)
+    if n < 0:
+        raise NsrgsError(1, lib().nsrgs_last_error().decode())
+    return [(B[i], U[i]) for i in range(min(n, 16))]
 
 
 def batch_rows_per_panel(d: int) -> int:

@@ -472,6 +472,20 @@ int nsrgs_get_tuning(nsrgs_tune_entry *entries, int max_count) {
   return n;
 }
 
+int nsrgs_step_variants(int d, int32_t *blocks_per_panel, int32_t *unroll, int max_count) {
+  StreamConfig v[16];
+  const int nv = stream_variants(d, v, 16);
+  if (max_count > 0 && (!blocks_per_panel || !unroll)) {
+    fail(NSRGS_ERR_INVALID_ARG, "NULL output arrays");
+    return -1;
+  }
+  for (int i = 0; i < nv && i < max_count; ++i) {
+    blocks_per_panel[i] = v[i].blocks_per_panel;
+    unroll[i] = v[i].unroll;
+  }
+  return nv;
+}
+
 int nsrgs_generate_measurement(const double *Z, int n, int d, double sigma, uint64_t seed,
                                int zero_diag_blocks, double p, int fmt, void *A, int64_t ld,
                                void *stream) {

@@ -39,7 +39,12 @@ constexpr int elem_bytes() {
 
 // Accumulate one column vector [c, c + V) of every panel row.
 // MASK: apply the matrix tail (columns >= nd) and, in mode 0, the exclusion of
-// each row's own diagonal block.
+// each row's own diagonal block.  The masked form has no divergent branch:
+// every load goes to a clamped, in-bounds address and a select zeroes what
+// lies outside, so it may be called with any c >= 0 (c >= nd adds nothing).
+// (Exec-masked loads under this register pressure let the compiler place
+// register copies at the join before the exec mask is restored; the copies
+// then skip the ragged lanes.  Branch-free code leaves no such join.)
 template <int FMT, int D, int R, bool MASK, bool EXCL>
 __device__ __forceinline__ void accum(typename Fmt<FMT>::acc_t (&acc)[R][D],
                                       const char *__restrict__ Ab,
@@ -69,18 +74,26 @@ __device__ __forceinline__ void accum(typename Fmt<FMT>::acc_t (&acc)[R][D],
     }
   } else {
 #pragma unroll
-    for (int v = 0; v < V; ++v)
+    for (int v = 0; v < V; ++v) {
+      const int cv = c + v;
+      const int src = cv < nd ? cv : nd - 1;
 #pragma unroll
-      for (int k = 0; k < D; ++k)
-        xv[v * D + k] = (c + v < nd) ? X[(int64_t)(c + v) * D + k] : T(0);
+      for (int k = 0; k < D; ++k) {
+        const T x = X[(int64_t)src * D + k];
+        xv[v * D + k] = cv < nd ? x : T(0);
+      }
+    }
   }
+  // A rows are padded to whole 16-byte vectors, so a vector that starts below
+  // nd stays inside the row; one that starts at or past nd reads column 0.
+  const int ca = (!MASK || c < nd) ? c : 0;
   uint4 raw[R];
   uint4 rawlo[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    raw[r] = ld16_stream(Ab + rowoff[r] + (int64_t)c * EB);
+    raw[r] = ld16_stream(Ab + rowoff[r] + (int64_t)ca * EB);
     if constexpr (FMT == NSRGS_A_BF16_SPLIT)
-      rawlo[r] = ld16_stream(Alo + rowoff[r] + (int64_t)c * EB);
+      rawlo[r] = ld16_stream(Alo + rowoff[r] + (int64_t)ca * EB);
     else
       rawlo[r] = raw[r];
   }
@@ -209,7 +222,8 @@ __device__ __forceinline__ void panel_compute(const PanelJob &job, char *lds) {
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
-  const int wave = tid / kWave;
+  // wave index, provably uniform: the column-group loops below branch on it
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
   const int nw = blockDim.x / kWave;
   const int nd = job.nd;
   const int row0 = job.panel * R;
@@ -253,7 +267,7 @@ __device__ __forceinline__ void panel_compute(const PanelJob &job, char *lds) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int c = g * GROUP + u * kWave * V + lane * V;
-      if (c < nd) accum<FMT, D, R, true, EXCL>(acc, Ab, Alo, rowoff, X, c, nd, row0);
+      accum<FMT, D, R, true, EXCL>(acc, Ab, Alo, rowoff, X, c, nd, row0);
     }
   }
 

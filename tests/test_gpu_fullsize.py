@@ -1,0 +1,108 @@
+"""Parity at the benchmark's full size (n = 20000, d = 3, A 60000 x 60000), in the
+launch configuration bench.py times: sampled blocks of one sync_step against the
+oracle's single-block step (rows regenerated on the host by the generator's twin),
+for every storage format; plus invariants of a full solve."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2604_07372_amd as P
+import synth
+from oracle import nsrgs as O
+from oracle import quantize as Q
+
+from gpu_common import FMT_NAME, host, require_gpu, step_tolerance
+
+pytestmark = pytest.mark.gpu
+
+N, D, C_NOISE, SEED = 20000, 3, 0.2, 20000
+
+
+@pytest.fixture(scope="module")
+def big():
+    require_gpu()
+    sigma = synth.sigma_for(C_NOISE, N, D)
+    Z = synth.haar_blocks(N, D, SEED)
+    A32 = P.generate(torch.from_numpy(Z).cuda(), sigma, SEED, fmt=P.F32)
+    X = synth.perturbed_start(Z, 0.05, SEED + 1).astype(np.float32)
+    rng = np.random.default_rng(7)
+    blocks = np.unique(np.concatenate([[0, N - 1], rng.choice(N, 30, replace=False)]))
+    rows = (blocks[:, None] * D + np.arange(D)).ravel()
+    print(f"full size: regenerating {len(rows)} rows on the host", flush=True)
+    A_rows = synth.measurement_rows(Z, sigma, SEED, rows)          # float64, host twin
+    yield dict(Z=Z, sigma=sigma, A32=A32, X=X, blocks=blocks, rows=rows, A_rows=A_rows)
+    del A32
+    torch.cuda.empty_cache()
+
+
+def _stored_rows(A_rows, fmt):
+    return Q.stored_value(A_rows, FMT_NAME[fmt])
+
+
+@pytest.mark.parametrize("fmt", [P.F32, P.BF16, P.BF16_SPLIT, P.FP8_E4M3], ids=lambda f: FMT_NAME[f])
+def test_fullsize_step_sampled_blocks(big, fmt):
+    Am = P.stored(big["A32"], P.F32) if fmt == P.F32 else P.convert(big["A32"], fmt)
+    Xin = torch.from_numpy(big["X"]).cuda()
+    Xout = torch.empty_like(Xin)
+    ws = P.workspace(N, D, fmt)
+    P.step(Am, N, D, Xin, Xout, ws)
+    torch.cuda.synchronize()
+    Xo = host(Xout)
+    Xh = big["X"].astype(np.float64)
+    rows_stored = _stored_rows(big["A_rows"], fmt)
+    tol = step_tolerance(rows_stored, Xh, N, fmt)
+    worst = 0.0
+    for k, i in enumerate(big["blocks"]):
+        ref = O.block_step(rows_stored[k * D:(k + 1) * D], Xh, D, int(i), Ts=3)
+        worst = max(worst, float(np.abs(Xo[i * D:(i + 1) * D] - ref).max()))
+    print(f"full size {FMT_NAME[fmt]}: worst sampled-block error {worst:.2e} (bound {tol:.2e})", flush=True)
+    assert worst <= tol
+    assert np.isfinite(Xo).all()
+    del Am
+
+
+def test_fullsize_solve_invariants(big):
+    """A full FP32 solve (spectral init + 200 iterations): orthogonal blocks, the
+    first-order error level, and a stationary point (tangent gradient ~ 0 on
+    sampled blocks)."""
+    Am = P.stored(big["A32"], P.F32)
+    X = torch.empty((N * D, D), dtype=torch.float32, device="cuda")
+    ws = P.workspace(N, D, P.F32)
+    info = P.solve(Am, N, D, X, ws, ns_steps=3, max_iters=200)
+    Xh = host(X)
+    Xb = Xh.reshape(N, D, D)
+    orth = np.abs(Xb @ np.swapaxes(Xb, 1, 2) - np.eye(D)).max()
+    e = O.alignment_error(Xh, big["Z"])
+    pred = big["sigma"] * math.sqrt(D * (D - 1) / (2.0 * N))
+    rows32 = _stored_rows(big["A_rows"], P.F32)
+    worst_tangent = 0.0
+    for k, i in enumerate(big["blocks"]):
+        Ai = rows32[k * D:(k + 1) * D]
+        s = slice(i * D, (i + 1) * D)
+        G = (N - 1) * Xh[s] - (Ai @ Xh - Ai[:, s] @ Xh[s])
+        Pt = 0.5 * (G - Xh[s] @ G.T @ Xh[s])
+        worst_tangent = max(worst_tangent, float(np.abs(Pt).max() / np.abs(G).max()))
+    print(f"full solve: iters {info['iters']} orth {orth:.2e} align {e:.6f} (first order {pred:.6f}) "
+          f"tangent/grad {worst_tangent:.2e}", flush=True)
+    assert info["iters"] == 200
+    assert orth <= 1e-5
+    assert abs(e / pred - 1.0) <= 0.05
+    assert worst_tangent <= 1e-4
+
+
+def test_fullsize_bf16_refined_solve_matches_fp32(big):
+    """BF16 storage with the last 10 iterations on FP32 lands on the FP32 solution."""
+    A32 = P.stored(big["A32"], P.F32)
+    Ab = P.convert(big["A32"], P.BF16)
+    X32 = torch.empty((N * D, D), dtype=torch.float32, device="cuda")
+    Xb = torch.empty_like(X32)
+    P.solve(A32, N, D, X32, P.workspace(N, D, P.F32), max_iters=200)
+    P.solve(Ab, N, D, Xb, P.workspace(N, D, P.BF16), max_iters=200, refine_iters=10, A_refine=A32)
+    d = O.dist_F(host(Xb), host(X32)) / math.sqrt(N)
+    e32 = O.alignment_error(host(X32), big["Z"])
+    eb = O.alignment_error(host(Xb), big["Z"])
+    print(f"bf16+refine vs f32: d_F/sqrt(n) {d:.2e}, align {eb:.8f} vs {e32:.8f}", flush=True)
+    assert abs(eb - e32) <= 1e-4 * e32
+    assert d <= 1e-3

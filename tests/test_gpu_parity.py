@@ -1,4 +1,5 @@
 """GPU parity of the HIP path against the FP64 oracle, through the C ABI."""
+import functools
 import math
 
 import numpy as np
@@ -336,3 +337,49 @@ def test_tolerance_stop_matches_oracle_iteration_count():
     assert info["converged"] == 1
     assert abs(info["iters"] - ref.iters) <= 1
     assert O.dist_F(host(X), ref.X) / math.sqrt(n) <= 1e-6
+
+
+
+@functools.lru_cache(maxsize=None)
+def _variant_problem(d):
+    # nd about 2500 and, unless d is a multiple of 16, not a multiple of 16:
+    # full column groups for the narrow vector widths and a ragged last vector.
+    n = 2500 // d + 1
+    while d % 16 and (n * d) % 16 == 0:
+        n += 1
+    return (n,) + _problem(n, d, seed=500 + d)
+
+
+def _variant_cases():
+    try:
+        shapes = {d: P.step_variants(d) for d in range(1, 17)}
+    except (ImportError, OSError) as e:   # library not built: nothing to enumerate
+        return [pytest.param(0, 0, 0, 0, marks=pytest.mark.skip(reason=str(e)))]
+    cases = []
+    for d, vs in shapes.items():
+        for B, U in vs:
+            for fmt in ALL_FMTS:
+                cases.append(pytest.param(d, B, U, fmt, id=f"d{d}-B{B}-U{U}-{FMT_NAME[fmt]}"))
+    return cases
+
+
+@pytest.mark.parametrize("d,B,U,fmt", _variant_cases())
+def test_every_compiled_variant(d, B, U, fmt, monkeypatch):
+    """Every compiled (B, U) shape of the step kernel, in every storage format,
+    against the oracle at a ragged size.  (Register-heavy shapes once lost the
+    ragged lane's X values to copies placed before the exec-mask restore.)"""
+    require_gpu()
+    monkeypatch.setenv("NSRGS_STEP_B", str(B))
+    monkeypatch.setenv("NSRGS_STEP_U", str(U))
+    n, Z, A64, X = _variant_problem(d)
+    print(f"variant d={d} B={B} U={U} fmt={FMT_NAME[fmt]} n={n}", flush=True)
+    Ad = device_matrix(A64, fmt)
+    As = oracle_matrix(A64, fmt)
+    Xin = to_dev(X, xdtype(fmt))
+    ws = P.workspace(n, d, fmt)
+    Xout = torch.full_like(Xin, float("nan"))
+    P.step(Ad, n, d, Xin, Xout, ws)
+    torch.cuda.synchronize()
+    ref = O.rgs_step(As, host(Xin), d, Ts=3)
+    err = np.abs(host(Xout) - ref.X).max()
+    assert err <= step_tolerance(As, host(Xin), n, fmt), (err, step_tolerance(As, host(Xin), n, fmt))

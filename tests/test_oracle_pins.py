@@ -328,3 +328,14 @@ def test_rel_err_gram_form_and_mse():
     r = O.solve(A, 3, T=30)
     assert abs(O.rel_err(r.X, Z, "gram") - O.rel_err(r.X, Z)) < 1e-9
     assert abs(O.mse(r.X, Z) - O.alignment_error(r.X, Z) ** 2) < 1e-15
+
+
+def test_block_step_equals_whole_step():
+    """The single-block form used for sampled checks equals the whole sweep."""
+    Z, A = _cfg0(seed=4, n=40)
+    d = 3
+    X = synth.perturbed_start(Z, 0.05, 3)
+    full = O.rgs_step(A, X, d, Ts=3).X
+    for i in (0, 17, 39):
+        got = O.block_step(A[i * d:(i + 1) * d], X, d, i, Ts=3)
+        assert np.abs(got - full[i * d:(i + 1) * d]).max() < 1e-13
