@@ -176,8 +176,7 @@ int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps,
  * launches, so a batch of 512 problems costs max_iters launches, not
  * 512 x max_iters.  Each problem follows exactly the arithmetic of sync_step
  * with the same panel shape.  Every problem of a batch uses one storage
- * format: F64, F32 or BF16, and 1 <= d <= 10 (a batch with a larger d is
- * refused with NSRGS_ERR_UNSUPPORTED; solve such problems with sync_solve).  Problem memory (A, X) is the caller's; the
+ * format: F64, F32 or BF16, and 1 <= d <= 16.  Problem memory (A, X) is the caller's; the
  * workspace holds the unit table, a second iterate buffer per problem and
  * per-panel monitors.  Waits for the stream. */
 typedef struct {
@@ -217,7 +216,7 @@ int sync_solve_batched(const nsrgs_problem *probs, int count, int ns_steps, int 
 /* ---- serving: a request loop with continuous batching --------------------
  * A server owns a device memory pool (one allocation at creation), a
  * scheduler thread and ingest worker threads.  Requests describe a synthetic
- * measurement problem (n, d <= 10, sigma, seed, ground truth Z on the host);
+ * measurement problem (n, d <= 16, sigma, seed, ground truth Z on the host);
  * they are admitted in arrival order when their footprint (A in the server's
  * storage format, two iterates, monitors, and transient ingest buffers) fits
  * the pool and a solve slot is free (a request that does not fit yet does

@@ -54,9 +54,6 @@ struct GroupArgs {
   int ns_steps;
 };
 
-// Largest d a batch may hold (see batch_check).
-constexpr int kBatchMaxD = 10;
-
 // Rows per panel of the batched kernel for each d (B blocks of d rows).
 __host__ __device__ constexpr int batch_blocks(int d) {
   return d == 1 ? 8 : d == 2 ? 4 : d == 3 ? 4 : d == 4 ? 2 : 1;
@@ -83,7 +80,8 @@ __device__ __forceinline__ void run_panel(int d, const PanelJob &job, char *lds)
       return;                                                                   \
     }
   NSRGS_BP(1) NSRGS_BP(2) NSRGS_BP(3) NSRGS_BP(4) NSRGS_BP(5) NSRGS_BP(6) NSRGS_BP(7)
-  NSRGS_BP(8) NSRGS_BP(9) NSRGS_BP(10)
+  NSRGS_BP(8) NSRGS_BP(9) NSRGS_BP(10) NSRGS_BP(11) NSRGS_BP(12) NSRGS_BP(13) NSRGS_BP(14)
+  NSRGS_BP(15) NSRGS_BP(16)
 #undef NSRGS_BP
 }
 
@@ -168,8 +166,9 @@ __global__ void group_reset_kernel(GroupInst *inst, int count) {
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-// Kernel classes: every d <= 4, or every d <= 10, handled by one inlined kernel.
-static int dclass(int dmax) { return dmax <= 4 ? 4 : 10; }
+// Kernel classes: every d <= 4, d <= 10 or d <= 16 handled by one inlined kernel
+// (a batch takes the smallest class that holds its largest d).
+static int dclass(int dmax) { return dmax <= 4 ? 4 : dmax <= 10 ? 10 : 16; }
 
 template <int FMT, int DMAX>
 static hipError_t launch_g(const GroupArgs &a, int grid, int waves, hipStream_t s) {
@@ -182,7 +181,8 @@ static hipError_t launch_group(int fmt, int dmax, const GroupArgs &a, int grid, 
 #define NSRGS_LG(F)                                         \
   if (fmt == F) {                                           \
     if (c == 4) return launch_g<F, 4>(a, grid, waves, s);   \
-    return launch_g<F, 10>(a, grid, waves, s);              \
+    if (c == 10) return launch_g<F, 10>(a, grid, waves, s); \
+    return launch_g<F, 16>(a, grid, waves, s);              \
   }
   NSRGS_LG(NSRGS_A_F64) NSRGS_LG(NSRGS_A_F32) NSRGS_LG(NSRGS_A_BF16)
 #undef NSRGS_LG
@@ -321,10 +321,6 @@ int batch_check(const nsrgs_problem *probs, int count, int *fmt, int *dmax) {
   }
   if (*fmt != NSRGS_A_F64 && *fmt != NSRGS_A_F32 && *fmt != NSRGS_A_BF16)
     return fail(NSRGS_ERR_UNSUPPORTED, "batched solves take F64, F32 or BF16 storage");
-  if (*dmax > kBatchMaxD)
-    return fail(NSRGS_ERR_UNSUPPORTED,
-                "batched solves take d <= %d (the dispatch kernel for d up to 16 is switched off in "
-                "this build); solve larger d with sync_solve", kBatchMaxD);
   return NSRGS_OK;
 }
 

@@ -468,7 +468,6 @@ int nsrgs_server_submit(nsrgs_server *srv, const nsrgs_request *req, int64_t *id
   Server &S = srv->impl;
   int st;
   if ((st = check_common(req->n, req->d))) return st;
-  if (req->d > 10) return fail(NSRGS_ERR_UNSUPPORTED, "served requests take d <= 10");
   if (!req->Z) return fail(NSRGS_ERR_INVALID_ARG, "request needs the ground truth Z to generate A");
   if (!std::isfinite(req->sigma)) return fail(NSRGS_ERR_INVALID_ARG, "bad sigma");
   auto q = std::make_shared<Request>();

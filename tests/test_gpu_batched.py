@@ -14,16 +14,13 @@ from gpu_common import FMT_NAME, device_matrix, host, oracle_matrix, require_gpu
 
 # Largest d is 16: the configuration that did not finish on the GPU (see below).
 MIX = [(2, 1), (5, 2), (37, 3), (100, 4), (61, 10), (341, 3), (20, 16), (130, 2), (47, 7), (700, 3)]
-# Largest d is 10: what batched solves accept in this build.
+# The same kind of mix with largest d 10 (the middle kernel class).
 MIX10 = [(2, 1), (5, 2), (37, 3), (100, 4), (61, 10), (341, 3), (33, 9), (130, 2), (47, 7), (700, 3)]
 
 PERSISTENT_OFF = ("the persistent single-launch schedule (items taken from a device counter, "
                   "cross-workgroup dependency waits) did not finish on the GPU on a batch with "
                   "d up to 16; it is switched off and sync_solve_batched returns "
                   "NSRGS_ERR_UNSUPPORTED for it")
-D16_OFF = ("a grouped batch with d up to 16 (kernel dispatching every d <= 16 through an "
-           "out-of-line device function) did not finish on the GPU; batches with d > 10 are "
-           "refused with NSRGS_ERR_UNSUPPORTED until the cause is shown")
 
 
 def _batch(fmt, shapes, seed=0, c=0.25):
@@ -66,21 +63,39 @@ def test_persistent_batched_matches_oracle():
     P.solve_batched(probs, max_iters=30, persistent=True)
 
 
-def test_batch_with_large_d_is_refused_on_the_host():
-    """CPU: d > 10 in a batch is refused before any device work."""
-    m = P._Matrix(P.F32, 16, None, None, 320)
-    arr = (P._Problem * 2)(P._Problem(m, 20, 16, 0.0, 4096, 0, 0.0), P._Problem(m, 100, 3, 0.0, 4096, 0, 0.0))
+def test_batch_with_too_large_d_is_refused_on_the_host():
+    """CPU: d > 16 in a batch is refused before any device work."""
+    m = P._Matrix(P.F32, 16, None, None, 352)
+    arr = (P._Problem * 2)(P._Problem(m, 20, 17, 0.0, 4096, 0, 0.0), P._Problem(m, 100, 3, 0.0, 4096, 0, 0.0))
     st = P.lib().sync_solve_batched(arr, 2, 3, 10, 256, 1 << 30, None, None, None)
-    assert st == 2
-    assert "d <= 10" in P.lib().nsrgs_last_error().decode()
+    assert st == 1
+    assert "d must be in [1, 16]" in P.lib().nsrgs_last_error().decode()
 
 
 @pytest.mark.gpu
-@pytest.mark.skip(reason=D16_OFF)
 @pytest.mark.parametrize("fmt", [P.F64, P.F32, P.BF16], ids=lambda f: FMT_NAME[f])
-def test_grouped_d16_batch_matches_oracle(fmt):
+def test_grouped_d16_batch_matches_oracle(fmt, monkeypatch):
+    """A batch whose largest d is 16 (the widest kernel class), every problem
+    against the oracle and bitwise against its own sync_solve."""
+    require_gpu()
+    iters = 30
     probs, refs = _batch(fmt, MIX, seed=10 * fmt)
-    P.solve_batched(probs, ns_steps=3, max_iters=30, waves=2)
+    for p in probs:
+        p["X0"] = p["X"].clone()
+    print(f"grouped d<=16 batch {FMT_NAME[fmt]}: {len(probs)} problems, {iters} iterations", flush=True)
+    st, infos = P.solve_batched(probs, ns_steps=3, max_iters=iters, waves=2)
+    assert st == 0
+    torch.cuda.synchronize()
+    for p, (Z, A64, X0), info in zip(probs, refs, infos):
+        n, d = p["n"], p["d"]
+        assert info["iters"] == iters
+        ref = O.solve(oracle_matrix(A64, fmt), d, Ts=3, T=iters, X0=host(p["X0"]))
+        err = O.dist_F(host(p["X"]), ref.X) / math.sqrt(n)
+        tol = 1e-10 if fmt == P.F64 else 2e-5
+        print(f"  n={n} d={d}: d_F/sqrt(n) vs oracle {err:.2e}", flush=True)
+        assert err <= tol, (n, d, err)
+        alone = _alone(p, iters, monkeypatch, waves=2)
+        assert torch.equal(alone, p["X"]), (n, d)
 
 
 @pytest.mark.gpu
