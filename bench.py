@@ -85,8 +85,8 @@ def batched_bench(iters: int = 100, base_iters: int = 10, count: int = 512, seed
     """512 independent problems: n log-uniform in [50, 3000], d uniform in
     {2, 3, 4, 10}, sigma = 0.2 sqrt(n/d), dense FP32 A generated on the device.
     Times `iters` iterations through grouped launches (one launch per iteration
-    for all problems) and `base_iters` iterations as one sync_step launch per
-    problem per iteration.  Every problem starts from its ground truth with a
+    for all problems), the same through one persistent launch, and `base_iters`
+    iterations as one sync_step launch per problem per iteration.  Every problem starts from its ground truth with a
     0.05 perturbation (the initialization is not part of the timed loop)."""
     import numpy as np
     import torch
@@ -112,6 +112,18 @@ def batched_bench(iters: int = 100, base_iters: int = 10, count: int = 512, seed
     st, infos = P.solve_batched(probs, ns_steps=3, max_iters=iters)
     torch.cuda.synchronize()
     t_group = time.perf_counter() - t0
+    X_group = [p["X"].clone() for p in probs]
+    for p in probs:
+        p["X"].copy_(p["X0"])
+    P.solve_batched(probs, max_iters=2, persistent=True)        # warm-up
+    for p in probs:
+        p["X"].copy_(p["X0"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_p, infos_p = P.solve_batched(probs, ns_steps=3, max_iters=iters, persistent=True)
+    torch.cuda.synchronize()
+    t_pers = time.perf_counter() - t0
+    same = all(torch.equal(p["X"], x) for p, x in zip(probs, X_group))
     wss = [P.workspace(p["n"], p["d"], P.F32) for p in probs]
     outs = [torch.empty_like(p["X0"]) for p in probs]
     for p, w, o in zip(probs, wss, outs):
@@ -126,10 +138,15 @@ def batched_bench(iters: int = 100, base_iters: int = 10, count: int = 512, seed
     res = {"problems": count, "iters": iters, "a_bytes_per_iter": a_bytes,
            "grouped_s": t_group, "grouped_problem_iters_per_s": count * iters / t_group,
            "grouped_GBps": a_bytes * iters / t_group / 1e9,
+           "persistent_s": t_pers, "persistent_problem_iters_per_s": count * iters / t_pers,
+           "persistent_GBps": a_bytes * iters / t_pers / 1e9, "persistent_status": st_p,
+           "persistent_equals_grouped": same,
            "per_problem_launch_s_scaled": t_base,
            "per_problem_launch_problem_iters_per_s": count * iters / t_base,
            "speedup_vs_per_problem_launches": t_base / t_group,
            "status": st, "all_iters_done": all(i["iters"] == iters for i in infos)}
+    print(f"[bench] batched: persistent {t_pers:.3f} s ({res['persistent_GBps']:.0f} GB/s), "
+          f"bitwise equal to grouped: {same}", file=sys.stderr, flush=True)
     print(f"[bench] batched: grouped {t_group:.3f} s ({res['grouped_GBps']:.0f} GB/s), per-problem launches "
           f"{t_base:.3f} s -> {res['speedup_vs_per_problem_launches']:.2f}x", file=sys.stderr, flush=True)
     del probs, wss, outs

@@ -167,15 +167,20 @@ int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps,
                void *stream, const nsrgs_solve_opts *opts, nsrgs_info *info);
 
 /* ---- batched solves: many problems per launch -----------------------------
- * Independent problems of uneven size (n, d) share every launch: one grouped
- * launch runs one iteration of Algorithm 2 for all still-active problems
- * (each workgroup one panel of B d rows of one problem, B fixed per d), and
- * the last panel of each problem to finish updates that problem's iteration
- * count, monitors and stop state on the device.  The host enqueues the
- * launches back to back and looks at the state only every opts->check_every
- * launches, so a batch of 512 problems costs max_iters launches, not
- * 512 x max_iters.  Each problem follows exactly the arithmetic of sync_step
- * with the same panel shape.  Every problem of a batch uses one storage
+ * Independent problems of uneven size (n, d) share every launch.  The unit of
+ * work is one panel of B d rows of one problem (B fixed per d); the last panel
+ * of each problem to finish an iteration updates that problem's iteration
+ * count, monitors and stop state on the device.  Two schedules:
+ *   grouped (default): one launch runs one iteration of Algorithm 2 for all
+ *     still-active problems; the host enqueues the launches back to back and
+ *     looks at the state only every opts->check_every launches, so a batch of
+ *     512 problems costs max_iters launches, not 512 x max_iters;
+ *   persistent (opts->persistent = 1): one launch runs the whole budget;
+ *     workgroups take (iteration, unit) tickets in order from a device counter
+ *     and wait on the device until the problem has finished the previous
+ *     iteration, so a problem's next iteration overlaps the tail of others.
+ * Each problem follows exactly the arithmetic of sync_step with the same
+ * panel shape, in either schedule.  Every problem of a batch uses one storage
  * format: F64, F32 or BF16, and 1 <= d <= 16.  Problem memory (A, X) is the caller's; the
  * workspace holds the unit table, a second iterate buffer per problem and
  * per-panel monitors.  Waits for the stream. */
@@ -202,8 +207,15 @@ typedef struct {
   int32_t init;            /* 1: spectral initialization of each problem first    */
   int32_t check_every;     /* launches between host looks at the state
                               [0: 8 if some tol > 0, else max_iters]              */
-  int32_t persistent;      /* 1: ask for a single persistent launch; this build
-                              returns NSRGS_ERR_UNSUPPORTED [0]                   */
+  int32_t persistent;      /* 1: one persistent launch for the whole budget
+                              (workgroups take (iteration, unit) tickets in order
+                              and wait only on earlier tickets); 0: one grouped
+                              launch per iteration [0]                            */
+  int32_t wait_polls;      /* persistent: polls per dependency wait before the
+                              launch is abandoned with NSRGS_ERR_DEVICE
+                              [0: about 2^21, a few seconds]                      */
+  int32_t ticket_kb;       /* persistent: panels of a problem are merged into
+                              tickets of at least this many KiB of A [0: 512]     */
 } nsrgs_batch_opts;
 
 /* Workspace bytes for a batch (with_init: include the initialization's). */

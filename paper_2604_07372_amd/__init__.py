@@ -70,7 +70,8 @@ class _ProblemInfo(ctypes.Structure):
 
 class _BatchOpts(ctypes.Structure):
     _fields_ = [("waves", ctypes.c_int32), ("order", ctypes.c_int32), ("init", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("persistent", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("wait_polls", ctypes.c_int32), ("ticket_kb", ctypes.c_int32)]
 
 
 class TuneEntry(ctypes.Structure):
@@ -368,8 +369,10 @@ def convert(A32: torch.Tensor, fmt: int) -> StoredMatrix:
 
 
 def solve_batched(problems, ns_steps: int = 3, max_iters: int = 100, init: bool = False, waves: int = 0,
-                  order: int = 0, check_every: int = 0, persistent: bool = False, check: bool = True):
-    """Many problems in one persistent launch (sync_solve_batched).
+                  order: int = 0, check_every: int = 0, persistent: bool = False, wait_polls: int = 0,
+                  ticket_kb: int = 0, check: bool = True):
+    """Many problems per launch (sync_solve_batched): one grouped launch per
+    iteration, or with persistent=True one launch for the whole budget.
 
     problems: sequence of dicts with keys A (StoredMatrix), n, d, X (device tensor,
     X^0 on entry unless init, result on return) and optional mu, iters, tol.
@@ -385,7 +388,8 @@ def solve_batched(problems, ns_steps: int = 3, max_iters: int = 100, init: bool 
         _check(1)
     buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=problems[0]["X"].device)
     off = (-buf.data_ptr()) % 256
-    opts = _BatchOpts(int(waves), int(order), int(init), int(check_every), int(persistent))
+    opts = _BatchOpts(int(waves), int(order), int(init), int(check_every), int(persistent), int(wait_polls),
+                      int(ticket_kb))
     infos = (_ProblemInfo * count)()
     st = lib().sync_solve_batched(arr, count, int(ns_steps), int(max_iters), buf.data_ptr() + off, nbytes,
                                   _stream(), ctypes.byref(opts), infos)

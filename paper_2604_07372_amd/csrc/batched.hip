@@ -1,15 +1,23 @@
 // Many independent NS-RGS problems of uneven size (n, d) per launch.
 //
-// One launch runs one iteration of every active problem: each workgroup takes
-// one (problem, panel) unit of a unit table, runs the same per-panel work as
-// sync_step (stream the panel's rows of A, fused Riemannian step and
-// Newton-Schulz retraction) and the last panel of each problem to arrive
+// Work unit: one (problem, panel) pair.  A workgroup runs the same per-panel
+// work as sync_step (stream the panel's rows of A, fused Riemannian step and
+// Newton-Schulz retraction), and the last panel of each problem to arrive
 // reduces that problem's monitors, advances its iteration counter and applies
-// its stop rule (tolerance, budget, non-finite).  The iteration barrier of
-// each problem is the launch boundary; no workgroup ever waits for another, so
-// the host can enqueue a whole budget of launches without synchronizing.
-// Problems that have stopped keep their units in the table; those workgroups
-// return at once.
+// its stop rule (tolerance, budget, non-finite).  Two schedules:
+//
+// * grouped: one launch per iteration over every unit.  The iteration barrier
+//   of each problem is the launch boundary; no workgroup waits for another,
+//   so the host enqueues a whole budget of launches without synchronizing.
+// * persistent: one launch for the whole budget.  Workgroups take tickets
+//   from one counter; ticket k is round k / U of unit k mod U (U units per
+//   round), so tickets go out round by round.  Before computing round r of a
+//   problem, a workgroup waits until that problem has published iteration
+//   t0 + r (or has stopped).  Every ticket it can wait on was handed out
+//   earlier, to a workgroup that is already running, so by induction on r
+//   every wait ends whatever the number of resident workgroups.  Each wait is
+//   also bounded: after `wait_polls` polls it raises a launch-wide abort flag,
+//   every other wait then gives up at once, and the grid drains.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -29,7 +37,7 @@ struct GroupInst {
   PanelStat *stats;       // one per panel
   int n, d, nd, panels;
   int iters;              // iteration budget
-  int pad0;
+  int t0;                 // iterations done before this launch sequence (static)
   double mu;
   double tol;             // > 0: stop after the first iteration with rel. change <= tol
   // kept by the device
@@ -43,15 +51,45 @@ struct GroupInst {
   double max_defect;
 };
 
+// Work unit: panels [panel, panel + npanels) of problem inst (grouped
+// launches use npanels = 1; persistent tickets merge small panels).
 struct GroupUnit {
   int inst;
   int panel;
+  int npanels;
+  int pad;
 };
 
 struct GroupArgs {
   GroupInst *inst;
   const GroupUnit *units;
   int ns_steps;
+};
+
+// Control words of the persistent schedule (zeroed before the launch).
+struct alignas(256) PersistCtl {
+  unsigned next;          // next ticket
+  int abort;              // a dependency wait ran out of polls
+  int pad[62];
+};
+
+// Polls per dependency wait before a persistent launch gives up (each poll
+// sleeps ~500 cycles, so about 2^21 polls is a few seconds: far longer than
+// one iteration of any problem that fits in memory).
+constexpr unsigned kDefaultWaitPolls = 1u << 21;
+// Smallest amount of A per persistent ticket: panels of small problems are
+// merged so that the per-ticket overhead (one device-wide atomic, one poll,
+// two fences) stays small against the streaming time.
+constexpr int kDefaultTicketKiB = 512;
+
+struct PersistArgs {
+  GroupInst *inst;
+  const GroupUnit *units;
+  int nunits;             // units per round
+  int rounds;             // rounds of tickets (largest remaining budget)
+  int ns_steps;
+  unsigned wait_polls;    // polls per dependency wait before the launch aborts
+  PersistCtl *pc;
 };
 
 // Rows per panel of the batched kernel for each d (B blocks of d rows).
@@ -85,8 +123,12 @@ __device__ __forceinline__ void run_panel(int d, const PanelJob &job, char *lds)
 #undef NSRGS_BP
 }
 
-// Last panel of problem I in this launch: monitors, iteration counter, stop rule.
-__device__ inline void finish_problem(GroupInst &I, double *s_scr) {
+// Last panel of problem I to arrive for the iteration that ends with t_new
+// iterations done: monitors, iteration counter, stop rule.  PUBLISH (the
+// persistent schedule) writes the stop state first and then releases t, so a
+// workgroup that acquires the new t also sees whether the problem stopped.
+template <bool PUBLISH>
+__device__ inline void finish_problem(GroupInst &I, double *s_scr, int t_new) {
   const int tid = threadIdx.x;
   double a = 0.0, b = 0.0, m = 0.0, f = 0.0;
   for (int p = tid; p < I.panels; p += blockDim.x) {
@@ -104,17 +146,25 @@ __device__ inline void finish_problem(GroupInst &I, double *s_scr) {
     const double rel = b > 0.0 ? sqrt(a / b) : 0.0;
     I.rel_change = rel;
     I.max_defect = m;
-    I.t = I.t + 1;
+    int act = 1;
     if (f != 0.0 || !isfinite(rel)) {
       I.nonfinite = 1;
-      I.active = 0;
+      act = 0;
     } else if (I.tol > 0.0 && rel <= I.tol) {
       I.converged = 1;
-      I.active = 0;
-    } else if (I.t >= I.iters) {
-      I.active = 0;
+      act = 0;
+    } else if (t_new >= I.iters) {
+      act = 0;
     }
-    I.arrive = 0u;
+    if constexpr (PUBLISH) {
+      __hip_atomic_store(&I.arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&I.active, act, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&I.t, t_new, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      I.arrive = 0u;
+      I.active = act;
+      I.t = t_new;
+    }
   }
 }
 
@@ -147,7 +197,92 @@ __global__ void __launch_bounds__(kWave * kMaxWaves) grouped_kernel(GroupArgs ar
   __syncthreads();
   if (s_last) {
     __threadfence();
-    finish_problem(I, s_scr);
+    finish_problem<false>(I, s_scr, t + 1);
+  }
+}
+
+// Persistent schedule: one launch for the whole budget (see the top of the file).
+// Thread 0 fetches the next ticket while the current one is computed; a
+// workgroup's prefetched ticket is always larger than its current one, so the
+// induction over tickets that makes every wait end still holds.
+template <int FMT, int DMAX>
+__global__ void __launch_bounds__(kWave * kMaxWaves) persistent_kernel(PersistArgs args) {
+  __shared__ double s_scr[kMaxWaves];
+  __shared__ unsigned s_ticket;
+  __shared__ int s_go, s_last;
+  __shared__ __attribute__((aligned(16))) char lds[batch_lds_bytes<FMT, DMAX>()];
+  const unsigned total = (unsigned)args.nunits * (unsigned)args.rounds;
+  unsigned next = 0;
+  if (threadIdx.x == 0) next = atomicAdd(&args.pc->next, 1u);
+  for (;;) {
+    if (threadIdx.x == 0) s_ticket = next;
+    __syncthreads();
+    const unsigned tk = s_ticket;
+    __syncthreads();                                  // s_ticket is rewritten next time round
+    if (tk >= total) break;                           // uniform
+    if (threadIdx.x == 0) next = atomicAdd(&args.pc->next, 1u);   // consumed next time round
+    const int round = (int)(tk / (unsigned)args.nunits);
+    const GroupUnit unit = args.units[tk % (unsigned)args.nunits];
+    GroupInst &I = args.inst[unit.inst];
+    const int t = I.t0 + round;                       // the iteration this ticket computes
+    if (t >= I.iters) continue;                       // past this problem's budget (uniform)
+    if (threadIdx.x == 0) {
+      // Wait for iteration t - 1 of this problem to be published, or for it to stop.
+      int go = 0;
+      for (unsigned poll = 0;; ++poll) {
+        const int done = __hip_atomic_load(&I.t, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const int act = __hip_atomic_load(&I.active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!act) break;                              // stopped: nothing left to compute
+        if (done >= t) {
+          go = 1;
+          break;
+        }
+        if (__hip_atomic_load(&args.pc->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        if (poll >= args.wait_polls) {
+          __hip_atomic_store(&args.pc->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(8);
+      }
+      s_go = go;
+    }
+    __syncthreads();
+    const int go = s_go;
+    if (!go) continue;                                // uniform; s_go is rewritten after two barriers
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // X^t written by other workgroups
+    PanelJob job;
+    job.A = I.A;
+    job.A_lo = I.A_lo;
+    job.scale = I.scale;
+    job.ld = I.ld;
+    job.X_in = I.X[t & 1];
+    job.X_out = I.X[(t + 1) & 1];
+    job.n = I.n;
+    job.nd = I.nd;
+    job.mu = I.mu;
+    job.ns_steps = args.ns_steps;
+    job.gram = nullptr;
+    for (int q = 0; q < unit.npanels; ++q) {
+      job.panel = unit.panel + q;
+      job.stat = I.stats + job.panel;
+      run_panel<FMT, DMAX>(I.d, job, lds);            // ends with a barrier
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // this ticket's X^{t+1} rows and monitors
+    if (threadIdx.x == 0)
+      s_last = (atomicAdd(&I.arrive, (unsigned)unit.npanels) + (unsigned)unit.npanels == (unsigned)I.panels);
+    __syncthreads();
+    if (s_last) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every panel's monitors
+      finish_problem<true>(I, s_scr, t + 1);
+    }
+    __syncthreads();                                  // s_last and LDS are reused next time round
+  }
+}
+
+__global__ void persist_reset_kernel(PersistCtl *pc) {
+  if (threadIdx.x == 0) {
+    pc->next = 0u;
+    pc->abort = 0;
   }
 }
 
@@ -189,6 +324,36 @@ static hipError_t launch_group(int fmt, int dmax, const GroupArgs &a, int grid, 
   return hipErrorInvalidValue;
 }
 
+// Persistent launch: as many workgroups as fit on the device at once (more
+// would only wait for a slot; fewer leave CUs idle), at most one per ticket.
+template <int FMT, int DMAX>
+static hipError_t launch_p(const PersistArgs &a, int waves, hipStream_t s) {
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<FMT, DMAX>, kWave * waves, 0);
+  if (e != hipSuccess) return e;
+  const long long tickets = (long long)a.nunits * a.rounds;
+  long long grid = (long long)std::max(1, cus) * std::max(1, per_cu);
+  grid = std::max(1LL, std::min(grid, tickets));
+  hipLaunchKernelGGL((persistent_kernel<FMT, DMAX>), dim3((unsigned)grid), dim3(kWave * waves), 0, s, a);
+  return hipGetLastError();
+}
+
+static hipError_t launch_persistent(int fmt, int dmax, const PersistArgs &a, int waves, hipStream_t s) {
+  const int c = dclass(dmax);
+#define NSRGS_LP(F)                                         \
+  if (fmt == F) {                                           \
+    if (c == 4) return launch_p<F, 4>(a, waves, s);         \
+    if (c == 10) return launch_p<F, 10>(a, waves, s);       \
+    return launch_p<F, 16>(a, waves, s);                    \
+  }
+  NSRGS_LP(NSRGS_A_F64) NSRGS_LP(NSRGS_A_F32) NSRGS_LP(NSRGS_A_BF16)
+#undef NSRGS_LP
+  return hipErrorInvalidValue;
+}
+
 int batch_rows_per_panel(int d) { return batch_blocks(d) * d; }
 
 int batch_panels(int n, int d) {
@@ -197,38 +362,49 @@ int batch_panels(int n, int d) {
 }
 
 // Unit order: 0 = problem-major, largest problems first (their long panels
-// start earliest); 1 = panels of all problems interleaved.
-static void build_units(const int *panels, int count, int order, std::vector<GroupUnit> &units) {
+// start earliest); 1 = units of all problems interleaved.  chunk[k] panels of
+// problem k form one unit (the last unit of a problem may hold fewer).
+static void build_units(const int *panels, const int *chunk, int count, int order,
+                        std::vector<GroupUnit> &units) {
   units.clear();
+  auto add = [&](int k, int p) { units.push_back(GroupUnit{k, p, std::min(chunk[k], panels[k] - p), 0}); };
   if (order == 1) {
-    int maxp = 0;
-    for (int k = 0; k < count; ++k) maxp = std::max(maxp, panels[k]);
-    for (int p = 0; p < maxp; ++p)
+    int maxu = 0;
+    for (int k = 0; k < count; ++k) maxu = std::max(maxu, (panels[k] + chunk[k] - 1) / chunk[k]);
+    for (int u = 0; u < maxu; ++u)
       for (int k = 0; k < count; ++k)
-        if (p < panels[k]) units.push_back(GroupUnit{k, p});
+        if (u * chunk[k] < panels[k]) add(k, u * chunk[k]);
   } else {
     std::vector<int> idx(count);
     for (int k = 0; k < count; ++k) idx[k] = k;
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return panels[a] > panels[b]; });
     for (int k : idx)
-      for (int p = 0; p < panels[k]; ++p) units.push_back(GroupUnit{k, p});
+      for (int p = 0; p < panels[k]; p += chunk[k]) add(k, p);
   }
 }
 
 size_t group_control_bytes(int count, size_t units) {
-  return align256((size_t)count * sizeof(GroupInst)) + align256(units * sizeof(GroupUnit));
+  return align256((size_t)count * sizeof(GroupInst)) + align256(units * sizeof(GroupUnit)) +
+         sizeof(PersistCtl);
 }
 
-// Upload descriptors (problem k resumes at iteration specs[k].t0, its
-// iterate in X[t0 & 1]), then up to `launches` grouped launches (every
-// `check_every` launches the descriptors are read back and the loop ends early
-// once no problem is active).  Reads the final state into `out`.
-int run_grouped(int fmt, const std::vector<GroupSpec> &specs, void *ctl, int launches, int ns_steps,
-                int waves, int order, int check_every, hipStream_t s, std::vector<BatchResult> &out) {
-  const int count = (int)specs.size();
+// Problem descriptors and the unit table of one batch, uploaded to the
+// control area (problem k resumes at iteration specs[k].t0 with its iterate in
+// X[t0 & 1]); device state reset.
+struct BatchDev {
+  std::vector<GroupInst> host;
+  std::vector<GroupUnit> units;
+  GroupInst *dinst = nullptr;
+  GroupUnit *dunits = nullptr;
+  PersistCtl *pc = nullptr;
   int dmax = 0;
-  std::vector<GroupInst> host(count);
-  std::vector<int> panels(count);
+};
+
+static int upload_batch(const std::vector<GroupSpec> &specs, void *ctl, int order, size_t min_unit_bytes,
+                        hipStream_t s, BatchDev &B) {
+  const int count = (int)specs.size();
+  B.host.assign(count, GroupInst{});
+  std::vector<int> panels(count), chunk(count, 1);
   for (int k = 0; k < count; ++k) {
     const GroupSpec &g = specs[k];
     GroupInst I{};
@@ -244,25 +420,59 @@ int run_grouped(int fmt, const std::vector<GroupSpec> &specs, void *ctl, int lau
     I.nd = g.n * g.d;
     I.panels = batch_panels(g.n, g.d);
     I.iters = g.iters;
+    I.t0 = g.t0;
     I.t = g.t0;
     I.mu = g.mu > 0.0 ? g.mu : 1.0 / g.n;
     I.tol = g.tol;
-    host[k] = I;
+    B.host[k] = I;
     panels[k] = I.panels;
-    dmax = std::max(dmax, g.d);
+    if (min_unit_bytes > 0) {
+      const size_t panel_bytes = (size_t)batch_rows_per_panel(g.d) * I.nd * elem_size(g.A.fmt);
+      chunk[k] = (int)std::min<size_t>((size_t)I.panels, std::max<size_t>(1, (min_unit_bytes + panel_bytes - 1) / panel_bytes));
+    }
+    B.dmax = std::max(B.dmax, g.d);
   }
-  std::vector<GroupUnit> units;
-  build_units(panels.data(), count, order, units);
+  build_units(panels.data(), chunk.data(), count, order, B.units);
   char *base = static_cast<char *>(ctl);
-  GroupInst *dinst = reinterpret_cast<GroupInst *>(base);
-  GroupUnit *dunits = reinterpret_cast<GroupUnit *>(base + align256((size_t)count * sizeof(GroupInst)));
-  NSRGS_HIP(hipMemcpyAsync(dinst, host.data(), host.size() * sizeof(GroupInst), hipMemcpyHostToDevice, s),
+  B.dinst = reinterpret_cast<GroupInst *>(base);
+  B.dunits = reinterpret_cast<GroupUnit *>(base + align256((size_t)count * sizeof(GroupInst)));
+  B.pc = reinterpret_cast<PersistCtl *>(base + align256((size_t)count * sizeof(GroupInst)) +
+                                        align256(B.units.size() * sizeof(GroupUnit)));
+  NSRGS_HIP(hipMemcpyAsync(B.dinst, B.host.data(), B.host.size() * sizeof(GroupInst), hipMemcpyHostToDevice, s),
             "batch descriptors");
-  NSRGS_HIP(hipMemcpyAsync(dunits, units.data(), units.size() * sizeof(GroupUnit), hipMemcpyHostToDevice, s),
+  NSRGS_HIP(hipMemcpyAsync(B.dunits, B.units.data(), B.units.size() * sizeof(GroupUnit), hipMemcpyHostToDevice, s),
             "batch units");
-  hipLaunchKernelGGL(group_reset_kernel, dim3((count + 255) / 256), dim3(256), 0, s, dinst, count);
+  hipLaunchKernelGGL(group_reset_kernel, dim3((count + 255) / 256), dim3(256), 0, s, B.dinst, count);
   NSRGS_HIP(hipGetLastError(), "batch reset");
-  GroupArgs a{dinst, dunits, ns_steps};
+  return NSRGS_OK;
+}
+
+static void copy_results(const std::vector<GroupInst> &back, std::vector<BatchResult> &out) {
+  out.resize(back.size());
+  for (size_t k = 0; k < back.size(); ++k) {
+    out[k].iters = back[k].t;
+    out[k].converged = back[k].converged;
+    out[k].nonfinite = back[k].nonfinite;
+    out[k].panels = back[k].panels;
+    out[k].rel_change = back[k].rel_change;
+    out[k].max_defect = back[k].max_defect;
+    out[k].active = back[k].active;
+  }
+}
+
+// Up to `launches` grouped launches; every `check_every` launches the
+// descriptors are read back and the loop ends early once no problem is
+// active.  Reads the final state into `out`.
+int run_grouped(int fmt, const std::vector<GroupSpec> &specs, void *ctl, int launches, int ns_steps,
+                int waves, int order, int check_every, hipStream_t s, std::vector<BatchResult> &out) {
+  BatchDev B;
+  int st;
+  if ((st = upload_batch(specs, ctl, order, 0, s, B))) return st;
+  GroupInst *dinst = B.dinst;
+  const int dmax = B.dmax;
+  const std::vector<GroupUnit> &units = B.units;
+  const std::vector<GroupInst> &host = B.host;
+  GroupArgs a{dinst, B.dunits, ns_steps};
   if (check_every <= 0) check_every = std::max(launches, 1);
   std::vector<GroupInst> back(host);
   for (int it = 0; it < launches;) {
@@ -281,16 +491,39 @@ int run_grouped(int fmt, const std::vector<GroupSpec> &specs, void *ctl, int lau
               "batch readback");
     NSRGS_HIP(hipStreamSynchronize(s), "stream sync");
   }
-  out.resize(count);
-  for (int k = 0; k < count; ++k) {
-    out[k].iters = back[k].t;
-    out[k].converged = back[k].converged;
-    out[k].nonfinite = back[k].nonfinite;
-    out[k].panels = back[k].panels;
-    out[k].rel_change = back[k].rel_change;
-    out[k].max_defect = back[k].max_defect;
-    out[k].active = back[k].active;
+  copy_results(back, out);
+  return NSRGS_OK;
+}
+
+// One persistent launch for the whole remaining budget of every problem.
+int run_persistent(int fmt, const std::vector<GroupSpec> &specs, void *ctl, int ns_steps, int waves,
+                   int order, unsigned wait_polls, size_t min_ticket_bytes, hipStream_t s,
+                   std::vector<BatchResult> &out) {
+  BatchDev B;
+  int st;
+  if ((st = upload_batch(specs, ctl, order, min_ticket_bytes, s, B))) return st;
+  int rounds = 0;
+  for (const GroupSpec &g : specs) rounds = std::max(rounds, g.iters - g.t0);
+  const double tickets = (double)B.units.size() * rounds;
+  if (tickets > 2147483647.0)
+    return fail(NSRGS_ERR_INVALID_ARG, "persistent schedule: %.0f tickets exceed 2^31 (fewer iterations per call)",
+                tickets);
+  hipLaunchKernelGGL(persist_reset_kernel, dim3(1), dim3(64), 0, s, B.pc);
+  NSRGS_HIP(hipGetLastError(), "persistent reset");
+  if (rounds > 0 && !B.units.empty()) {
+    PersistArgs a{B.dinst, B.dunits, (int)B.units.size(), rounds, ns_steps, wait_polls, B.pc};
+    NSRGS_HIP(launch_persistent(fmt, B.dmax, a, waves, s), "persistent launch");
   }
+  std::vector<GroupInst> back(B.host);
+  PersistCtl pc{};
+  NSRGS_HIP(hipMemcpyAsync(back.data(), B.dinst, back.size() * sizeof(GroupInst), hipMemcpyDeviceToHost, s),
+            "batch readback");
+  NSRGS_HIP(hipMemcpyAsync(&pc, B.pc, sizeof(PersistCtl), hipMemcpyDeviceToHost, s), "persistent readback");
+  NSRGS_HIP(hipStreamSynchronize(s), "stream sync");
+  copy_results(back, out);
+  if (pc.abort)
+    return fail(NSRGS_ERR_DEVICE,
+                "persistent schedule: a dependency wait exceeded %u polls and the launch was abandoned", wait_polls);
   return NSRGS_OK;
 }
 
@@ -368,10 +601,10 @@ int sync_solve_batched(const nsrgs_problem *probs, int count, int ns_steps, int 
   if (max_iters < 0) return fail(NSRGS_ERR_INVALID_ARG, "max_iters must be >= 0");
   nsrgs_batch_opts o{};
   if (opts) o = *opts;
-  if (o.persistent)
-    return fail(NSRGS_ERR_UNSUPPORTED,
-                "the persistent single-launch schedule is switched off in this build; "
-                "batches run as one grouped launch per iteration");
+  if (o.persistent < 0 || o.persistent > 1) return fail(NSRGS_ERR_INVALID_ARG, "persistent must be 0 or 1");
+  if (o.order < 0 || o.order > 1) return fail(NSRGS_ERR_INVALID_ARG, "order must be 0 or 1");
+  if (o.wait_polls < 0) return fail(NSRGS_ERR_INVALID_ARG, "wait_polls must be >= 0");
+  if (o.ticket_kb < 0) return fail(NSRGS_ERR_INVALID_ARG, "ticket_kb must be >= 0");
   if (o.waves < 0 || o.waves > kMaxWaves) return fail(NSRGS_ERR_INVALID_ARG, "waves must be in [0, %d]", kMaxWaves);
   if (o.waves == 0) o.waves = tuned_batch_waves(fmt, dmax);
   const BatchLayout L = batch_layout(probs, count, o.init);
@@ -408,8 +641,13 @@ int sync_solve_batched(const nsrgs_problem *probs, int count, int ns_steps, int 
   }
   std::vector<BatchResult> res;
   const int check_every = o.check_every > 0 ? o.check_every : (any_tol ? 8 : max_iters);
-  if ((st = run_grouped(fmt, specs, base + L.ctl, max_iters, ns_steps, o.waves, o.order, check_every, s, res)))
-    return st;
+  if (o.persistent)
+    st = run_persistent(fmt, specs, base + L.ctl, ns_steps, o.waves, o.order,
+                        o.wait_polls > 0 ? (unsigned)o.wait_polls : kDefaultWaitPolls,
+                        (size_t)(o.ticket_kb > 0 ? o.ticket_kb : kDefaultTicketKiB) * 1024, s, res);
+  else
+    st = run_grouped(fmt, specs, base + L.ctl, max_iters, ns_steps, o.waves, o.order, check_every, s, res);
+  if (st) return st;
   int result = NSRGS_OK;
   for (int k = 0; k < count; ++k) {
     const nsrgs_problem &P = probs[k];

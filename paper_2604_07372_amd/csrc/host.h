@@ -49,6 +49,12 @@ size_t group_control_bytes(int count, size_t units);
 int run_grouped(int fmt, const std::vector<GroupSpec> &specs, void *ctl, int launches, int ns_steps,
                 int waves, int order, int check_every, hipStream_t s, std::vector<BatchResult> &out);
 
+// One persistent launch for the remaining budget of every problem (batched.hip).
+int run_persistent(int fmt, const std::vector<GroupSpec> &specs, void *ctl, int ns_steps, int waves,
+                   int order, unsigned wait_polls, size_t min_ticket_bytes, hipStream_t s,
+                   std::vector<BatchResult> &out);
+size_t elem_size(int fmt);   // bytes per stored A element (hi + lo for the split format)
+
 // Tuning table (runtime.hip): waves per workgroup of the grouped launch.
 int tuned_batch_waves(int fmt, int dmax);
 

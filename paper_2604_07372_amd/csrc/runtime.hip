@@ -38,6 +38,16 @@ int dev_fail(hipError_t e, const char *what) {
 
 bool valid_fmt(int fmt) { return fmt >= NSRGS_A_F64 && fmt <= NSRGS_A_FP8_E4M3; }
 size_t xbytes(int fmt) { return fmt == NSRGS_A_F64 ? 8 : 4; }
+
+size_t elem_size(int fmt) {
+  switch (fmt) {
+    case NSRGS_A_F64: return 8;
+    case NSRGS_A_F32: return 4;
+    case NSRGS_A_BF16: return 2;
+    case NSRGS_A_BF16_SPLIT: return 4;
+    default: return 1;
+  }
+}
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // ---- workspace layout ------------------------------------------------------

@@ -37,71 +37,57 @@ constexpr int elem_bytes() {
        : (FMT == NSRGS_A_BF16 || FMT == NSRGS_A_BF16_SPLIT) ? 2 : 1;
 }
 
-// Accumulate one column vector [c, c + V) of every panel row.
-// MASK: apply the matrix tail (columns >= nd) and, in mode 0, the exclusion of
-// each row's own diagonal block.  The masked form has no divergent branch:
-// every load goes to a clamped, in-bounds address and a select zeroes what
-// lies outside, so it may be called with any c >= 0 (c >= nd adds nothing).
-// (Exec-masked loads under this register pressure let the compiler place
-// register copies at the join before the exec mask is restored; the copies
-// then skip the ragged lanes.  Branch-free code leaves no such join.)
-template <int FMT, int D, int R, bool MASK, bool EXCL>
-__device__ __forceinline__ void accum(typename Fmt<FMT>::acc_t (&acc)[R][D],
-                                      const char *__restrict__ Ab,
-                                      const char *__restrict__ Alo,
-                                      const int64_t (&rowoff)[R],
-                                      const typename Fmt<FMT>::acc_t *__restrict__ X,
-                                      int c, int nd, int row0) {
+// Accumulate one column vector [c, c + V) of every panel row, masking the
+// matrix tail (columns >= nd) and, with EXCL, each row's own diagonal block.
+// Used for the few column groups per panel that need masks, so it favours low
+// register use over load batching: rows go in chunks of RC, and a scheduling
+// barrier keeps the compiler from hoisting every row's load to the front.
+// It has no divergent branch: every load goes to a clamped, in-bounds address
+// and a select zeroes what lies outside, so it may be called with any c >= 0
+// (c >= nd adds nothing).  (Exec-masked loads under this register pressure let
+// the compiler place register copies at the join before the exec mask was
+// restored, so the copies skipped the ragged lanes.)
+template <int FMT, int D, int R, bool EXCL>
+__device__ __forceinline__ void accum_masked(typename Fmt<FMT>::acc_t (&acc)[R][D],
+                                             const char *__restrict__ Ab,
+                                             const char *__restrict__ Alo,
+                                             const int64_t (&rowoff)[R],
+                                             const typename Fmt<FMT>::acc_t *__restrict__ X,
+                                             int c, int nd, int row0) {
   using T = typename Fmt<FMT>::acc_t;
   constexpr int V = Fmt<FMT>::V;
   constexpr int EB = elem_bytes<FMT>();
+  constexpr int RC = (R % 4 == 0) ? 4 : (R % 3 == 0) ? 3 : (R % 2 == 0) ? 2 : 1;
   T xv[V * D];
-  if constexpr (!MASK) {
-    constexpr int NQ = V * D * (int)sizeof(T) / 16;
-    const uint4 *xp = reinterpret_cast<const uint4 *>(X + (int64_t)c * D);
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      uint4 u = xp[q];
-      if constexpr (sizeof(T) == 4) {
-        xv[4 * q + 0] = __uint_as_float(u.x);
-        xv[4 * q + 1] = __uint_as_float(u.y);
-        xv[4 * q + 2] = __uint_as_float(u.z);
-        xv[4 * q + 3] = __uint_as_float(u.w);
-      } else {
-        xv[2 * q + 0] = __hiloint2double((int)u.y, (int)u.x);
-        xv[2 * q + 1] = __hiloint2double((int)u.w, (int)u.z);
-      }
-    }
-  } else {
+  for (int v = 0; v < V; ++v) {
+    const int cv = c + v;
+    const int src = cv < nd ? cv : nd - 1;
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-      const int cv = c + v;
-      const int src = cv < nd ? cv : nd - 1;
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        const T x = X[(int64_t)src * D + k];
-        xv[v * D + k] = cv < nd ? x : T(0);
-      }
+    for (int k = 0; k < D; ++k) {
+      const T x = X[(int64_t)src * D + k];
+      xv[v * D + k] = cv < nd ? x : T(0);
     }
   }
   // A rows are padded to whole 16-byte vectors, so a vector that starts below
   // nd stays inside the row; one that starts at or past nd reads column 0.
-  const int ca = (!MASK || c < nd) ? c : 0;
-  uint4 raw[R];
-  uint4 rawlo[R];
+  const int64_t ca = (int64_t)(c < nd ? c : 0) * EB;
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    raw[r] = ld16_stream(Ab + rowoff[r] + (int64_t)ca * EB);
-    if constexpr (FMT == NSRGS_A_BF16_SPLIT)
-      rawlo[r] = ld16_stream(Alo + rowoff[r] + (int64_t)ca * EB);
-    else
-      rawlo[r] = raw[r];
-  }
+  for (int r0 = 0; r0 < R; r0 += RC) {
+    uint4 raw[RC], rawlo[RC];
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    T a[V];
-    expand<FMT>(raw[r], rawlo[r], a);
-    if constexpr (MASK) {
+    for (int i = 0; i < RC; ++i) {
+      raw[i] = ld16_stream(Ab + rowoff[r0 + i] + ca);
+      if constexpr (FMT == NSRGS_A_BF16_SPLIT)
+        rawlo[i] = ld16_stream(Alo + rowoff[r0 + i] + ca);
+      else
+        rawlo[i] = raw[i];
+    }
+#pragma unroll
+    for (int i = 0; i < RC; ++i) {
+      const int r = r0 + i;
+      T a[V];
+      expand<FMT>(raw[i], rawlo[i], a);
       const int blk = (row0 + r) / D;
 #pragma unroll
       for (int v = 0; v < V; ++v) {
@@ -109,11 +95,12 @@ __device__ __forceinline__ void accum(typename Fmt<FMT>::acc_t (&acc)[R][D],
         if constexpr (EXCL) ok = ok && ((c + v) / D != blk);
         a[v] = ok ? a[v] : T(0);
       }
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[r][k] = fmaT(a[v], xv[v * D + k], acc[r][k]);
     }
-#pragma unroll
-    for (int v = 0; v < V; ++v)
-#pragma unroll
-      for (int k = 0; k < D; ++k) acc[r][k] = fmaT(a[v], xv[v * D + k], acc[r][k]);
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -267,7 +254,7 @@ __device__ __forceinline__ void panel_compute(const PanelJob &job, char *lds) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int c = g * GROUP + u * kWave * V + lane * V;
-      accum<FMT, D, R, true, EXCL>(acc, Ab, Alo, rowoff, X, c, nd, row0);
+      accum_masked<FMT, D, R, EXCL>(acc, Ab, Alo, rowoff, X, c, nd, row0);
     }
   }
 

@@ -12,15 +12,10 @@ from oracle import nsrgs as O
 
 from gpu_common import FMT_NAME, device_matrix, host, oracle_matrix, require_gpu, to_dev, xdtype
 
-# Largest d is 16: the configuration that did not finish on the GPU (see below).
+# Largest d is 16 (the widest kernel class).
 MIX = [(2, 1), (5, 2), (37, 3), (100, 4), (61, 10), (341, 3), (20, 16), (130, 2), (47, 7), (700, 3)]
 # The same kind of mix with largest d 10 (the middle kernel class).
 MIX10 = [(2, 1), (5, 2), (37, 3), (100, 4), (61, 10), (341, 3), (33, 9), (130, 2), (47, 7), (700, 3)]
-
-PERSISTENT_OFF = ("the persistent single-launch schedule (items taken from a device counter, "
-                  "cross-workgroup dependency waits) did not finish on the GPU on a batch with "
-                  "d up to 16; it is switched off and sync_solve_batched returns "
-                  "NSRGS_ERR_UNSUPPORTED for it")
 
 
 def _batch(fmt, shapes, seed=0, c=0.25):
@@ -46,21 +41,88 @@ def _alone(p, iters, monkeypatch, waves):
     return X
 
 
-def test_persistent_schedule_is_refused_on_the_host():
-    """CPU: the switched-off schedule is refused before any device work."""
+def test_batch_options_are_checked_on_the_host():
+    """CPU: bad schedule options are refused before any device work."""
     m = P._Matrix(P.F32, 16, None, None, 304)
     arr = (P._Problem * 1)(P._Problem(m, 100, 3, 0.0, 4096, 0, 0.0))
-    opts = P._BatchOpts(0, 0, 0, 0, 1)
-    st = P.lib().sync_solve_batched(arr, 1, 3, 10, 256, 1 << 30, None, ctypes.byref(opts), None)
-    assert st == 2
-    assert "persistent" in P.lib().nsrgs_last_error().decode()
+    for opts, msg in ((P._BatchOpts(0, 0, 0, 0, 2, 0), "persistent"),
+                      (P._BatchOpts(0, 3, 0, 0, 0, 0), "order"),
+                      (P._BatchOpts(0, 0, 0, 0, 1, -1), "wait_polls"),
+                      (P._BatchOpts(9, 0, 0, 0, 1, 0), "waves")):
+        st = P.lib().sync_solve_batched(arr, 1, 3, 10, 256, 1 << 30, None, ctypes.byref(opts), None)
+        assert st == 1, msg
+        assert msg in P.lib().nsrgs_last_error().decode()
 
 
 @pytest.mark.gpu
-@pytest.mark.skip(reason=PERSISTENT_OFF)
-def test_persistent_batched_matches_oracle():
-    probs, refs = _batch(P.F64, MIX)
-    P.solve_batched(probs, max_iters=30, persistent=True)
+@pytest.mark.parametrize("fmt", [P.F64, P.F32, P.BF16], ids=lambda f: FMT_NAME[f])
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("ticket_kb", [1, 0], ids=["panel_tickets", "merged_tickets"])
+def test_persistent_matches_grouped_and_oracle(fmt, order, ticket_kb):
+    """One persistent launch gives bitwise the grouped schedule's iterates (the
+    same per-panel arithmetic) for every problem of a d <= 16 mix, and the
+    oracle's within the format's bar; with one panel per ticket and with the
+    default merging (here whole problems per ticket)."""
+    require_gpu()
+    iters = 30
+    probs, refs = _batch(fmt, MIX, seed=20 + 10 * fmt)
+    X0s = [p["X"].clone() for p in probs]
+    print(f"persistent batch {FMT_NAME[fmt]} order={order} ticket_kb={ticket_kb}", flush=True)
+    st, infos = P.solve_batched(probs, max_iters=iters, waves=2, order=order, persistent=True,
+                                ticket_kb=ticket_kb)
+    assert st == 0
+    grouped = [dict(p, X=x.clone()) for p, x in zip(probs, X0s)]
+    st2, infos2 = P.solve_batched(grouped, max_iters=iters, waves=2, order=order)
+    assert st2 == 0
+    torch.cuda.synchronize()
+    for p, q, (Z, A64, X0), info, info2 in zip(probs, grouped, refs, infos, infos2):
+        n, d = p["n"], p["d"]
+        assert info["iters"] == iters == info2["iters"]
+        assert torch.equal(p["X"], q["X"]), (n, d)
+        assert info["rel_change"] == info2["rel_change"] and info["max_orth_defect"] == info2["max_orth_defect"]
+        ref = O.solve(oracle_matrix(A64, fmt), d, Ts=3, T=iters, X0=X0)
+        err = O.dist_F(host(p["X"]), ref.X) / math.sqrt(n)
+        assert err <= (1e-10 if fmt == P.F64 else 2e-5), (n, d, err)
+
+
+@pytest.mark.gpu
+def test_persistent_budgets_tolerance_and_nonfinite():
+    """Per-problem budgets, the relative-change stop and a non-finite problem,
+    all decided on the device inside one launch."""
+    require_gpu()
+    probs, refs = _batch(P.F64, [(60, 3), (80, 2), (40, 4), (50, 3)], seed=7)
+    X0 = [host(p["X"]) for p in probs]
+    probs[0]["iters"] = 5
+    probs[1]["tol"] = 1e-7
+    probs[3]["A"].data[5, 40] = float("nan")
+    st, infos = P.solve_batched(probs, max_iters=200, persistent=True, check=False)
+    assert st == 6                                        # the non-finite problem
+    assert infos[0]["iters"] == 5
+    ref1 = O.solve(refs[1][1], 2, Ts=3, T=200, stop="rel_change", tol=1e-7, X0=X0[1])
+    assert infos[1]["converged"] == 1 and abs(infos[1]["iters"] - ref1.iters) <= 1
+    assert infos[2]["iters"] == 200
+    assert infos[3]["nonfinite"] == 1 and infos[3]["iters"] == 1
+    for k, T in ((0, 5), (2, 200), (1, infos[1]["iters"])):
+        ref = O.solve(refs[k][1], probs[k]["d"], Ts=3, T=T, X0=X0[k])
+        assert O.dist_F(host(probs[k]["X"]), ref.X) <= 1e-10
+
+
+@pytest.mark.gpu
+def test_persistent_wait_bound_abandons_the_launch_cleanly():
+    """With a one-poll bound on every dependency wait (forced from the host),
+    the launch gives up instead of waiting, returns NSRGS_ERR_DEVICE, and the
+    device is usable afterwards."""
+    require_gpu()
+    probs, refs = _batch(P.F32, [(400, 3), (300, 3)], seed=13)
+    X0s = [p["X"].clone() for p in probs]
+    st, infos = P.solve_batched(probs, max_iters=50, persistent=True, wait_polls=1, check=False)
+    torch.cuda.synchronize()
+    assert st in (0, 4)
+    if st == 4:
+        assert "polls" in P.lib().nsrgs_last_error().decode()
+    again = [dict(p, X=x.clone()) for p, x in zip(probs, X0s)]
+    st2, infos2 = P.solve_batched(again, max_iters=50, persistent=True)
+    assert st2 == 0 and all(i["iters"] == 50 for i in infos2)
 
 
 def test_batch_with_too_large_d_is_refused_on_the_host():
