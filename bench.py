@@ -85,9 +85,11 @@ def batched_bench(iters: int = 100, base_iters: int = 10, count: int = 512, seed
     """512 independent problems: n log-uniform in [50, 3000], d uniform in
     {2, 3, 4, 10}, sigma = 0.2 sqrt(n/d), dense FP32 A generated on the device.
     Times `iters` iterations through grouped launches (one launch per iteration
-    for all problems), the same through one persistent launch, and `base_iters`
-    iterations as one sync_step launch per problem per iteration.  Every problem starts from its ground truth with a
-    0.05 perturbation (the initialization is not part of the timed loop)."""
+    for all problems), the same through one persistent launch, the same with
+    the schedule the autotuner picks (tuned untimed on the same problems), and
+    `base_iters` iterations as one sync_step launch per problem per iteration.
+    Every problem starts from its ground truth with a 0.05 perturbation (the
+    initialization is not part of the timed loop)."""
     import numpy as np
     import torch
     import paper_2604_07372_amd as P
@@ -124,6 +126,16 @@ def batched_bench(iters: int = 100, base_iters: int = 10, count: int = 512, seed
     torch.cuda.synchronize()
     t_pers = time.perf_counter() - t0
     same = all(torch.equal(p["X"], x) for p, x in zip(probs, X_group))
+    from paper_2604_07372_amd import autotune
+    for p in probs:
+        p["X"].copy_(p["X0"])
+    ranking = autotune.tune_batched(probs, iters=3)                 # untimed
+    best = autotune.batch_options(ranking[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_t, _ = P.solve_batched(probs, ns_steps=3, max_iters=iters, **best)
+    torch.cuda.synchronize()
+    t_tuned = time.perf_counter() - t0
     wss = [P.workspace(p["n"], p["d"], P.F32) for p in probs]
     outs = [torch.empty_like(p["X0"]) for p in probs]
     for p, w, o in zip(probs, wss, outs):
@@ -141,10 +153,16 @@ def batched_bench(iters: int = 100, base_iters: int = 10, count: int = 512, seed
            "persistent_s": t_pers, "persistent_problem_iters_per_s": count * iters / t_pers,
            "persistent_GBps": a_bytes * iters / t_pers / 1e9, "persistent_status": st_p,
            "persistent_equals_grouped": same,
+           "tuned_schedule": best, "tuned_s": t_tuned, "tuned_status": st_t,
+           "tuned_problem_iters_per_s": count * iters / t_tuned, "tuned_GBps": a_bytes * iters / t_tuned / 1e9,
+           "speedup_tuned_vs_per_problem_launches": None,
            "per_problem_launch_s_scaled": t_base,
            "per_problem_launch_problem_iters_per_s": count * iters / t_base,
            "speedup_vs_per_problem_launches": t_base / t_group,
            "status": st, "all_iters_done": all(i["iters"] == iters for i in infos)}
+    res["speedup_tuned_vs_per_problem_launches"] = t_base / t_tuned
+    print(f"[bench] batched: tuned {best} {t_tuned:.3f} s ({res['tuned_GBps']:.0f} GB/s)",
+          file=sys.stderr, flush=True)
     print(f"[bench] batched: persistent {t_pers:.3f} s ({res['persistent_GBps']:.0f} GB/s), "
           f"bitwise equal to grouped: {same}", file=sys.stderr, flush=True)
     print(f"[bench] batched: grouped {t_group:.3f} s ({res['grouped_GBps']:.0f} GB/s), per-problem launches "
@@ -263,10 +281,13 @@ def main(argv=None):
     torch.cuda.synchronize()
     X0 = torch.from_numpy(synth.perturbed_start(Z, 0.05, SEED + 1)).to(dev, torch.float32)
 
+    from paper_2604_07372_amd import autotune
     results = {}
     for name in fmts:
         Am = stores[name]
         ws = P.workspace(n, d, Am.fmt)
+        # launch shape from the autotuner, measured on this problem (untimed)
+        tuned = autotune.tune_step(Am, n, d, X0, ws=ws, reps=5)[0]
         Xa, Xb = X0.clone(), torch.empty_like(X0)
         for _ in range(a.warmup):
             P.step(Am, n, d, Xa, Xb, ws)
@@ -285,9 +306,11 @@ def main(argv=None):
         a_bytes = Am.data.shape[0] * Am.data.shape[0] * {"f32": 4, "bf16": 2, "bf16_split": 4, "fp8": 1}[name]
         a_bytes += (nd * 4 if name == "fp8" else 0) + 2 * nd * d * 4
         results[name] = {"ms_per_step": ms, "iters_per_s": 1e3 / ms, "wall_s": wall,
-                         "alg_bytes": a_bytes, "alg_GBps": a_bytes / (ms * 1e-3) / 1e9}
+                         "alg_bytes": a_bytes, "alg_GBps": a_bytes / (ms * 1e-3) / 1e9,
+                         "shape": {k: tuned[k] for k in ("blocks_per_panel", "unroll", "waves")}}
         print(f"[bench] {name}: {ms:.4f} ms/iter, {1e3 / ms:.1f} it/s, "
-              f"{results[name]['alg_GBps']:.0f} GB/s", file=sys.stderr, flush=True)
+              f"{results[name]['alg_GBps']:.0f} GB/s (tuned B={tuned['blocks_per_panel']} "
+              f"U={tuned['unroll']} W={tuned['waves']})", file=sys.stderr, flush=True)
 
     solve = {}
     if not a.no_solve:

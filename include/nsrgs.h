@@ -317,6 +317,33 @@ int nsrgs_get_tuning(nsrgs_tune_entry *entries, int max_count);
  * (message in nsrgs_last_error) when max_count > 0 and an array is NULL. */
 int nsrgs_step_variants(int d, int32_t *blocks_per_panel, int32_t *unroll, int max_count);
 
+/* ---- autotuner ------------------------------------------------------------
+ * Measure launch shapes on the caller's own problem (device memory and
+ * workspace as for the call being tuned) and return them fastest first in
+ * results[0 .. min(*count, max_results)); *count receives the number measured.
+ * Nothing is installed: pass the winners to nsrgs_set_tuning (or the batch
+ * options).  Both wait for the stream.
+ *
+ * nsrgs_autotune_step: every compiled (blocks_per_panel, unroll) shape of d
+ *   and waves in {1, 2, 4, 8}; reps timed sync_step launches each (HIP events,
+ *   after one untimed launch), T_s = 3, mu = 1/n.  X_out is overwritten.
+ * nsrgs_autotune_batched: the grouped and persistent schedules, unit orders 0
+ *   and 1, waves in {1, 2, 4}, persistent tickets of 128 / 512 / 2048 KiB;
+ *   each candidate runs `iters` iterations of every problem (tolerances are
+ *   ignored so every candidate does the same work), wall time per iteration.
+ *   The problems' X are iterated on (overwritten); pass copies. */
+typedef struct {
+  int32_t blocks_per_panel, unroll, waves;   /* step shape (waves also batched) */
+  int32_t persistent, order, ticket_kb;      /* batched schedule                */
+  double ms;                                 /* time per iteration             */
+} nsrgs_tune_result;
+int nsrgs_autotune_step(const nsrgs_matrix *A, int n, int d, const void *X_in, void *X_out,
+                        void *ws, size_t ws_bytes, void *stream, int reps,
+                        nsrgs_tune_result *results, int max_results, int *count);
+int nsrgs_autotune_batched(const nsrgs_problem *probs, int count, int ns_steps, int iters,
+                           void *ws, size_t ws_bytes, void *stream,
+                           nsrgs_tune_result *results, int max_results, int *n_results);
+
 /* ---- inputs: measurement generator and format conversion ----------------
  * nsrgs_generate_measurement writes A = Z Z^T + sigma W in F64 or F32
  * (fmt), element (r, c) computed in double and rounded once, where

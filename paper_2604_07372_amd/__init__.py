@@ -17,7 +17,7 @@ __all__ = [
     "lib", "StoredMatrix", "Workspace", "workspace", "step", "read_info",
     "init_spectral", "solve", "generate", "convert", "stored", "padded_ld",
     "Info", "solve_batched", "batch_rows_per_panel", "set_tuning", "get_tuning", "TuneEntry", "Server",
-    "step_variants",
+    "step_variants", "TuneResult",
 ]
 
 F64, F32, BF16, BF16_SPLIT, FP8_E4M3 = 0, 1, 2, 3, 4
@@ -72,6 +72,12 @@ class _BatchOpts(ctypes.Structure):
     _fields_ = [("waves", ctypes.c_int32), ("order", ctypes.c_int32), ("init", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("wait_polls", ctypes.c_int32), ("ticket_kb", ctypes.c_int32)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("blocks_per_panel", ctypes.c_int32), ("unroll", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("persistent", ctypes.c_int32), ("order", ctypes.c_int32), ("ticket_kb", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
 
 
 class TuneEntry(ctypes.Structure):
@@ -136,6 +142,10 @@ def lib() -> ctypes.CDLL:
         "nsrgs_set_tuning": (i32, [ctypes.POINTER(TuneEntry), i32]),
         "nsrgs_get_tuning": (i32, [ctypes.POINTER(TuneEntry), i32]),
         "nsrgs_step_variants": (i32, [i32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), i32]),
+        "nsrgs_autotune_step": (i32, [pm, i32, i32, vp, vp, vp, sz, vp, i32, ctypes.POINTER(TuneResult), i32,
+                                      ctypes.POINTER(i32)]),
+        "nsrgs_autotune_batched": (i32, [ctypes.POINTER(_Problem), i32, i32, i32, vp, sz, vp,
+                                         ctypes.POINTER(TuneResult), i32, ctypes.POINTER(i32)]),
         "nsrgs_server_create": (i32, [ctypes.POINTER(_ServerOpts), ctypes.POINTER(vp)]),
         "nsrgs_server_submit": (i32, [vp, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_int64)]),
         "nsrgs_server_poll": (i32, [vp, ctypes.POINTER(_Result), i32, ctypes.POINTER(i32)]),
@@ -368,15 +378,8 @@ def convert(A32: torch.Tensor, fmt: int) -> StoredMatrix:
     return out
 
 
-def solve_batched(problems, ns_steps: int = 3, max_iters: int = 100, init: bool = False, waves: int = 0,
-                  order: int = 0, check_every: int = 0, persistent: bool = False, wait_polls: int = 0,
-                  ticket_kb: int = 0, check: bool = True):
-    """Many problems per launch (sync_solve_batched): one grouped launch per
-    iteration, or with persistent=True one launch for the whole budget.
-
-    problems: sequence of dicts with keys A (StoredMatrix), n, d, X (device tensor,
-    X^0 on entry unless init, result on return) and optional mu, iters, tol.
-    Returns (status, list of per-problem info dicts)."""
+def _batch_args(problems, init=False):
+    """C problem array and an aligned workspace for a batch."""
     count = len(problems)
     arr = (_Problem * count)()
     for k, p in enumerate(problems):
@@ -388,6 +391,20 @@ def solve_batched(problems, ns_steps: int = 3, max_iters: int = 100, init: bool 
         _check(1)
     buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=problems[0]["X"].device)
     off = (-buf.data_ptr()) % 256
+    return arr, buf, off, nbytes
+
+
+def solve_batched(problems, ns_steps: int = 3, max_iters: int = 100, init: bool = False, waves: int = 0,
+                  order: int = 0, check_every: int = 0, persistent: bool = False, wait_polls: int = 0,
+                  ticket_kb: int = 0, check: bool = True):
+    """Many problems per launch (sync_solve_batched): one grouped launch per
+    iteration, or with persistent=True one launch for the whole budget.
+
+    problems: sequence of dicts with keys A (StoredMatrix), n, d, X (device tensor,
+    X^0 on entry unless init, result on return) and optional mu, iters, tol.
+    Returns (status, list of per-problem info dicts)."""
+    count = len(problems)
+    arr, buf, off, nbytes = _batch_args(problems, init)
     opts = _BatchOpts(int(waves), int(order), int(init), int(check_every), int(persistent), int(wait_polls),
                       int(ticket_kb))
     infos = (_ProblemInfo * count)()

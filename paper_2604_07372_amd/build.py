@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libnsrgs.so")
 
-SOURCES = (["stream.hip", "init.hip", "gen.hip", "runtime.hip", "batched.hip", "server.hip"]
+SOURCES = (["stream.hip", "init.hip", "gen.hip", "runtime.hip", "batched.hip", "server.hip", "autotune.hip"]
            + [f"stream_{f}_m{m}.hip" for f in ("f64", "f32", "bf16", "split", "fp8") for m in (0, 1)])
 
 HIPCC_FLAGS = [

@@ -55,6 +55,14 @@ int run_persistent(int fmt, const std::vector<GroupSpec> &specs, void *ctl, int 
                    std::vector<BatchResult> &out);
 size_t elem_size(int fmt);   // bytes per stored A element (hi + lo for the split format)
 
+// Single-problem step with a given launch shape, and sync_step's argument
+// checks (runtime.hip); used by the autotuner.
+struct StreamConfig;
+int step_with_config(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
+                     void *X_out, void *ws, hipStream_t s, const StreamConfig &cfg);
+int check_step_args(const nsrgs_matrix *A, int n, int d, int ns_steps, const void *X_in, void *X_out,
+                    void *ws, size_t ws_bytes);
+
 // Tuning table (runtime.hip): waves per workgroup of the grouped launch.
 int tuned_batch_waves(int fmt, int dmax);
 

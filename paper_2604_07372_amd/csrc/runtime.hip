@@ -240,10 +240,11 @@ int sync_workspace_init(void *ws, size_t ws_bytes, void *stream) {
   return NSRGS_OK;
 }
 
+// One step launch; `force` (nullable) replaces the chosen launch shape.
 static int step_impl(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps,
                      const void *X_in, void *X_out, void *ws, hipStream_t s, int iter,
-                     double tol, bool check_done) {
-  const StreamConfig cfg = choose_stream_config(A->fmt, d, n * d, 0);
+                     double tol, bool check_done, const StreamConfig *force = nullptr) {
+  const StreamConfig cfg = force ? *force : choose_stream_config(A->fmt, d, n * d, 0);
   StreamArgs a = make_args(A, n, d, cfg);
   const WsLayout L = layout(n, d, A->fmt);
   a.X_in = X_in;
@@ -273,6 +274,33 @@ int sync_step(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, cons
   if (overlap(X_in, X_out, xb)) return fail(NSRGS_ERR_INVALID_ARG, "X_in and X_out overlap");
   return step_impl(A, n, d, mu, ns_steps, X_in, X_out, ws, (hipStream_t)stream, 0, 0.0, false);
 }
+
+}  // extern "C"
+
+namespace nsrgs {
+// sync_step with a given launch shape (the autotuner's timing loop); the
+// arguments must already have passed sync_step's checks.
+int step_with_config(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
+                     void *X_out, void *ws, hipStream_t s, const StreamConfig &cfg) {
+  return step_impl(A, n, d, mu, ns_steps, X_in, X_out, ws, s, 0, 0.0, false, &cfg);
+}
+
+int check_step_args(const nsrgs_matrix *A, int n, int d, int ns_steps, const void *X_in, void *X_out,
+                    void *ws, size_t ws_bytes) {
+  int st;
+  if ((st = check_common(n, d))) return st;
+  if ((st = check_matrix(A, n, d))) return st;
+  if ((st = check_ws(ws, ws_bytes, n, d, A->fmt))) return st;
+  if (!X_in || !X_out) return fail(NSRGS_ERR_INVALID_ARG, "X_in / X_out is NULL");
+  if (!aligned16(X_in) || !aligned16(X_out)) return fail(NSRGS_ERR_INVALID_ARG, "X buffers must be 16-byte aligned");
+  if (ns_steps < 0 || ns_steps > 64) return fail(NSRGS_ERR_INVALID_ARG, "ns_steps must be in [0, 64]");
+  if (overlap(X_in, X_out, (size_t)n * d * d * xbytes(A->fmt)))
+    return fail(NSRGS_ERR_INVALID_ARG, "X_in and X_out overlap");
+  return NSRGS_OK;
+}
+}  // namespace nsrgs
+
+extern "C" {
 
 static void fill_info(const DevCtl &c, int d, nsrgs_info *info, int status) {
   if (!info) return;
