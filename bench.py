@@ -251,6 +251,9 @@ def main(argv=None):
     ap.add_argument("--serving-window", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--tuning", default="",
+                    help="load the step tuning table from this JSON file instead of tuning")
+    ap.add_argument("--save-tuning", default="", help="write the step tuning table to this JSON file")
     a = ap.parse_args(argv)
     if a.copy_calibration:
         return copy_calibration()
@@ -282,12 +285,18 @@ def main(argv=None):
     X0 = torch.from_numpy(synth.perturbed_start(Z, 0.05, SEED + 1)).to(dev, torch.float32)
 
     from paper_2604_07372_amd import autotune
+    if a.tuning:
+        autotune.load_table(a.tuning)
     results = {}
     for name in fmts:
         Am = stores[name]
         ws = P.workspace(n, d, Am.fmt)
-        # launch shape from the autotuner, measured on this problem (untimed)
-        tuned = autotune.tune_step(Am, n, d, X0, ws=ws, reps=5)[0]
+        if a.tuning:
+            tuned = next(e for e in P.get_tuning()
+                         if e["kind"] == 0 and e["fmt"] == Am.fmt and e["d"] == d and e["nd_min"] <= nd <= e["nd_max"])
+        else:
+            # launch shape from the autotuner, measured on this problem (untimed)
+            tuned = autotune.tune_step(Am, n, d, X0, ws=ws, reps=5)[0]
         Xa, Xb = X0.clone(), torch.empty_like(X0)
         for _ in range(a.warmup):
             P.step(Am, n, d, Xa, Xb, ws)
@@ -312,6 +321,8 @@ def main(argv=None):
               f"{results[name]['alg_GBps']:.0f} GB/s (tuned B={tuned['blocks_per_panel']} "
               f"U={tuned['unroll']} W={tuned['waves']})", file=sys.stderr, flush=True)
 
+    if a.save_tuning:
+        autotune.save_table(a.save_tuning)
     solve = {}
     if not a.no_solve:
         pred = sigma * math.sqrt(d * (d - 1) / (2.0 * n))
