@@ -297,9 +297,12 @@ int nsrgs_server_destroy(nsrgs_server *server);
 
 /* ---- tuning table ---------------------------------------------------------
  * Launch shapes measured by the autotuner.  kind 0: the single-problem step
- * (blocks_per_panel B, unroll U column vectors per row, waves W) for storage
- * format fmt, block size d and n*d in [nd_min, nd_max]; an entry whose (B, U)
- * is not compiled for d is ignored.  kind 1: waves per workgroup of the
+ * (blocks_per_panel B: the workgroup's panel is B d rows; unroll U: 0 = one
+ * 16-byte column vector per row per loop iteration with the next iteration's
+ * loads issued before this one's arithmetic, U >= 1 = U vectors per row
+ * loaded together; waves W splitting the columns) for storage format fmt,
+ * block size d and n*d in [nd_min, nd_max]; an entry whose (B, U) is not
+ * compiled for d is ignored.  kind 1: waves per workgroup of the
  * grouped batched launch for format fmt and batches whose largest d is <= d.
  * The first matching entry wins; entries replace the whole table (count 0
  * clears it).  Not thread-safe against concurrent launches. */

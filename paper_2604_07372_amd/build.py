@@ -1,5 +1,9 @@
 """Build libnsrgs.so (HIP for gfx950) in the package directory.
 
+Every translation unit keeps its device assembly (-save-temps), and the build
+fails if any kernel runs vector work under a narrowed exec mask at a branch
+join (see asmcheck.py).
+
 Usage: python -m paper_2604_07372_amd.build  [--jobs N] [--verbose]
 """
 from __future__ import annotations
@@ -11,6 +15,11 @@ import subprocess
 import sys
 from concurrent.futures import ThreadPoolExecutor
 
+try:
+    from . import asmcheck
+except ImportError:          # run as a script
+    import asmcheck
+
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
@@ -18,8 +27,9 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libnsrgs.so")
 
-SOURCES = (["stream.hip", "init.hip", "gen.hip", "runtime.hip", "batched.hip", "server.hip", "autotune.hip"]
-           + [f"stream_{f}_m{m}.hip" for f in ("f64", "f32", "bf16", "split", "fp8") for m in (0, 1)])
+SOURCES = (["batched_f64.hip", "batched_f32.hip", "batched_bf16.hip"]
+           + [f"stream_{f}_{part}.hip" for f in ("fp8", "split", "f64", "bf16", "f32") for part in ("m0c", "m0b", "m0a", "m1")]
+           + ["stream.hip", "init.hip", "gen.hip", "runtime.hip", "batched.hip", "server.hip", "autotune.hip"])
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -38,7 +48,7 @@ def hipcc() -> str:
 
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *HIPCC_FLAGS, "-save-temps=obj", "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -54,6 +64,10 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     jobs = jobs or min(len(srcs), os.cpu_count() or 4)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+    device_asm = [os.path.join(BUILD, os.path.splitext(s)[0] + "-hip-amdgcn-amd-amdhsa-gfx950.s") for s in srcs]
+    problems = asmcheck.check_files([p for p in device_asm if os.path.exists(p)])
+    if problems:
+        raise RuntimeError("generated code runs vector work under a narrowed exec mask:\n" + "\n".join(problems))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

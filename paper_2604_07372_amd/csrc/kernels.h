@@ -34,7 +34,8 @@ struct StreamArgs {
 struct StreamConfig {
   int blocks_per_panel;   // B: rows per panel R = B d
   int waves;              // W: waves per workgroup splitting the columns
-  int unroll;             // U: 16-byte column vectors per lane per row per iteration
+  int unroll;             // U: 16-byte column vectors per lane per row per iteration;
+                          //    0: one, software-pipelined
 };
 
 // Compiled (B, U) variants for a given d (waves = 1); returns the count.

@@ -149,26 +149,23 @@ int tuned_batch_waves(int fmt, int dmax) {
 }
 
 StreamConfig choose_stream_config(int fmt, int d, int nd, int mode) {
-  StreamConfig cfg{stream_block_init(d), 1, 1};
-  const bool forced = env_int("NSRGS_STEP_B", 0) > 0 || env_int("NSRGS_STEP_U", 0) > 0 ||
-                      env_int("NSRGS_STEP_W", 0) > 0;
+  StreamConfig cfg{stream_block_init(d), 1, 0};
+  const int fb = env_int("NSRGS_STEP_B", 0), fu = env_int("NSRGS_STEP_U", -1);
+  const bool forced = fb > 0 || fu >= 0 || env_int("NSRGS_STEP_W", 0) > 0;
   if (mode == 0 && !forced && tuned_step(fmt, d, nd, &cfg)) return cfg;
   if (mode == 0) {
     StreamConfig v[16];
     const int nv = stream_variants(d, v, 16);
-    // Default: the largest panel with at most 12 rows (24 for the 1- and
-    // 2-byte formats, whose X slice per load is wider), one vector per row per
-    // iteration; FP32 at d = 3 takes two (measured best at n = 20000).
-    // Environment overrides select any compiled variant.
-    const int max_rows = (fmt == NSRGS_A_BF16 || fmt == NSRGS_A_FP8_E4M3) ? 24 : 12;
+    // Default: the software-pipelined loop (U = 0) with the largest panel of
+    // at most 12 rows (every d has a B = 1 pipelined shape).  The autotuner's
+    // table, or the environment (NSRGS_STEP_B/U/W), selects any compiled shape.
+    cfg.blocks_per_panel = 1;
+    cfg.unroll = 0;
     for (int i = 0; i < nv; ++i)
-      if (v[i].unroll == 1 && v[i].blocks_per_panel * d <= max_rows &&
-          v[i].blocks_per_panel > cfg.blocks_per_panel)
+      if (v[i].unroll == 0 && v[i].blocks_per_panel * d <= 12 && v[i].blocks_per_panel > cfg.blocks_per_panel)
         cfg.blocks_per_panel = v[i].blocks_per_panel;
-    if (fmt == NSRGS_A_F32 && d == 3) cfg.unroll = 2;
-    const int fb = env_int("NSRGS_STEP_B", 0), fu = env_int("NSRGS_STEP_U", 0);
-    if (fb > 0 || fu > 0) {
-      const int wb = fb > 0 ? fb : cfg.blocks_per_panel, wu = fu > 0 ? fu : cfg.unroll;
+    if (fb > 0 || fu >= 0) {
+      const int wb = fb > 0 ? fb : cfg.blocks_per_panel, wu = fu >= 0 ? fu : cfg.unroll;
       for (int i = 0; i < nv; ++i)
         if (v[i].blocks_per_panel == wb && v[i].unroll == wu) {
           cfg.blocks_per_panel = wb;
@@ -181,7 +178,7 @@ StreamConfig choose_stream_config(int fmt, int d, int nd, int mode) {
   // Enough waves to cover 256 CUs several times over, while every wave keeps
   // a few column groups of work.
   const int V = fmt == NSRGS_A_F64 ? 2 : fmt == NSRGS_A_F32 ? 4 : fmt == NSRGS_A_FP8_E4M3 ? 16 : 8;
-  const int group = 64 * V * cfg.unroll;
+  const int group = 64 * V * (cfg.unroll > 0 ? cfg.unroll : 1);
   const int groups = (nd + group - 1) / group;
   int W = 1;
   while (W < kMaxWaves && (int64_t)panels * W < 8192 && groups / (2 * W) >= 4) W *= 2;

@@ -1,0 +1,8 @@
+// Instantiations of the streaming kernel: format NSRGS_A_F32, mode 0, d in [1, 4].
+#include "stream_impl.h"
+
+namespace nsrgs {
+hipError_t launch_stream_f32_m0a(const StreamConfig &cfg, const StreamArgs &args, hipStream_t s) {
+  return launch_fmt_impl<0, NSRGS_A_F32, 1, 4>(cfg, args, s);
+}
+}  // namespace nsrgs

@@ -122,9 +122,15 @@ __device__ __forceinline__ void accum_full(typename Fmt<FMT>::acc_t (&acc)[R][D]
   uint4 xr[U][NQ];
   uint4 raw[U][R];
   uint4 rawlo[U][R];
+  // X first, then the rows in the order they are used: the load counter
+  // drains in issue order, so the arithmetic on row r can start as soon as
+  // row r has arrived instead of waiting for the whole batch.
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int c = c0 + u * kWave * V;
+    const uint4 *xp = reinterpret_cast<const uint4 *>(X + (int64_t)c * D);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) xr[u][q] = xp[q];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       raw[u][r] = ld16_stream(Ab + rowoff[r] + (int64_t)c * EB);
@@ -133,9 +139,6 @@ __device__ __forceinline__ void accum_full(typename Fmt<FMT>::acc_t (&acc)[R][D]
       else
         rawlo[u][r] = raw[u][r];
     }
-    const uint4 *xp = reinterpret_cast<const uint4 *>(X + (int64_t)c * D);
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) xr[u][q] = xp[q];
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -161,6 +164,64 @@ __device__ __forceinline__ void accum_full(typename Fmt<FMT>::acc_t (&acc)[R][D]
 #pragma unroll
         for (int k = 0; k < D; ++k) acc[r][k] = fmaT(a[v], xv[v * D + k], acc[r][k]);
     }
+  }
+}
+
+// The two halves of one unmasked column vector per row, for the software
+// pipeline of panel_compute: issue the R row loads and the X slice of the
+// next column group, then accumulate the current one (loaded one round
+// earlier) while those loads are in flight.  Loading the X slice with its
+// group keeps the wait for the current operands from also waiting for the
+// prefetch (the load counter drains in issue order).
+template <int FMT, int D>
+constexpr int x_quads() {
+  return Fmt<FMT>::V * D * (int)sizeof(typename Fmt<FMT>::acc_t) / 16;
+}
+
+template <int FMT, int D, int R, int NQ>
+__device__ __forceinline__ void load_group(uint4 (&raw)[R], uint4 (&rawlo)[R], uint4 (&xr)[NQ],
+                                           const char *__restrict__ Ab, const char *__restrict__ Alo,
+                                           const int64_t (&rowoff)[R],
+                                           const typename Fmt<FMT>::acc_t *__restrict__ X, int c) {
+  constexpr int EB = elem_bytes<FMT>();
+  const uint4 *xp = reinterpret_cast<const uint4 *>(X + (int64_t)c * D);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) xr[q] = xp[q];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    raw[r] = ld16_stream(Ab + rowoff[r] + (int64_t)c * EB);
+    if constexpr (FMT == NSRGS_A_BF16_SPLIT)
+      rawlo[r] = ld16_stream(Alo + rowoff[r] + (int64_t)c * EB);
+  }
+}
+
+template <int FMT, int D, int R, int NQ>
+__device__ __forceinline__ void fma_group(typename Fmt<FMT>::acc_t (&acc)[R][D], const uint4 (&raw)[R],
+                                          const uint4 (&rawlo)[R], const uint4 (&xr)[NQ]) {
+  using T = typename Fmt<FMT>::acc_t;
+  constexpr int V = Fmt<FMT>::V;
+  T xv[V * D];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const uint4 u = xr[q];
+    if constexpr (sizeof(T) == 4) {
+      xv[4 * q + 0] = __uint_as_float(u.x);
+      xv[4 * q + 1] = __uint_as_float(u.y);
+      xv[4 * q + 2] = __uint_as_float(u.z);
+      xv[4 * q + 3] = __uint_as_float(u.w);
+    } else {
+      xv[2 * q + 0] = __hiloint2double((int)u.y, (int)u.x);
+      xv[2 * q + 1] = __hiloint2double((int)u.w, (int)u.z);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    T a[V];
+    expand<FMT>(raw[r], FMT == NSRGS_A_BF16_SPLIT ? rawlo[r] : raw[r], a);
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int k = 0; k < D; ++k) acc[r][k] = fmaT(a[v], xv[v * D + k], acc[r][k]);
   }
 }
 
@@ -197,7 +258,8 @@ __device__ __forceinline__ void panel_compute(const PanelJob &job, char *lds) {
   constexpr int V = Fmt<FMT>::V;
   constexpr int R = B * D;
   constexpr int NE = R * D;              // panel entries of C (= B blocks of d x d)
-  constexpr int GROUP = kWave * V * U;   // columns per wave per loop iteration
+  constexpr int UV = U > 0 ? U : 1;      // vectors per row per loop iteration
+  constexpr int GROUP = kWave * V * UV;  // columns per wave per loop iteration
   constexpr int EB = elem_bytes<FMT>();
   constexpr bool EXCL = (MODE == 0);
 
@@ -241,9 +303,51 @@ __device__ __forceinline__ void panel_compute(const PanelJob &job, char *lds) {
     gd0 = row0 / GROUP;
     gd1 = min(row0 + R - 1, nd - 1) / GROUP;
   }
-  for (int g = wave; g < nfull; g += nw) {
-    if (g == gd0 || g == gd1) continue;
-    accum_full<FMT, D, R, U>(acc, Ab, Alo, rowoff, X, g * GROUP + lane * V);
+  if constexpr (U == 0) {
+    // Software pipeline over this wave's full groups (diagonal groups skipped):
+    // the loads of the next group are in flight while the current one is
+    // accumulated.  g, gn are wave-uniform, so the branches are scalar.
+    auto skip_diag = [&](int g) {
+      while (g < nfull && (g == gd0 || g == gd1)) g += nw;
+      return g;
+    };
+    // Two register buffers take turns (unrolled by two, so no copy hands one
+    // over to the other); in the loop the prefetch is unconditional, so the
+    // arithmetic waits only for the previous round's loads, never for the
+    // one just issued.  The exits accumulate the last group.
+    int g = skip_diag(wave);
+    constexpr int NQ = x_quads<FMT, D>();
+    if (g < nfull) {
+      uint4 b0[R], b0lo[R], x0[NQ], b1[R], b1lo[R], x1[NQ];
+      load_group<FMT, D, R, NQ>(b0, b0lo, x0, Ab, Alo, rowoff, X, g * GROUP + lane * V);
+      for (;;) {
+        int gn = skip_diag(g + nw);
+        if (gn >= nfull) {
+          fma_group<FMT, D, R, NQ>(acc, b0, b0lo, x0);
+          break;
+        }
+        load_group<FMT, D, R, NQ>(b1, b1lo, x1, Ab, Alo, rowoff, X, gn * GROUP + lane * V);
+        fma_group<FMT, D, R, NQ>(acc, b0, b0lo, x0);
+        g = gn;
+        gn = skip_diag(g + nw);
+        if (gn >= nfull) {
+          fma_group<FMT, D, R, NQ>(acc, b1, b1lo, x1);
+          break;
+        }
+        load_group<FMT, D, R, NQ>(b0, b0lo, x0, Ab, Alo, rowoff, X, gn * GROUP + lane * V);
+        fma_group<FMT, D, R, NQ>(acc, b1, b1lo, x1);
+        g = gn;
+      }
+    }
+  } else {
+    // One path through the loop body (the diagonal groups are stepped over
+    // by the induction, not by a branch in the body).
+    auto skip_diag = [&](int g) {
+      while (g < nfull && (g == gd0 || g == gd1)) g += nw;
+      return g;
+    };
+    for (int g = skip_diag(wave); g < nfull; g = skip_diag(g + nw))
+      accum_full<FMT, D, R, U>(acc, Ab, Alo, rowoff, X, g * GROUP + lane * V);
   }
   const int gt = nfull < ngroups ? nfull : -1;
   for (int q = 0; q < 3; ++q) {
@@ -252,7 +356,7 @@ __device__ __forceinline__ void panel_compute(const PanelJob &job, char *lds) {
     if (q == 1 && g == gd0) continue;
     if (q == 2 && (g == gd0 || g == gd1)) continue;
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+    for (int u = 0; u < UV; ++u) {
       const int c = g * GROUP + u * kWave * V + lane * V;
       accum_masked<FMT, D, R, EXCL>(acc, Ab, Alo, rowoff, X, c, nd, row0);
     }
@@ -508,21 +612,28 @@ stream_kernel(StreamArgs args) {
 }
 
 // ---------------------------------------------------------------------------
-// Instantiation table: (d, B) pairs, R = B d rows per panel.  Mode 1 (the
-// spectral-initialization product) uses only the first entry of each d.
+// Instantiation table: (d, B, U) triples, R = B d rows per panel; U = 0 is
+// one 16-byte vector per row per iteration with the next iteration's loads
+// issued before this one's arithmetic (software pipeline), U >= 1 loads U
+// vectors per row together and then accumulates them.  Mode 1 (the
+// spectral-initialization product) uses the second table.
 // ---------------------------------------------------------------------------
-#define NSRGS_BOPTS(X)                                                                    \
-  X(1, 8, 1) X(1, 16, 1) X(1, 8, 2) X(2, 4, 1) X(2, 8, 1) X(2, 4, 2)                       \
-  X(3, 4, 1) X(3, 2, 1) X(3, 8, 1) X(3, 2, 2) X(3, 4, 2) X(3, 1, 2) X(3, 1, 4) X(3, 2, 4) \
-  X(4, 2, 1) X(4, 4, 1) X(4, 2, 2) X(4, 1, 2)                                              \
-  X(5, 1, 1) X(5, 2, 1) X(6, 1, 1) X(6, 2, 1) X(7, 1, 1) X(7, 2, 1) X(8, 1, 1) X(8, 2, 1) \
-  X(9, 1, 1) X(10, 1, 1) X(11, 1, 1) X(12, 1, 1) X(13, 1, 1) X(14, 1, 1) X(15, 1, 1)       \
-  X(16, 1, 1)
+#define NSRGS_BOPTS(X)                                                                      \
+  X(1, 8, 0) X(1, 16, 0) X(1, 16, 1) X(1, 8, 2)                                            \
+  X(2, 4, 0) X(2, 8, 0) X(2, 8, 1) X(2, 4, 2)                                              \
+  X(3, 4, 0) X(3, 2, 0) X(3, 8, 0) X(3, 8, 1) X(3, 4, 1) X(3, 2, 2) X(3, 4, 2) X(3, 1, 2)  \
+  X(3, 1, 4) X(3, 2, 4)                                                                    \
+  X(4, 2, 0) X(4, 4, 0) X(4, 4, 1) X(4, 2, 2) X(4, 1, 2)                                   \
+  X(5, 1, 0) X(5, 2, 0) X(5, 2, 1) X(6, 1, 0) X(6, 2, 0) X(6, 2, 1)                        \
+  X(7, 1, 0) X(7, 2, 1) X(8, 1, 0) X(8, 2, 1)                                              \
+  X(9, 1, 0) X(9, 1, 1) X(10, 1, 0) X(10, 1, 1) X(11, 1, 0) X(11, 1, 1) X(12, 1, 0)        \
+  X(12, 1, 1) X(13, 1, 0) X(13, 1, 1) X(14, 1, 0) X(14, 1, 1) X(15, 1, 0) X(15, 1, 1)      \
+  X(16, 1, 0) X(16, 1, 1)
 
 #define NSRGS_BOPTS_INIT(X)                                                   \
-  X(1, 8, 1) X(2, 4, 1) X(3, 4, 1) X(4, 2, 1) X(5, 1, 1) X(6, 1, 1) X(7, 1, 1) \
-  X(8, 1, 1) X(9, 1, 1) X(10, 1, 1) X(11, 1, 1) X(12, 1, 1) X(13, 1, 1)        \
-  X(14, 1, 1) X(15, 1, 1) X(16, 1, 1)
+  X(1, 8, 0) X(2, 4, 0) X(3, 4, 0) X(4, 2, 0) X(5, 1, 0) X(6, 1, 0) X(7, 1, 0) \
+  X(8, 1, 0) X(9, 1, 0) X(10, 1, 0) X(11, 1, 0) X(12, 1, 0) X(13, 1, 0)        \
+  X(14, 1, 0) X(15, 1, 0) X(16, 1, 0)
 
 template <int MODE, int FMT, int D, int B, int U>
 hipError_t launch_one(const StreamConfig &cfg, const StreamArgs &args, hipStream_t s) {
@@ -531,11 +642,15 @@ hipError_t launch_one(const StreamConfig &cfg, const StreamArgs &args, hipStream
   return hipGetLastError();
 }
 
-template <int MODE, int FMT>
+// Dispatch to the compiled shapes with DLO <= d <= DHI (the step kernels of
+// one format are split over two translation units by d so the library builds
+// in parallel).
+template <int MODE, int FMT, int DLO = 1, int DHI = kMaxD>
 hipError_t launch_fmt_impl(const StreamConfig &cfg, const StreamArgs &args, hipStream_t s) {
-#define NSRGS_CASE(DD, BB, UU)                                                        \
-  if (args.d == DD && cfg.blocks_per_panel == BB && cfg.unroll == UU)                   \
-    return launch_one<MODE, FMT, DD, BB, UU>(cfg, args, s);
+#define NSRGS_CASE(DD, BB, UU)                                                          \
+  if constexpr (DD >= DLO && DD <= DHI)                                                   \
+    if (args.d == DD && cfg.blocks_per_panel == BB && cfg.unroll == UU)                   \
+      return launch_one<MODE, FMT, DD, BB, UU>(cfg, args, s);
   if constexpr (MODE == 0) {
     NSRGS_BOPTS(NSRGS_CASE)
   } else {
