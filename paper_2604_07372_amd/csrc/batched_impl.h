@@ -191,11 +191,13 @@ __global__ void __launch_bounds__(kWave * kMaxWaves) grouped_kernel(GroupArgs ar
   job.stat = I.stats + unit.panel;
   job.gram = nullptr;
   run_panel<FMT, DMAX>(I.d, job, lds);
-  __threadfence();
+  // release: this workgroup's results before its arrival is counted (no L2
+  // invalidate here: a full fence per workgroup keeps evicting the reused X)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   if (threadIdx.x == 0) s_last = (atomicAdd(&I.arrive, 1u) == (unsigned)I.panels - 1u);
   __syncthreads();
   if (s_last) {
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // every other workgroup's results
     finish_problem<false>(I, s_scr, t + 1);
   }
 }

@@ -71,12 +71,14 @@ __global__ void __launch_bounds__(256) init_apply_kernel(InitArgs a) {
     part[2 * blockIdx.x] = res2;
     part[2 * blockIdx.x + 1] = fbad;
   }
-  __threadfence();
+  // release: this workgroup's results before its arrival is counted (no L2
+  // invalidate here: a full fence per workgroup keeps evicting the reused X)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   if (tid == 0) s_last = (atomicAdd(&ctl->arrive2, 1u) == (unsigned)a.num_groups - 1u);
   __syncthreads();
   if (s_last) {
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // every other workgroup's results
     double s = 0.0, b = 0.0;
     for (int g = tid; g < a.num_groups; g += blockDim.x) {
       s += part[2 * g];

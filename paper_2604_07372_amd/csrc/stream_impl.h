@@ -10,8 +10,9 @@
 // and writes X^{t+1} plus per-panel monitors.  C, G and F never reach memory.
 //
 // Mode 1 (spectral initialization): the same stream computes W = A Y for the
-// panel (no exclusion) and per-panel partial Grams Y^T W and W^T W; the last
-// workgroup reduces them in FP64 and factors W^T W = R^T R (Cholesky-QR).
+// panel (no exclusion) and per-panel partial Grams Y^T W and W^T W; a
+// one-workgroup kernel then reduces them in FP64 and factors W^T W = R^T R
+// (Cholesky-QR).
 //
 // Data layout: A row-major (16-byte vectors along a row: lane l of a wave reads
 // columns [c, c + V) of every panel row, consecutive lanes consecutive vectors,
@@ -140,6 +141,10 @@ __device__ __forceinline__ void accum_full(typename Fmt<FMT>::acc_t (&acc)[R][D]
         rawlo[u][r] = raw[u][r];
     }
   }
+  // Keep every load of the group ahead of the arithmetic: left alone, the
+  // scheduler sinks some of them below the first FMAs to save registers, and
+  // their latency is then paid once per group with nothing else in flight.
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     T xv[V * D];
@@ -193,6 +198,7 @@ __device__ __forceinline__ void load_group(uint4 (&raw)[R], uint4 (&rawlo)[R], u
     if constexpr (FMT == NSRGS_A_BF16_SPLIT)
       rawlo[r] = ld16_stream(Alo + rowoff[r] + (int64_t)c * EB);
   }
+  __builtin_amdgcn_sched_barrier(0);   // the prefetch stays ahead of the arithmetic
 }
 
 template <int FMT, int D, int R, int NQ>
@@ -491,7 +497,7 @@ __device__ __forceinline__ void panel_compute(const PanelJob &job, char *lds) {
   __syncthreads();
 }
 
-// Last workgroup of a mode-0 launch: reduce the panel monitors in a fixed
+// After a mode-0 launch (one workgroup): reduce the panel monitors in a fixed
 // order (FP64) into the control block and apply the stop rule.
 __device__ inline void finish_step(const StreamArgs &args, double *s_scr) {
   const int tid = threadIdx.x;
@@ -528,7 +534,7 @@ __device__ inline void finish_step(const StreamArgs &args, double *s_scr) {
   }
 }
 
-// Last workgroup of a mode-1 launch: FP64 reduction of the partial Grams,
+// After a mode-1 launch (one workgroup): FP64 reduction of the partial Grams,
 // the Rayleigh quotient T = Y^T A Y and the Cholesky factor of W^T W.
 template <typename T, int D>
 __device__ inline void finish_gram(const StreamArgs &args) {
@@ -578,8 +584,6 @@ template <int FMT, int D, int B, int U, int MODE>
 __global__ void __launch_bounds__(kWave * kMaxWaves)
 stream_kernel(StreamArgs args) {
   using T = typename Fmt<FMT>::acc_t;
-  __shared__ double s_scr[kMaxWaves];
-  __shared__ int s_last;
   __shared__ __attribute__((aligned(16))) char lds[panel_lds_bytes<FMT, D, B>()];
   if (args.stop_flag) {
     if (__atomic_load_n(args.stop_flag, __ATOMIC_RELAXED)) return;   // uniform
@@ -599,16 +603,21 @@ stream_kernel(StreamArgs args) {
   job.stat = static_cast<PanelStat *>(args.partials) + blockIdx.x;
   job.gram = static_cast<T *>(args.partials) + (int64_t)blockIdx.x * 2 * D * D;
   panel_compute<FMT, D, B, U, MODE>(job, lds);
-  // The last workgroup to arrive reduces the per-panel results.
-  __threadfence();
-  unsigned *arrive = MODE == 0 ? &args.ctl->arrive : &args.ctl->arrive2;
-  if (threadIdx.x == 0) s_last = (atomicAdd(arrive, 1u) == (unsigned)args.num_panels - 1u);
-  __syncthreads();
-  if (s_last) {
-    __threadfence();
-    if constexpr (MODE == 0) finish_step(args, s_scr);
-    else finish_gram<T, D>(args);
+}
+
+// The per-panel results are reduced by a second, one-workgroup kernel on the
+// same stream: the kernel boundary orders every panel's writes before the
+// reduction once per step.  (A last-arriving workgroup would need a release
+// fence in every workgroup, and each of those writes back the L2; at
+// thousands of panels per step that cost about a tenth of the stream.)
+template <typename T, int D, int MODE>
+__global__ void __launch_bounds__(256) stream_finish_kernel(StreamArgs args) {
+  __shared__ double s_scr[kMaxWaves];
+  if (args.stop_flag) {
+    if (__atomic_load_n(args.stop_flag, __ATOMIC_RELAXED)) return;   // uniform
   }
+  if constexpr (MODE == 0) finish_step(args, s_scr);
+  else finish_gram<T, D>(args);
 }
 
 // ---------------------------------------------------------------------------
@@ -637,8 +646,12 @@ stream_kernel(StreamArgs args) {
 
 template <int MODE, int FMT, int D, int B, int U>
 hipError_t launch_one(const StreamConfig &cfg, const StreamArgs &args, hipStream_t s) {
+  using T = typename Fmt<FMT>::acc_t;
   const dim3 grid(args.num_panels), block(kWave * cfg.waves);
   hipLaunchKernelGGL((stream_kernel<FMT, D, B, U, MODE>), grid, block, 0, s, args);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((stream_finish_kernel<T, D, MODE>), dim3(1), dim3(256), 0, s, args);
   return hipGetLastError();
 }
 
