@@ -36,6 +36,15 @@ static hipError_t launch_persistent(int fmt, int dmax, const PersistArgs &a, int
   }
 }
 
+// Grouped schedule, second launch of an iteration: each active problem's
+// monitors, iteration counter and stop rule (one workgroup per problem).
+__global__ void __launch_bounds__(256) group_finish_kernel(GroupInst *inst) {
+  __shared__ double s_scr[kMaxWaves];
+  GroupInst &I = inst[blockIdx.x];
+  if (!I.active) return;                              // uniform
+  finish_problem<false>(I, s_scr, I.t + 1);
+}
+
 __global__ void persist_reset_kernel(PersistCtl *pc) {
   if (threadIdx.x == 0) {
     pc->next = 0u;
@@ -179,8 +188,11 @@ int run_grouped(int fmt, const std::vector<GroupSpec> &specs, void *ctl, int lau
   std::vector<GroupInst> back(host);
   for (int it = 0; it < launches;) {
     const int end = std::min(launches, it + check_every);
-    for (; it < end; ++it)
+    for (; it < end; ++it) {
       NSRGS_HIP(launch_group(fmt, dmax, a, (int)units.size(), waves, s), "grouped launch");
+      hipLaunchKernelGGL(group_finish_kernel, dim3((unsigned)host.size()), dim3(256), 0, s, dinst);
+      NSRGS_HIP(hipGetLastError(), "grouped finish");
+    }
     NSRGS_HIP(hipMemcpyAsync(back.data(), dinst, back.size() * sizeof(GroupInst), hipMemcpyDeviceToHost, s),
               "batch readback");
     NSRGS_HIP(hipStreamSynchronize(s), "stream sync");

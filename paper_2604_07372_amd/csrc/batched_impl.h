@@ -7,9 +7,11 @@
 // reduces that problem's monitors, advances its iteration counter and applies
 // its stop rule (tolerance, budget, non-finite).  Two schedules:
 //
-// * grouped: one launch per iteration over every unit.  The iteration barrier
-//   of each problem is the launch boundary; no workgroup waits for another,
-//   so the host enqueues a whole budget of launches without synchronizing.
+// * grouped: per iteration, one launch over every unit and one small launch
+//   (a workgroup per problem) that reduces each problem's monitors and
+//   applies its stop rule.  The iteration barrier of each problem is the
+//   launch boundary; no workgroup waits for another, so the host enqueues a
+//   whole budget of launches without synchronizing.
 // * persistent: one launch for the whole budget.  Workgroups take tickets
 //   from one counter; ticket k is round k / U of unit k mod U (U units per
 //   round), so tickets go out round by round.  Before computing round r of a
@@ -113,7 +115,7 @@ __device__ __forceinline__ void run_panel(int d, const PanelJob &job, char *lds)
 #define NSRGS_BP(DD)                                                            \
   if constexpr (DD <= DMAX)                                                     \
     if (d == DD) {                                                              \
-      panel_compute<FMT, DD, batch_blocks(DD), 0, 0>(job, lds);                 \
+      panel_compute<FMT, DD, batch_blocks(DD), 1, 0>(job, lds);                 \
       return;                                                                   \
     }
   NSRGS_BP(1) NSRGS_BP(2) NSRGS_BP(3) NSRGS_BP(4) NSRGS_BP(5) NSRGS_BP(6) NSRGS_BP(7)
@@ -128,19 +130,24 @@ __device__ __forceinline__ void run_panel(int d, const PanelJob &job, char *lds)
 // workgroup that acquires the new t also sees whether the problem stopped.
 template <bool PUBLISH>
 __device__ inline void finish_problem(GroupInst &I, double *s_scr, int t_new) {
+  (void)s_scr;
   const int tid = threadIdx.x;
+  // Wave 0 alone reduces (fixed 64-lane stride, then a fixed butterfly), so
+  // the monitors are bitwise the same whatever the workgroup size of the
+  // launch that runs this (the grouped and persistent schedules differ).
+  if (tid >= kWave) return;
   double a = 0.0, b = 0.0, m = 0.0, f = 0.0;
-  for (int p = tid; p < I.panels; p += blockDim.x) {
+  for (int p = tid; p < I.panels; p += kWave) {
     const PanelStat q = I.stats[p];
     a += q.dx2;
     b += q.x2;
     m = q.dmax > m ? q.dmax : m;
     f = q.nonfinite > f ? q.nonfinite : f;
   }
-  a = block_sum(a, s_scr);
-  b = block_sum(b, s_scr);
-  m = block_max(m, s_scr);
-  f = block_max(f, s_scr);
+  a = wave_sum(a);
+  b = wave_sum(b);
+  m = wave_max(m);
+  f = wave_max(f);
   if (tid == 0) {
     const double rel = b > 0.0 ? sqrt(a / b) : 0.0;
     I.rel_change = rel;
@@ -167,10 +174,11 @@ __device__ inline void finish_problem(GroupInst &I, double *s_scr, int t_new) {
   }
 }
 
+// Grouped schedule, one launch per iteration: the panels of every active
+// problem.  The per-problem reduction and stop rule run in a second launch
+// (group_finish_kernel), after the kernel boundary has ordered all panel writes.
 template <int FMT, int DMAX>
 __global__ void __launch_bounds__(kWave * kMaxWaves) grouped_kernel(GroupArgs args) {
-  __shared__ double s_scr[kMaxWaves];
-  __shared__ int s_last;
   __shared__ __attribute__((aligned(16))) char lds[batch_lds_bytes<FMT, DMAX>()];
   const GroupUnit unit = args.units[blockIdx.x];
   GroupInst &I = args.inst[unit.inst];
@@ -191,15 +199,6 @@ __global__ void __launch_bounds__(kWave * kMaxWaves) grouped_kernel(GroupArgs ar
   job.stat = I.stats + unit.panel;
   job.gram = nullptr;
   run_panel<FMT, DMAX>(I.d, job, lds);
-  // release: this workgroup's results before its arrival is counted (no L2
-  // invalidate here: a full fence per workgroup keeps evicting the reused X)
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  if (threadIdx.x == 0) s_last = (atomicAdd(&I.arrive, 1u) == (unsigned)I.panels - 1u);
-  __syncthreads();
-  if (s_last) {
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // every other workgroup's results
-    finish_problem<false>(I, s_scr, t + 1);
-  }
 }
 
 // Persistent schedule: one launch for the whole budget (see the top of the file).

@@ -149,20 +149,21 @@ int tuned_batch_waves(int fmt, int dmax) {
 }
 
 StreamConfig choose_stream_config(int fmt, int d, int nd, int mode) {
-  StreamConfig cfg{stream_block_init(d), 1, 0};
+  StreamConfig cfg{stream_block_init(d), 1, 1};
   const int fb = env_int("NSRGS_STEP_B", 0), fu = env_int("NSRGS_STEP_U", -1);
   const bool forced = fb > 0 || fu >= 0 || env_int("NSRGS_STEP_W", 0) > 0;
   if (mode == 0 && !forced && tuned_step(fmt, d, nd, &cfg)) return cfg;
   if (mode == 0) {
     StreamConfig v[16];
     const int nv = stream_variants(d, v, 16);
-    // Default: the software-pipelined loop (U = 0) with the largest panel of
-    // at most 12 rows (every d has a B = 1 pipelined shape).  The autotuner's
-    // table, or the environment (NSRGS_STEP_B/U/W), selects any compiled shape.
+    // Default: one vector per row per iteration (U = 1) with the largest
+    // panel of at most 12 rows (every d has a B = 1, U = 1 shape).  The
+    // autotuner's table, or the environment (NSRGS_STEP_B/U/W), selects any
+    // compiled shape.
     cfg.blocks_per_panel = 1;
-    cfg.unroll = 0;
+    cfg.unroll = 1;
     for (int i = 0; i < nv; ++i)
-      if (v[i].unroll == 0 && v[i].blocks_per_panel * d <= 12 && v[i].blocks_per_panel > cfg.blocks_per_panel)
+      if (v[i].unroll == 1 && v[i].blocks_per_panel * d <= 12 && v[i].blocks_per_panel > cfg.blocks_per_panel)
         cfg.blocks_per_panel = v[i].blocks_per_panel;
     if (fb > 0 || fu >= 0) {
       const int wb = fb > 0 ? fb : cfg.blocks_per_panel, wu = fu >= 0 ? fu : cfg.unroll;

@@ -621,28 +621,28 @@ __global__ void __launch_bounds__(256) stream_finish_kernel(StreamArgs args) {
 }
 
 // ---------------------------------------------------------------------------
-// Instantiation table: (d, B, U) triples, R = B d rows per panel; U = 0 is
-// one 16-byte vector per row per iteration with the next iteration's loads
-// issued before this one's arithmetic (software pipeline), U >= 1 loads U
-// vectors per row together and then accumulates them.  Mode 1 (the
+// Instantiation table: (d, B, U) triples, R = B d rows per panel; U >= 1
+// loads U vectors per row together (X slice first, every load ahead of the
+// arithmetic) and then accumulates them; U = 0 is one vector per row per
+// iteration with the next iteration's loads issued into a second register
+// buffer before this one's arithmetic (software pipeline; it pays only while
+// two buffers fit in registers, so only small d have it).  Mode 1 (the
 // spectral-initialization product) uses the second table.
 // ---------------------------------------------------------------------------
 #define NSRGS_BOPTS(X)                                                                      \
-  X(1, 8, 0) X(1, 16, 0) X(1, 16, 1) X(1, 8, 2)                                            \
-  X(2, 4, 0) X(2, 8, 0) X(2, 8, 1) X(2, 4, 2)                                              \
-  X(3, 4, 0) X(3, 2, 0) X(3, 8, 0) X(3, 8, 1) X(3, 4, 1) X(3, 2, 2) X(3, 4, 2) X(3, 1, 2)  \
-  X(3, 1, 4) X(3, 2, 4)                                                                    \
-  X(4, 2, 0) X(4, 4, 0) X(4, 4, 1) X(4, 2, 2) X(4, 1, 2)                                   \
-  X(5, 1, 0) X(5, 2, 0) X(5, 2, 1) X(6, 1, 0) X(6, 2, 0) X(6, 2, 1)                        \
-  X(7, 1, 0) X(7, 2, 1) X(8, 1, 0) X(8, 2, 1)                                              \
-  X(9, 1, 0) X(9, 1, 1) X(10, 1, 0) X(10, 1, 1) X(11, 1, 0) X(11, 1, 1) X(12, 1, 0)        \
-  X(12, 1, 1) X(13, 1, 0) X(13, 1, 1) X(14, 1, 0) X(14, 1, 1) X(15, 1, 0) X(15, 1, 1)      \
-  X(16, 1, 0) X(16, 1, 1)
+  X(1, 8, 1) X(1, 16, 1) X(1, 8, 0) X(1, 8, 2)                                             \
+  X(2, 4, 1) X(2, 8, 1) X(2, 4, 0) X(2, 4, 2)                                              \
+  X(3, 4, 1) X(3, 2, 1) X(3, 8, 1) X(3, 4, 0) X(3, 2, 2) X(3, 4, 2) X(3, 1, 2) X(3, 1, 4)  \
+  X(3, 2, 4)                                                                               \
+  X(4, 2, 1) X(4, 4, 1) X(4, 2, 0) X(4, 2, 2) X(4, 1, 2)                                   \
+  X(5, 1, 1) X(5, 2, 1) X(6, 1, 1) X(6, 2, 1) X(7, 1, 1) X(7, 2, 1) X(8, 1, 1) X(8, 2, 1)  \
+  X(9, 1, 1) X(10, 1, 1) X(11, 1, 1) X(12, 1, 1) X(13, 1, 1) X(14, 1, 1) X(15, 1, 1)      \
+  X(16, 1, 1)
 
 #define NSRGS_BOPTS_INIT(X)                                                   \
-  X(1, 8, 0) X(2, 4, 0) X(3, 4, 0) X(4, 2, 0) X(5, 1, 0) X(6, 1, 0) X(7, 1, 0) \
-  X(8, 1, 0) X(9, 1, 0) X(10, 1, 0) X(11, 1, 0) X(12, 1, 0) X(13, 1, 0)        \
-  X(14, 1, 0) X(15, 1, 0) X(16, 1, 0)
+  X(1, 8, 1) X(2, 4, 1) X(3, 4, 1) X(4, 2, 1) X(5, 1, 1) X(6, 1, 1) X(7, 1, 1) \
+  X(8, 1, 1) X(9, 1, 1) X(10, 1, 1) X(11, 1, 1) X(12, 1, 1) X(13, 1, 1)        \
+  X(14, 1, 1) X(15, 1, 1) X(16, 1, 1)
 
 template <int MODE, int FMT, int D, int B, int U>
 hipError_t launch_one(const StreamConfig &cfg, const StreamArgs &args, hipStream_t s) {

@@ -61,15 +61,15 @@ def test_install_replaces_overlapping_entries_and_json_round_trip(tmp_path, clea
 
 
 def test_step_variants_cover_every_d():
-    """Every d has shapes, a software-pipelined one (U = 0) for the default, and
-    the batched kernel's panel shape as a single-problem shape (the batched
-    result equals sync_step's with that shape)."""
+    """Every d has shapes, a B = 1, U = 1 one for the default, and the batched
+    kernel's panel shape as a single-problem shape (the batched result equals
+    sync_step's with that shape)."""
     for d in range(1, 17):
         v = P.step_variants(d)
         assert v and all(B >= 1 and U >= 0 for B, U in v)
         assert len(set(v)) == len(v)
-        assert any(U == 0 for _, U in v)
-        assert (P.batch_rows_per_panel(d) // d, 0) in v
+        assert (1, 1) in v or d <= 4
+        assert (P.batch_rows_per_panel(d) // d, 1) in v
     assert P.step_variants(17) == [] and P.step_variants(0) == []
 
 

@@ -33,7 +33,7 @@ def _alone(p, iters, monkeypatch, waves):
     """The same problem through sync_solve with the batched launch's panel shape."""
     rows = P.batch_rows_per_panel(p["d"])
     monkeypatch.setenv("NSRGS_STEP_B", str(rows // p["d"]))
-    monkeypatch.setenv("NSRGS_STEP_U", "0")
+    monkeypatch.setenv("NSRGS_STEP_U", "1")
     monkeypatch.setenv("NSRGS_STEP_W", str(waves))
     X = p["X0"].clone()
     ws = P.workspace(p["n"], p["d"], p["A"].fmt)
