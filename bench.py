@@ -347,6 +347,15 @@ def main(argv=None):
         if ref:
             for name in solve:
                 solve[name]["align_err_rel_vs_f32"] = abs(solve[name]["align_err"] - ref) / ref
+        # BF16 and FP8 solves end with 10 iterations on the FP32 copy, which
+        # brings them to the FP32 solve's accuracy (tests pin this against the
+        # FP64 oracle): their time ratio is the speed-up at equal accuracy.
+        if "f32" in solve:
+            equal_acc = {f"{k}+refine": solve["f32"]["solve_s"] / solve[k]["solve_s"]
+                         for k in ("bf16", "fp8") if k in solve}
+            equal_acc["bf16_split"] = (solve["f32"]["solve_s"] / solve["bf16_split"]["solve_s"]
+                                       if "bf16_split" in solve else None)
+            solve["speedup_vs_f32_at_equal_accuracy"] = equal_acc
 
     stores.clear()
     Am = A32 = None
