@@ -247,6 +247,7 @@ def main(argv=None):
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--formats", default="f32,bf16,bf16_split,fp8")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-symmetric", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-window", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -321,6 +322,37 @@ def main(argv=None):
               f"{results[name]['alg_GBps']:.0f} GB/s (tuned B={tuned['blocks_per_panel']} "
               f"U={tuned['unroll']} W={tuned['waves']})", file=sys.stderr, flush=True)
 
+    # Symmetric half-stream step (sync_step_symmetric): reads only the blocks
+    # above the block diagonal; its algorithmic bytes are those blocks plus X.
+    symmetric = {}
+    if not a.no_symmetric:
+        for name in [f for f in fmts if f in ("f32", "bf16", "bf16_split")]:
+            Am = stores[name]
+            ws = P.workspace(n, d, Am.fmt, symmetric=True)
+            Xa, Xb = X0.clone(), torch.empty_like(X0)
+            for _ in range(a.warmup):
+                P.step_symmetric(Am, n, d, Xa, Xb, ws)
+                Xa, Xb = Xb, Xa
+            torch.cuda.synchronize()
+            start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            start.record()
+            for _ in range(a.steps):
+                P.step_symmetric(Am, n, d, Xa, Xb, ws)
+                Xa, Xb = Xb, Xa
+            end.record()
+            torch.cuda.synchronize()
+            ms = start.elapsed_time(end) / a.steps
+            eb = {"f32": 4, "bf16": 2, "bf16_split": 4}[name]
+            s_bytes = (nd * nd - n * d * d) // 2 * eb + 2 * nd * d * 4
+            symmetric[name] = {"ms_per_step": ms, "iters_per_s": 1e3 / ms, "alg_bytes": s_bytes,
+                               "alg_GBps": s_bytes / (ms * 1e-3) / 1e9,
+                               "speedup_vs_full_stream": results[name]["ms_per_step"] / ms,
+                               "workspace_bytes": ws.nbytes}
+            print(f"[bench] symmetric {name}: {ms:.4f} ms/iter, {1e3 / ms:.1f} it/s, "
+                  f"{symmetric[name]['alg_GBps']:.0f} GB/s, "
+                  f"{symmetric[name]['speedup_vs_full_stream']:.2f}x the full stream", file=sys.stderr, flush=True)
+            del ws
+
     if a.save_tuning:
         autotune.save_table(a.save_tuning)
     solve = {}
@@ -392,6 +424,7 @@ def main(argv=None):
         "formats": {k: {kk: round(vv, 4) if isinstance(vv, float) else vv for kk, vv in r.items()}
                     for k, r in results.items()},
         "speedup_vs_f32": {k: results["f32"]["ms_per_step"] / r["ms_per_step"] for k, r in results.items()},
+        "symmetric_step": symmetric,
         "solve": solve,
         "batched": batched,
         "serving": serving,

@@ -130,6 +130,32 @@ int sync_step(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps,
               const void *X_in, void *X_out, void *ws, size_t ws_bytes,
               void *stream);
 
+/* ---- sync_step_symmetric: sync_step reading half of A ---------------------
+ * The measurement matrix is symmetric, A_ji = A_ij^T (Sec. 2.2), so every
+ * product term of the step is available from the blocks above the block
+ * diagonal.  This call reads only those blocks and uses each element twice,
+ * for C_i += A_ij X_j and for C_j += A_ij^T X_i; the rest of the step is
+ * sync_step's.  An iteration therefore streams about half of A.
+ * The result equals sync_step's up to the order of the additions, provided
+ * the stored A is exactly symmetric.  The generator's output and its BF16 and
+ * hi+lo conversions are.
+ * Values on and below the block diagonal are never used.  Cache lines
+ * near the diagonal may still be loaded, so they must be readable memory;
+ * their contents do not matter.
+ * Formats F64, F32, BF16 and BF16_SPLIT; 1 <= d <= 8.  FP8_E4M3 is refused
+ * with NSRGS_ERR_UNSUPPORTED: its per-row scales make the stored A_ij and
+ * A_ji differ.
+ * ws must hold sync_step_symmetric_workspace_bytes(n, d, fmt) bytes: the
+ * sync_step workspace followed by the per-tile partial sums, about
+ * (n d)^2 d (1/H + 1/CW) accumulator values, with strip height H ~ 384 and
+ * chunk width CW = 256 V.  It is prepared by sync_workspace_init, and
+ * sync_read_info reads the monitors as after sync_step.
+ * The call returns 0 bytes for unsupported (n, d, fmt).  It is asynchronous. */
+size_t sync_step_symmetric_workspace_bytes(int n, int d, int fmt);
+int sync_step_symmetric(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps,
+                        const void *X_in, void *X_out, void *ws, size_t ws_bytes,
+                        void *stream);
+
 /* Copy the monitors of the last step / init on this workspace to *info
  * (waits for `stream`). */
 int sync_read_info(const void *ws, size_t ws_bytes, int n, int d, int fmt,

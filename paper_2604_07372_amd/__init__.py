@@ -17,7 +17,7 @@ __all__ = [
     "lib", "StoredMatrix", "Workspace", "workspace", "step", "read_info",
     "init_spectral", "solve", "generate", "convert", "stored", "padded_ld",
     "Info", "solve_batched", "batch_rows_per_panel", "set_tuning", "get_tuning", "TuneEntry", "Server",
-    "step_variants", "TuneResult",
+    "step_variants", "TuneResult", "step_symmetric", "symmetric_workspace_bytes",
 ]
 
 F64, F32, BF16, BF16_SPLIT, FP8_E4M3 = 0, 1, 2, 3, 4
@@ -133,6 +133,8 @@ def lib() -> ctypes.CDLL:
         "sync_workspace_bytes": (sz, [i32, i32, i32]),
         "sync_workspace_init": (i32, [vp, sz, vp]),
         "sync_step": (i32, [pm, i32, i32, dbl, i32, vp, vp, vp, sz, vp]),
+        "sync_step_symmetric_workspace_bytes": (sz, [i32, i32, i32]),
+        "sync_step_symmetric": (i32, [pm, i32, i32, dbl, i32, vp, vp, vp, sz, vp]),
         "sync_read_info": (i32, [vp, sz, i32, i32, i32, ctypes.POINTER(Info), vp]),
         "sync_init_spectral": (i32, [pm, i32, i32, vp, i32, dbl, vp, sz, vp, ctypes.POINTER(Info)]),
         "sync_solve": (i32, [pm, i32, i32, dbl, i32, i32, dbl, vp, vp, sz, vp,
@@ -260,8 +262,9 @@ def stored(A: torch.Tensor, fmt: int = F32) -> StoredMatrix:
 class Workspace:
     """Device workspace for one (n, d, precision) problem; prepared on creation."""
 
-    def __init__(self, n: int, d: int, fmt: int, device="cuda"):
-        nbytes = lib().sync_workspace_bytes(n, d, fmt)
+    def __init__(self, n: int, d: int, fmt: int, device="cuda", symmetric: bool = False):
+        nbytes = (lib().sync_step_symmetric_workspace_bytes(n, d, fmt) if symmetric
+                  else lib().sync_workspace_bytes(n, d, fmt))
         if nbytes == 0:
             raise NsrgsError(1, f"invalid workspace request n={n} d={d} fmt={fmt}")
         buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
@@ -277,8 +280,9 @@ class Workspace:
         return self.tensor.data_ptr()
 
 
-def workspace(n: int, d: int, fmt: int, device="cuda") -> Workspace:
-    return Workspace(n, d, fmt, device)
+def workspace(n: int, d: int, fmt: int, device="cuda", symmetric: bool = False) -> Workspace:
+    """symmetric=True sizes it for step_symmetric (which also serves every other call)."""
+    return Workspace(n, d, fmt, device, symmetric)
 
 
 def _xdtype(fmt: int):
@@ -298,6 +302,21 @@ def step(A: StoredMatrix, n: int, d: int, X_in: torch.Tensor, X_out: torch.Tenso
     m = A.c()
     _check(lib().sync_step(ctypes.byref(m), n, d, float(mu), int(ns_steps), X_in.data_ptr(),
                            X_out.data_ptr(), ws.ptr, ws.nbytes, _stream()))
+
+
+def step_symmetric(A: StoredMatrix, n: int, d: int, X_in: torch.Tensor, X_out: torch.Tensor,
+                   ws: Workspace, mu: float = 0.0, ns_steps: int = 3) -> None:
+    """sync_step_symmetric: the iteration from the blocks above the block diagonal
+    only (A must be exactly symmetric); ws from workspace(..., symmetric=True)."""
+    _check_x(X_in, n * d, d, A.fmt, "X_in")
+    _check_x(X_out, n * d, d, A.fmt, "X_out")
+    m = A.c()
+    _check(lib().sync_step_symmetric(ctypes.byref(m), n, d, float(mu), int(ns_steps), X_in.data_ptr(),
+                                     X_out.data_ptr(), ws.ptr, ws.nbytes, _stream()))
+
+
+def symmetric_workspace_bytes(n: int, d: int, fmt: int) -> int:
+    return int(lib().sync_step_symmetric_workspace_bytes(n, d, fmt))
 
 
 def read_info(ws: Workspace) -> dict:

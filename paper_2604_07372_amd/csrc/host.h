@@ -63,6 +63,12 @@ int step_with_config(const nsrgs_matrix *A, int n, int d, double mu, int ns_step
 int check_step_args(const nsrgs_matrix *A, int n, int d, int ns_steps, const void *X_in, void *X_out,
                     void *ws, size_t ws_bytes);
 
+// Bytes of the single-problem workspace (control block, panel monitors,
+// iterate and initialization buffers) and the offset of its panel monitors
+// (runtime.hip).
+size_t step_ws_bytes(int n, int d, int fmt);
+size_t step_ws_stats_offset(int n, int d, int fmt);
+
 // Tuning table (runtime.hip): waves per workgroup of the grouped launch.
 int tuned_batch_waves(int fmt, int dmax);
 

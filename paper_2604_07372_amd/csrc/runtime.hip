@@ -276,6 +276,9 @@ int sync_step(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, cons
 }  // extern "C"
 
 namespace nsrgs {
+size_t step_ws_bytes(int n, int d, int fmt) { return layout(n, d, fmt).total; }
+size_t step_ws_stats_offset(int n, int d, int fmt) { return layout(n, d, fmt).stats; }
+
 // sync_step with a given launch shape (the autotuner's timing loop); the
 // arguments must already have passed sync_step's checks.
 int step_with_config(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,

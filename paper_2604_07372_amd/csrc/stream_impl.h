@@ -231,6 +231,103 @@ __device__ __forceinline__ void fma_group(typename Fmt<FMT>::acc_t (&acc)[R][D],
   }
 }
 
+// Per-block Riemannian step and Newton-Schulz retraction of B blocks whose
+// C_i (sum over j != i of A_ij X_j) and X_i are in LDS (sC, sX: B d x d
+// entries, row-major per block); sG, sT, sF, sM are LDS scratch of the same
+// size.  Writes X^{t+1} for rows row0 .. row0 + B d - 1 (those below nd) and
+// the blocks' monitors to *stat.  Every thread of the workgroup calls it.
+template <typename T, int D, int B>
+__device__ __forceinline__ void block_step_epilogue(int n, double mu_d, int ns_steps, int nd, int row0,
+                                                    T *__restrict__ Xo, PanelStat *stat, T *sX, T *sC,
+                                                    T *sG, T *sT, T *sF, T *sM, double *s_scr) {
+  constexpr int NE = B * D * D;
+  const int tid = threadIdx.x;
+  // ---- fused per-block Riemannian step and Newton-Schulz retraction ----
+  const T nm1 = T(n - 1);
+  const T mu = T(mu_d);
+  for (int e = tid; e < NE; e += blockDim.x) sG[e] = nm1 * sX[e] - sC[e];
+  __syncthreads();
+  // sT = G^T X  (per block)
+  for (int e = tid; e < NE; e += blockDim.x) {
+    const int bb = (e / (D * D)) * D * D, a = (e / D) % D, k = e % D;
+    T s = 0;
+#pragma unroll
+    for (int m = 0; m < D; ++m) s = fmaT(sG[bb + m * D + a], sX[bb + m * D + k], s);
+    sT[e] = s;
+  }
+  __syncthreads();
+  // F = X - mu (G - X (G^T X)) / 2
+  for (int e = tid; e < NE; e += blockDim.x) {
+    const int bb = (e / (D * D)) * D * D, a = (e / D) % D, k = e % D;
+    T s = 0;
+#pragma unroll
+    for (int m = 0; m < D; ++m) s = fmaT(sX[bb + a * D + m], sT[bb + m * D + k], s);
+    const T P = T(0.5) * (sG[e] - s);
+    sF[e] = sX[e] - mu * P;
+  }
+  __syncthreads();
+  T *cur = sF;
+  T *nxt = sT;
+  const int steps = ns_steps;
+  for (int st = 0; st < (steps > 0 ? steps : 1); ++st) {
+    // M = S^T S
+    for (int e = tid; e < NE; e += blockDim.x) {
+      const int bb = (e / (D * D)) * D * D, a = (e / D) % D, k = e % D;
+      T s = 0;
+#pragma unroll
+      for (int m = 0; m < D; ++m) s = fmaT(cur[bb + m * D + a], cur[bb + m * D + k], s);
+      sM[e] = s;
+      if (st == 0) {
+        const T dlt = (a == k ? T(1) : T(0)) - s;
+        sC[e] = dlt * dlt;                       // defect terms of F^T F
+      }
+    }
+    __syncthreads();
+    if (st < steps) {
+      // S <- 1.5 S - 0.5 S M
+      for (int e = tid; e < NE; e += blockDim.x) {
+        const int bb = (e / (D * D)) * D * D, a = (e / D) % D, k = e % D;
+        T s = 0;
+#pragma unroll
+        for (int m = 0; m < D; ++m) s = fmaT(cur[bb + a * D + m], sM[bb + m * D + k], s);
+        nxt[e] = T(1.5) * cur[e] - T(0.5) * s;
+      }
+      __syncthreads();
+      T *tmp = cur;
+      cur = nxt;
+      nxt = tmp;
+    }
+  }
+  // ---- write X^{t+1} and the panel monitors ------------------------------
+  double dx2 = 0.0, x2 = 0.0, dmax = 0.0;
+  int nonfin = 0;
+  for (int e = tid; e < NE; e += blockDim.x) {
+    const int row = row0 + e / D;
+    if (row < nd) {
+      const T v = cur[e];
+      Xo[(int64_t)row * D + (e % D)] = v;
+      const double dv = (double)v - (double)sX[e];
+      dx2 += dv * dv;
+      x2 += (double)sX[e] * (double)sX[e];
+      nonfin |= !isfinite(v);
+    }
+  }
+  for (int b = tid; b < B; b += blockDim.x) {
+    if (row0 + b * D < nd) {
+      double s = 0.0;
+      for (int j = 0; j < D * D; ++j) s += (double)sC[b * D * D + j];
+      const double df = sqrt(s);
+      dmax = df > dmax ? df : dmax;
+      nonfin |= !isfinite(df);
+    }
+  }
+  dx2 = block_sum(dx2, s_scr);
+  x2 = block_sum(x2, s_scr);
+  dmax = block_max(dmax, s_scr);
+  const double nf = block_max((double)nonfin, s_scr);
+  if (tid == 0) *stat = PanelStat{dx2, x2, dmax, nf};
+}
+
 // One panel of R = B d rows: what one workgroup does per column sweep.
 struct PanelJob {
   const void *A;          // storage of this problem's A
@@ -388,91 +485,8 @@ __device__ __forceinline__ void panel_compute(const PanelJob &job, char *lds) {
   __syncthreads();
 
   if constexpr (MODE == 0) {
-    // ---- fused per-block Riemannian step and Newton-Schulz retraction ----
-    const T nm1 = T(job.n - 1);
-    const T mu = T(job.mu);
-    for (int e = tid; e < NE; e += blockDim.x) sG[e] = nm1 * sX[e] - sC[e];
-    __syncthreads();
-    // sT = G^T X  (per block)
-    for (int e = tid; e < NE; e += blockDim.x) {
-      const int bb = (e / (D * D)) * D * D, a = (e / D) % D, k = e % D;
-      T s = 0;
-#pragma unroll
-      for (int m = 0; m < D; ++m) s = fmaT(sG[bb + m * D + a], sX[bb + m * D + k], s);
-      sT[e] = s;
-    }
-    __syncthreads();
-    // F = X - mu (G - X (G^T X)) / 2
-    for (int e = tid; e < NE; e += blockDim.x) {
-      const int bb = (e / (D * D)) * D * D, a = (e / D) % D, k = e % D;
-      T s = 0;
-#pragma unroll
-      for (int m = 0; m < D; ++m) s = fmaT(sX[bb + a * D + m], sT[bb + m * D + k], s);
-      const T P = T(0.5) * (sG[e] - s);
-      sF[e] = sX[e] - mu * P;
-    }
-    __syncthreads();
-    T *cur = sF;
-    T *nxt = sT;
-    const int steps = job.ns_steps;
-    for (int st = 0; st < (steps > 0 ? steps : 1); ++st) {
-      // M = S^T S
-      for (int e = tid; e < NE; e += blockDim.x) {
-        const int bb = (e / (D * D)) * D * D, a = (e / D) % D, k = e % D;
-        T s = 0;
-#pragma unroll
-        for (int m = 0; m < D; ++m) s = fmaT(cur[bb + m * D + a], cur[bb + m * D + k], s);
-        sM[e] = s;
-        if (st == 0) {
-          const T dlt = (a == k ? T(1) : T(0)) - s;
-          sC[e] = dlt * dlt;                       // defect terms of F^T F
-        }
-      }
-      __syncthreads();
-      if (st < steps) {
-        // S <- 1.5 S - 0.5 S M
-        for (int e = tid; e < NE; e += blockDim.x) {
-          const int bb = (e / (D * D)) * D * D, a = (e / D) % D, k = e % D;
-          T s = 0;
-#pragma unroll
-          for (int m = 0; m < D; ++m) s = fmaT(cur[bb + a * D + m], sM[bb + m * D + k], s);
-          nxt[e] = T(1.5) * cur[e] - T(0.5) * s;
-        }
-        __syncthreads();
-        T *tmp = cur;
-        cur = nxt;
-        nxt = tmp;
-      }
-    }
-    // ---- write X^{t+1} and the panel monitors ------------------------------
-    T *__restrict__ Xo = static_cast<T *>(job.X_out);
-    double dx2 = 0.0, x2 = 0.0, dmax = 0.0;
-    int nonfin = 0;
-    for (int e = tid; e < NE; e += blockDim.x) {
-      const int row = row0 + e / D;
-      if (row < nd) {
-        const T v = cur[e];
-        Xo[(int64_t)row * D + (e % D)] = v;
-        const double dv = (double)v - (double)sX[e];
-        dx2 += dv * dv;
-        x2 += (double)sX[e] * (double)sX[e];
-        nonfin |= !isfinite(v);
-      }
-    }
-    for (int b = tid; b < B; b += blockDim.x) {
-      if (row0 + b * D < nd) {
-        double s = 0.0;
-        for (int j = 0; j < D * D; ++j) s += (double)sC[b * D * D + j];
-        const double df = sqrt(s);
-        dmax = df > dmax ? df : dmax;
-        nonfin |= !isfinite(df);
-      }
-    }
-    dx2 = block_sum(dx2, s_scr);
-    x2 = block_sum(x2, s_scr);
-    dmax = block_max(dmax, s_scr);
-    const double nf = block_max((double)nonfin, s_scr);
-    if (tid == 0) *job.stat = PanelStat{dx2, x2, dmax, nf};
+    block_step_epilogue<T, D, B>(job.n, job.mu, job.ns_steps, nd, row0, static_cast<T *>(job.X_out),
+                                 job.stat, sX, sC, sG, sT, sF, sM, s_scr);
   } else {
     // ---- mode 1: W = A Y for the panel rows; partial Grams Y^T W, W^T W ----
     T *__restrict__ Wo = static_cast<T *>(job.X_out);

@@ -1,0 +1,327 @@
+// Symmetric half-stream step (the symmetric measurement matrix, Sec. 2.2:
+// A_ji = A_ij^T).  Only the blocks above the block diagonal are streamed, and
+// each element is used twice: C_i += A_ij X_j (row direction) and
+// C_j += A_ij^T X_i (column direction), so one iteration reads about half of A.
+//
+// Work is cut into tiles: strips of H rows (a multiple of d) by chunks of
+// CW = W * 64 * V * U columns, the tiles on or above the block diagonal.  In a
+// tile each lane owns U column vectors for the whole strip and walks the
+// strip's rows in panels of R rows:
+//   * column direction: the lane's V x d sums over the strip's rows stay in
+//     registers (X_i of the panel rows is wave-uniform);
+//   * row direction: the R x d per-lane sums of a panel are reduced over the
+//     wave by a transpose-reduce and kept in LDS per wave.
+// At the end of the tile the row sums (H x d) go to prow[chunk] and the column
+// sums (CW x d) to pcol[strip].  A second kernel adds, for each row, the row
+// sums of its strip's tiles and the column sums of the tiles above it in its
+// column, in a fixed order, and runs the per-block epilogue.  Elements on or
+// below the block diagonal, or past nd, are masked with selects (no divergent
+// branch), and only diagonal and ragged tiles take the masked path.
+#pragma once
+
+#include <limits.h>
+
+#include "stream_impl.h"
+
+namespace nsrgs {
+
+struct SymArgs {
+  const void *A;
+  const void *A_lo;
+  int64_t ld;
+  const void *X_in;
+  int nd;
+  int H;          // strip height (rows), a multiple of d, of R and of the epilogue panel
+  int CW;         // chunk width (columns) = waves * 64 * V * U
+  int nchunks;
+  int nstrips;
+  void *prow;     // nchunks x nd x d: row sums of tile (strip(r), chunk) at row r
+  void *pcol;     // nstrips x nd x d: column sums of tile (strip, chunk(c)) at column c
+};
+
+// Panel rows of the tile kernel and blocks per epilogue workgroup, per d.
+constexpr int sym_rows(int d) { return d <= 2 ? 16 : d <= 4 ? 12 : d == 5 ? 10 : d == 6 ? 8 : d == 7 ? 7 : 8; }
+constexpr int sym_epi_blocks(int d) { return d == 1 ? 64 : d == 2 ? 32 : d <= 4 ? 16 : d == 5 ? 8 : d == 6 ? 6 : 4; }
+constexpr int kSymMaxD = 8;
+
+// ---- transpose-reduce over the 64 lanes of a wave ------------------------
+// Each of 6 steps pairs lanes that differ in one bit: one lane of the pair
+// keeps the lower half of its values, the other the upper half, and each adds
+// the partner's copy of what it keeps (an odd middle value is kept and summed
+// by both).  After the last step every value a lane holds is the full 64-lane
+// sum of one entry; sym_tr_entry gives which.  The additions are in a fixed
+// order, and lanes holding the same entry hold bitwise equal sums.
+constexpr int sym_tr_count(int m, int steps) {
+  return steps == 0 ? m : sym_tr_count(m / 2 + (m & 1), steps - 1);
+}
+
+template <typename T, int M, int STEP>
+__device__ __forceinline__ void sym_tr_step(T *v, int lane) {
+  if constexpr (STEP < 6) {
+    constexpr int off = 32 >> STEP;
+    constexpr int h = M / 2;
+    const bool hi = (lane & off) != 0;
+#pragma unroll
+    for (int i = 0; i < h; ++i) {
+      const T keep = hi ? v[h + i] : v[i];
+      const T send = hi ? v[i] : v[h + i];
+      v[i] = keep + __shfl_xor(send, off, kWave);
+    }
+    if constexpr (M & 1) v[h] = v[M - 1] + __shfl_xor(v[M - 1], off, kWave);
+    sym_tr_step<T, h + (M & 1), STEP + 1>(v, lane);
+  }
+}
+
+// For N <= 64 each lane ends with one value; the entry it holds, found by
+// walking the steps backwards from position 0 (a value at position p < h
+// after a step came from p, or from h + p in the lane that kept the upper
+// half; the odd middle value came from the last position).
+template <int N>
+__device__ __forceinline__ int sym_tr_entry(int lane) {
+  static_assert(sym_tr_count(N, 6) == 1, "one value per lane after the reduction");
+  int p = 0;
+#pragma unroll
+  for (int st = 5; st >= 0; --st) {
+    const int m = sym_tr_count(N, st);
+    const int h = m / 2;
+    const bool hi = ((lane >> (5 - st)) & 1) != 0;
+    p = p < h ? (hi ? h + p : p) : m - 1;
+  }
+  return p;
+}
+
+// The rows [strip0, strip1) of one tile for this wave's columns.
+template <int FMT, int D, int R, int U, bool MASK>
+__device__ __forceinline__ void sym_tile_rows(const SymArgs &a, int strip0, int strip1, int lane, int cw0,
+                                              const int (&col)[U],
+                                              const typename Fmt<FMT>::acc_t (&xc)[U][Fmt<FMT>::V][D],
+                                              typename Fmt<FMT>::acc_t (&cacc)[U][Fmt<FMT>::V][D],
+                                              typename Fmt<FMT>::acc_t *myrow) {
+  using T = typename Fmt<FMT>::acc_t;
+  constexpr int V = Fmt<FMT>::V;
+  constexpr int EB = elem_bytes<FMT>();
+  constexpr int N = R * D;
+  constexpr int WCOLS = kWave * V * U;
+  const int nd = a.nd;
+  const char *__restrict__ Ab = static_cast<const char *>(a.A);
+  const char *__restrict__ Alo = static_cast<const char *>(a.A_lo);
+  const T *__restrict__ X = static_cast<const T *>(a.X_in);
+
+  const int ridx = sym_tr_entry<N>(lane);
+
+  // masked path: block index of each column (-1 past nd, so nothing counts)
+  int cblk[U][V];
+  int cc[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    cc[u] = (!MASK || col[u] < nd) ? col[u] : 0;   // clamped load column
+#pragma unroll
+    for (int v = 0; v < V; ++v) cblk[u][v] = (col[u] + v < nd) ? (col[u] + v) / D : -1;
+  }
+  // wave-uniform: the block of this wave's last column inside the matrix
+  const int wlast_blk = cw0 < nd ? (min(cw0 + WCOLS, nd) - 1) / D : -1;
+
+  for (int row0 = strip0; row0 < strip1; row0 += R) {
+    T *out = myrow + (row0 - strip0) * D;
+    if (MASK && row0 / D >= wlast_blk) {
+      // every element of this panel in this wave's columns is on or below the
+      // block diagonal (or past nd): its sums are zero
+      static_assert(N <= kWave, "one lane per panel entry");
+      out[lane < N ? lane : N - 1] = T(0);
+      continue;
+    }
+    int64_t rowoff[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int row = (!MASK || row0 + r < nd) ? row0 + r : nd - 1;
+      rowoff[r] = (int64_t)row * a.ld * EB;
+    }
+    uint4 raw[R][U], rawlo[R][U];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        raw[r][u] = ld16_stream(Ab + rowoff[r] + (int64_t)cc[u] * EB);
+        if constexpr (FMT == NSRGS_A_BF16_SPLIT) rawlo[r][u] = ld16_stream(Alo + rowoff[r] + (int64_t)cc[u] * EB);
+        else rawlo[r][u] = make_uint4(0, 0, 0, 0);
+      }
+    T xr[R][D];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int row = (!MASK || row0 + r < nd) ? row0 + r : nd - 1;
+#pragma unroll
+      for (int k = 0; k < D; ++k) xr[r][k] = X[(int64_t)row * D + k];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+
+    T acc[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[i] = T(0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int rblk = (row0 + r < nd) ? (row0 + r) / D : INT_MAX;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        T av[V];
+        expand<FMT>(raw[r][u], rawlo[r][u], av);
+        if constexpr (MASK) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) av[v] = (rblk < cblk[u][v]) ? av[v] : T(0);
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            acc[r * D + k] = fmaT(av[v], xc[u][v][k], acc[r * D + k]);
+            cacc[u][v][k] = fmaT(av[v], xr[r][k], cacc[u][v][k]);
+          }
+      }
+    }
+    sym_tr_step<T, N, 0>(acc, lane);
+    out[ridx] = acc[0];
+  }
+}
+
+// One tile per workgroup: blockIdx.x = chunk, blockIdx.y = strip; tiles left
+// of the strip's diagonal chunk return at once.  Dynamic LDS: waves * H * d
+// values of the accumulation type.
+template <int FMT, int D, int R, int U>
+__global__ void __launch_bounds__(kWave * kMaxWaves) sym_tile_kernel(SymArgs a) {
+  using T = typename Fmt<FMT>::acc_t;
+  constexpr int V = Fmt<FMT>::V;
+  constexpr int WCOLS = kWave * V * U;
+  extern __shared__ __attribute__((aligned(16))) char sym_lds[];
+  const int j = blockIdx.x, s = blockIdx.y;
+  const int nd = a.nd, H = a.H, CW = a.CW;
+  const int strip0 = s * H;
+  if (j < strip0 / CW) return;                     // uniform
+  const int strip1 = min(strip0 + H, nd);
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+  const int nw = blockDim.x / kWave;
+  const int cw0 = j * CW + wave * WCOLS;
+  T *s_row = reinterpret_cast<T *>(sym_lds);
+  T *myrow = s_row + (int64_t)wave * H * D;
+  const T *__restrict__ X = static_cast<const T *>(a.X_in);
+
+  int col[U];
+  T xc[U][V][D], cacc[U][V][D];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    col[u] = cw0 + u * kWave * V + lane * V;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int c = col[u] + v;
+      const int cl = c < nd ? c : nd - 1;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const T x = X[(int64_t)cl * D + k];
+        xc[u][v][k] = c < nd ? x : T(0);
+        cacc[u][v][k] = T(0);
+      }
+    }
+  }
+  // masked path for tiles that reach the block diagonal or the matrix edge
+  const bool mask = (j * CW) / D <= (strip1 - 1) / D || (j + 1) * CW > nd || strip0 + H > nd;
+  if (mask) sym_tile_rows<FMT, D, R, U, true>(a, strip0, strip1, lane, cw0, col, xc, cacc, myrow);
+  else sym_tile_rows<FMT, D, R, U, false>(a, strip0, strip1, lane, cw0, col, xc, cacc, myrow);
+  __syncthreads();
+
+  // row sums: the waves' partials added in wave order
+  T *__restrict__ prow = static_cast<T *>(a.prow) + ((int64_t)j * nd + strip0) * D;
+  const int nrow = (strip1 - strip0) * D;
+  for (int e = tid; e < nrow; e += blockDim.x) {
+    T v = s_row[e];
+    for (int w = 1; w < nw; ++w) v += s_row[(int64_t)w * H * D + e];
+    prow[e] = v;
+  }
+  // column sums of this lane's columns
+  T *__restrict__ pcol = static_cast<T *>(a.pcol) + (int64_t)s * nd * D;
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int c = col[u] + v;
+      if (c < nd) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) pcol[(int64_t)c * D + k] = cacc[u][v][k];
+      }
+    }
+}
+
+// One workgroup per BE blocks: C for each row = the row sums of the tiles of
+// its strip (chunks in order) + the column sums of the tiles above it in its
+// column (strips in order), then the per-block epilogue of the step.
+template <int FMT, int D, int BE>
+__global__ void __launch_bounds__(256) sym_epilogue_kernel(SymArgs a, StreamArgs sa) {
+  using T = typename Fmt<FMT>::acc_t;
+  constexpr int NE = BE * D * D;
+  __shared__ double s_scr[kMaxWaves];
+  __shared__ T sbuf[6 * NE];
+  if (sa.stop_flag) {
+    if (__atomic_load_n(sa.stop_flag, __ATOMIC_RELAXED)) return;   // uniform
+  }
+  const int tid = threadIdx.x;
+  const int nd = a.nd;
+  const int row0 = blockIdx.x * BE * D;
+  const int s = row0 / a.H;                 // BE d divides H: one strip per workgroup
+  const int j0 = (s * a.H) / a.CW;
+  T *sX = sbuf, *sC = sX + NE, *sG = sC + NE, *sT = sG + NE, *sF = sT + NE, *sM = sF + NE;
+  const T *__restrict__ prow = static_cast<const T *>(a.prow);
+  const T *__restrict__ pcol = static_cast<const T *>(a.pcol);
+  const T *__restrict__ X = static_cast<const T *>(sa.X_in);
+  const int64_t plane = (int64_t)nd * D;
+  for (int e = tid; e < NE; e += blockDim.x) {
+    const int row = row0 + e / D;
+    const int rr = row < nd ? row : nd - 1;
+    const int64_t o = (int64_t)rr * D + (e % D);
+    T sum = T(0);
+    for (int jj = j0; jj < a.nchunks; ++jj) sum += prow[jj * plane + o];
+    for (int ss = 0; ss <= s; ++ss) sum += pcol[ss * plane + o];
+    const T x = X[o];
+    sC[e] = row < nd ? sum : T(0);
+    sX[e] = row < nd ? x : T(0);
+  }
+  __syncthreads();
+  block_step_epilogue<T, D, BE>(sa.n, sa.mu, sa.ns_steps, nd, row0, static_cast<T *>(sa.X_out),
+                                static_cast<PanelStat *>(sa.partials) + blockIdx.x, sX, sC, sG, sT, sF,
+                                sM, s_scr);
+}
+
+template <int FMT, int D, int U>
+hipError_t sym_launch_d(const SymArgs &a, const StreamArgs &sa, int waves, hipStream_t s) {
+  using T = typename Fmt<FMT>::acc_t;
+  constexpr int R = sym_rows(D);
+  constexpr int BE = sym_epi_blocks(D);
+  const size_t lds = (size_t)waves * a.H * D * sizeof(T);
+  hipLaunchKernelGGL((sym_tile_kernel<FMT, D, R, U>), dim3(a.nchunks, a.nstrips), dim3(kWave * waves), lds,
+                     s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((sym_epilogue_kernel<FMT, D, BE>), dim3(sa.num_panels), dim3(256), 0, s, a, sa);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((stream_finish_kernel<T, D, 0>), dim3(1), dim3(256), 0, s, sa);
+  return hipGetLastError();
+}
+
+// Dispatch over d (1 .. kSymMaxD) for one format.
+template <int FMT>
+hipError_t sym_launch_fmt(int d, int unroll, const SymArgs &a, const StreamArgs &sa, int waves,
+                          hipStream_t s) {
+  if (unroll != 1) return hipErrorInvalidValue;
+  switch (d) {
+    case 1: return sym_launch_d<FMT, 1, 1>(a, sa, waves, s);
+    case 2: return sym_launch_d<FMT, 2, 1>(a, sa, waves, s);
+    case 3: return sym_launch_d<FMT, 3, 1>(a, sa, waves, s);
+    case 4: return sym_launch_d<FMT, 4, 1>(a, sa, waves, s);
+    case 5: return sym_launch_d<FMT, 5, 1>(a, sa, waves, s);
+    case 6: return sym_launch_d<FMT, 6, 1>(a, sa, waves, s);
+    case 7: return sym_launch_d<FMT, 7, 1>(a, sa, waves, s);
+    case 8: return sym_launch_d<FMT, 8, 1>(a, sa, waves, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace nsrgs

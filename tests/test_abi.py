@@ -1,6 +1,7 @@
 """The C-ABI library loads, exports every declared symbol, and rejects bad
 arguments on the host before touching a device (CPU only)."""
 import ctypes
+import math
 import os
 import re
 
@@ -109,3 +110,36 @@ def test_solve_and_init_reject_before_device_use():
     assert L.nsrgs_generate_measurement(16, 100, 3, 1.0, 0, 0, 1.0, P.BF16, 16, 304, None) == 1
     out = P._Matrix(P.F32, 16, None, None, 304)
     assert L.nsrgs_convert(16, 300, 304, ctypes.byref(out), None) == 1
+
+
+def test_symmetric_step_workspace_and_refusals():
+    """sync_step_symmetric: workspace sizes from the tile shape (the partial sums
+    grow like (n d)^2 d / H), and every refusal happens on the host."""
+    L = P.lib()
+    assert L.sync_step_symmetric_workspace_bytes(100, 9, P.F32) == 0          # d <= 8
+    assert L.sync_step_symmetric_workspace_bytes(100, 3, P.FP8_E4M3) == 0     # not symmetric storage
+    assert L.sync_step_symmetric_workspace_bytes(1, 3, P.F32) == 0
+    n, d = 20000, 3
+    base = L.sync_workspace_bytes(n, d, P.F32)
+    sym = L.sync_step_symmetric_workspace_bytes(n, d, P.F32)
+    nd = n * d
+    # strips of 384 rows and chunks of 1024 columns at the default shape
+    parts = (math.ceil(nd / 384) + math.ceil(nd / 1024)) * nd * d * 4
+    assert parts <= sym - base <= parts + 1024
+    assert sym - base < 0.02 * nd * nd * 4        # small next to the A it replaces reading
+    m = _mat()
+    ws_bytes = L.sync_step_symmetric_workspace_bytes(100, 3, P.F32)
+    # FP8 is refused as unsupported, after the common checks
+    f8 = P._Matrix(P.FP8_E4M3, 16, None, 32, 304)
+    st = L.sync_step_symmetric(ctypes.byref(f8), 100, 3, 0.0, 3, 4096, 1 << 20, 256, ws_bytes, None)
+    assert st == 2 and "FP8" in L.nsrgs_last_error().decode()
+    # d > 8 is unsupported; the sync_step workspace alone is too small
+    st = L.sync_step_symmetric(ctypes.byref(m), 30, 10, 0.0, 3, 4096, 1 << 20, 256, 1 << 30, None)
+    assert st == 2
+    st = L.sync_step_symmetric(ctypes.byref(m), 100, 3, 0.0, 3, 4096, 1 << 20, 256,
+                               L.sync_workspace_bytes(100, 3, P.F32), None)
+    assert st == 3 and "sync_step_symmetric" in L.nsrgs_last_error().decode()
+    # the common checks (aliasing, mu)
+    assert L.sync_step_symmetric(ctypes.byref(m), 100, 3, 0.0, 3, 4096, 4096 + 64, 256, ws_bytes, None) == 1
+    assert L.sync_step_symmetric(ctypes.byref(m), 100, 3, float("inf"), 3, 4096, 1 << 20, 256, ws_bytes,
+                                 None) == 1

@@ -63,6 +63,33 @@ def test_fullsize_step_sampled_blocks(big, fmt):
     del Am
 
 
+@pytest.mark.parametrize("fmt", [P.F32, P.BF16], ids=lambda f: FMT_NAME[f])
+def test_fullsize_symmetric_step_sampled_blocks(big, fmt):
+    """sync_step_symmetric at full size, in the shape bench.py times, on the
+    same sampled blocks."""
+    Am = P.stored(big["A32"], P.F32) if fmt == P.F32 else P.convert(big["A32"], fmt)
+    Xin = torch.from_numpy(big["X"]).cuda()
+    Xout = torch.empty_like(Xin)
+    ws = P.workspace(N, D, fmt, symmetric=True)
+    P.step_symmetric(Am, N, D, Xin, Xout, ws)
+    torch.cuda.synchronize()
+    Xo = host(Xout)
+    Xh = big["X"].astype(np.float64)
+    rows_stored = _stored_rows(big["A_rows"], fmt)
+    tol = step_tolerance(rows_stored, Xh, N, fmt)
+    worst = 0.0
+    for k, i in enumerate(big["blocks"]):
+        ref = O.block_step(rows_stored[k * D:(k + 1) * D], Xh, D, int(i), Ts=3)
+        worst = max(worst, float(np.abs(Xo[i * D:(i + 1) * D] - ref).max()))
+    print(f"full size symmetric {FMT_NAME[fmt]}: worst sampled-block error {worst:.2e} (bound {tol:.2e})",
+          flush=True)
+    assert worst <= tol
+    info = P.read_info(ws)
+    assert info["nonfinite"] == 0
+    del ws, Am
+    torch.cuda.empty_cache()
+
+
 def test_fullsize_solve_invariants(big):
     """A full FP32 solve (spectral init + 200 iterations): orthogonal blocks, the
     first-order error level, and a stationary point (tangent gradient ~ 0 on
