@@ -375,6 +375,23 @@ def main(argv=None):
                            "refine_iters": kw.get("refine_iters", 0)}
             print(f"[bench] solve {name}: {dt:.3f} s, align err {e:.6f} (first-order {pred:.6f})",
                   file=sys.stderr, flush=True)
+        # the same solves with every iteration on the symmetric half-stream
+        if not a.no_symmetric:
+            for name in [f for f in ("f32", "bf16") if f in fmts]:
+                Am = stores[name]
+                ws = P.workspace(n, d, Am.fmt, symmetric=True)
+                X = torch.empty((nd, d), dtype=torch.float32, device=dev)
+                kw = dict(refine_iters=10, A_refine=stores["f32"]) if name == "bf16" else {}
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = P.solve(Am, n, d, X, ws, ns_steps=3, max_iters=SOLVE_ITERS, symmetric=True, **kw)
+                dt = time.perf_counter() - t0
+                e = alignment_error(X.cpu().double().numpy(), Z)
+                solve[f"{name}_symmetric"] = {"solve_s": dt, "align_err": e, "first_order_pred": pred,
+                                              "iters": info["iters"], "init_residual": info["init_residual"],
+                                              "refine_iters": kw.get("refine_iters", 0)}
+                print(f"[bench] solve {name} symmetric: {dt:.3f} s, align err {e:.6f}", file=sys.stderr, flush=True)
+                del ws
         ref = solve.get("f32", {}).get("align_err")
         if ref:
             for name in solve:
@@ -385,6 +402,10 @@ def main(argv=None):
         if "f32" in solve:
             equal_acc = {f"{k}+refine": solve["f32"]["solve_s"] / solve[k]["solve_s"]
                          for k in ("bf16", "fp8") if k in solve}
+            if "f32_symmetric" in solve:
+                equal_acc["f32_symmetric"] = solve["f32"]["solve_s"] / solve["f32_symmetric"]["solve_s"]
+            if "bf16_symmetric" in solve:
+                equal_acc["bf16_symmetric+refine"] = solve["f32"]["solve_s"] / solve["bf16_symmetric"]["solve_s"]
             equal_acc["bf16_split"] = (solve["f32"]["solve_s"] / solve["bf16_split"]["solve_s"]
                                        if "bf16_split" in solve else None)
             solve["speedup_vs_f32_at_equal_accuracy"] = equal_acc

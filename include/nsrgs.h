@@ -101,6 +101,9 @@ typedef struct {
   const nsrgs_matrix *A_refine; /* matrix for those iterations (e.g. F32 or
                                    BF16_SPLIT copy of A), or NULL [NULL]          */
   int32_t check_every;      /* iterations enqueued between host checks [16]         */
+  int32_t symmetric;        /* 1: every iteration is sync_step_symmetric's (A and
+                               A_refine exactly symmetric, formats and d as there;
+                               ws of sync_step_symmetric_workspace_bytes) [0]      */
 } nsrgs_solve_opts;
 
 /* ---- status and version ------------------------------------------------ */
@@ -146,9 +149,11 @@ int sync_step(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps,
  * with NSRGS_ERR_UNSUPPORTED: its per-row scales make the stored A_ij and
  * A_ji differ.
  * ws must hold sync_step_symmetric_workspace_bytes(n, d, fmt) bytes: the
- * sync_step workspace followed by the per-tile partial sums, about
- * (n d)^2 d (1/H + 1/CW) accumulator values, with strip height H ~ 384 and
- * chunk width CW = 256 V.  It is prepared by sync_workspace_init, and
+ * sync_step workspace followed by the per-tile partial sums (sized for every
+ * format with fmt's accumulation type, so one workspace serves F32, BF16 and
+ * BF16_SPLIT matrices of the same n and d), about
+ * (n d)^2 d (1/H + 1/CW) accumulator values, with strip height H of several
+ * hundred rows (up to what 64 KiB of LDS holds) and chunk width CW = 256 V.  It is prepared by sync_workspace_init, and
  * sync_read_info reads the monitors as after sync_step.
  * The call returns 0 bytes for unsupported (n, d, fmt).  It is asynchronous. */
 size_t sync_step_symmetric_workspace_bytes(int n, int d, int fmt);

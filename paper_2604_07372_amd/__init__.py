@@ -54,7 +54,8 @@ class Info(ctypes.Structure):
 class _SolveOpts(ctypes.Structure):
     _fields_ = [("init", ctypes.c_int32), ("init_iters", ctypes.c_int32),
                 ("init_tol", ctypes.c_double), ("refine_iters", ctypes.c_int32),
-                ("A_refine", ctypes.POINTER(_Matrix)), ("check_every", ctypes.c_int32)]
+                ("A_refine", ctypes.POINTER(_Matrix)), ("check_every", ctypes.c_int32),
+                ("symmetric", ctypes.c_int32)]
 
 
 class _Problem(ctypes.Structure):
@@ -343,13 +344,15 @@ def init_spectral(A: StoredMatrix, n: int, d: int, X0: torch.Tensor, ws: Workspa
 def solve(A: StoredMatrix, n: int, d: int, X: torch.Tensor, ws: Workspace, mu: float = 0.0,
           ns_steps: int = 3, max_iters: int = 100, tol: float = 0.0, init: bool = True,
           init_iters: int = 60, init_tol: float = 0.0, refine_iters: int = 0,
-          A_refine: StoredMatrix | None = None, check_every: int = 16, check: bool = True) -> dict:
-    """Algorithm 2 end to end (sync_solve).  X receives the result (and holds X0 if init=False)."""
+          A_refine: StoredMatrix | None = None, check_every: int = 16, check: bool = True,
+          symmetric: bool = False) -> dict:
+    """Algorithm 2 end to end (sync_solve).  X receives the result (and holds X0 if init=False).
+    symmetric=True runs every iteration as step_symmetric (ws from workspace(..., symmetric=True))."""
     _check_x(X, n * d, d, A.fmt, "X")
     m = A.c()
     mref = A_refine.c() if A_refine is not None else None
     opts = _SolveOpts(int(init), int(init_iters), float(init_tol), int(refine_iters),
-                      ctypes.pointer(mref) if mref is not None else None, int(check_every))
+                      ctypes.pointer(mref) if mref is not None else None, int(check_every), int(symmetric))
     info = Info()
     st = lib().sync_solve(ctypes.byref(m), n, d, float(mu), int(ns_steps), int(max_iters), float(tol),
                           X.data_ptr(), ws.ptr, ws.nbytes, _stream(), ctypes.byref(opts), ctypes.byref(info))

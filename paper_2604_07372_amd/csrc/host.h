@@ -69,6 +69,12 @@ int check_step_args(const nsrgs_matrix *A, int n, int d, int ns_steps, const voi
 size_t step_ws_bytes(int n, int d, int fmt);
 size_t step_ws_stats_offset(int n, int d, int fmt);
 
+// Symmetric half-stream step (symmetric.hip): its own argument checks and
+// one launch with the solve's iteration index, tolerance and stop flag.
+int sym_check(const nsrgs_matrix *A, int n, int d, size_t ws_bytes);
+int sym_step_launch(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
+                    void *X_out, void *ws, hipStream_t s, int iter, double tol, bool check_done);
+
 // Tuning table (runtime.hip): waves per workgroup of the grouped launch.
 int tuned_batch_waves(int fmt, int dmax);
 

@@ -427,9 +427,19 @@ int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, int
   if (ns_steps < 0 || ns_steps > 64) return fail(NSRGS_ERR_INVALID_ARG, "ns_steps must be in [0, 64]");
   if (max_iters < 0) return fail(NSRGS_ERR_INVALID_ARG, "max_iters must be >= 0");
   if (!std::isfinite(mu)) return fail(NSRGS_ERR_INVALID_ARG, "mu must be finite");
-  nsrgs_solve_opts o{1, 60, 0.0, 0, nullptr, 16};
+  nsrgs_solve_opts o{1, 60, 0.0, 0, nullptr, 16, 0};
   if (opts) o = *opts;
   if (o.check_every <= 0) o.check_every = 16;
+  if (o.symmetric != 0 && o.symmetric != 1) return fail(NSRGS_ERR_INVALID_ARG, "symmetric must be 0 or 1");
+  if (o.symmetric) {
+    if ((st = sym_check(A, n, d, ws_bytes))) return st;
+    if (o.refine_iters > 0 && o.A_refine && (st = sym_check(o.A_refine, n, d, ws_bytes))) return st;
+  }
+  // one iteration on matrix M, with the solve's iteration index and stop rule
+  auto iterate = [&](const nsrgs_matrix *M, const void *xi, void *xo, int t, double tl) {
+    return o.symmetric ? sym_step_launch(M, n, d, mu, ns_steps, xi, xo, ws, (hipStream_t)stream, t, tl, true)
+                       : step_impl(M, n, d, mu, ns_steps, xi, xo, ws, (hipStream_t)stream, t, tl, true);
+  };
   int refine = 0;
   if (o.refine_iters > 0 && o.A_refine) {
     if ((st = check_matrix(o.A_refine, n, d))) return st;
@@ -459,9 +469,7 @@ int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, int
   while (t < phase1) {
     const int tend = std::min(phase1, t + o.check_every);
     for (; t < tend; ++t)
-      if ((st = step_impl(A, n, d, mu, ns_steps, buf[t & 1], buf[(t + 1) & 1], ws, s, t,
-                          tol, true)))
-        return st;
+      if ((st = iterate(A, buf[t & 1], buf[(t + 1) & 1], t, tol))) return st;
     if ((st = read_ctl(ws, &host, s))) return st;
     if (host.done) break;
   }
@@ -472,9 +480,7 @@ int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, int
     NSRGS_HIP(launch_ctl_reset(static_cast<DevCtl *>(ws), 1, s), "ctl reset");
     for (int r = 0; r < refine; ++r) {
       const int tt = done_iters + r;
-      if ((st = step_impl(o.A_refine, n, d, mu, ns_steps, buf[tt & 1], buf[(tt + 1) & 1], ws, s,
-                          tt, 0.0, true)))
-        return st;
+      if ((st = iterate(o.A_refine, buf[tt & 1], buf[(tt + 1) & 1], tt, 0.0))) return st;
     }
     const int conv = host.converged;
     if ((st = read_ctl(ws, &host, s))) return st;

@@ -37,10 +37,17 @@ struct SymArgs {
   int nstrips;
   void *prow;     // nchunks x nd x d: row sums of tile (strip(r), chunk) at row r
   void *pcol;     // nstrips x nd x d: column sums of tile (strip, chunk(c)) at column c
+  const int *stop_flag;   // non-NULL: return at once when *stop_flag != 0
 };
 
-// Panel rows of the tile kernel and blocks per epilogue workgroup, per d.
-constexpr int sym_rows(int d) { return d <= 2 ? 16 : d <= 4 ? 12 : d == 5 ? 10 : d == 6 ? 8 : d == 7 ? 7 : 8; }
+// Compiled tile shapes (d, R panel rows, U vectors per lane per row); the
+// first one of each d is the default.  R d accumulators and R U loads per
+// lane per panel; R d <= 64.
+#define NSRGS_SYM_SHAPES(X)                                                                  \
+  X(1, 16, 1) X(2, 16, 1) X(3, 12, 1) X(3, 16, 1) X(3, 12, 2) X(3, 6, 2) X(4, 12, 1) X(4, 8, 2) \
+  X(4, 16, 1) X(5, 10, 1) X(6, 8, 1) X(7, 7, 1) X(8, 8, 1)
+
+// Blocks per epilogue workgroup, per d.
 constexpr int sym_epi_blocks(int d) { return d == 1 ? 64 : d == 2 ? 32 : d <= 4 ? 16 : d == 5 ? 8 : d == 6 ? 6 : 4; }
 constexpr int kSymMaxD = 8;
 
@@ -92,7 +99,8 @@ __device__ __forceinline__ int sym_tr_entry(int lane) {
 
 // The rows [strip0, strip1) of one tile for this wave's columns.
 template <int FMT, int D, int R, int U, bool MASK>
-__device__ __forceinline__ void sym_tile_rows(const SymArgs &a, int strip0, int strip1, int lane, int cw0,
+__device__ __forceinline__ void sym_tile_rows(const SymArgs &a, const typename Fmt<FMT>::acc_t *__restrict__ X,
+                                              int strip0, int strip1, int lane, int cw0,
                                               const int (&col)[U],
                                               const typename Fmt<FMT>::acc_t (&xc)[U][Fmt<FMT>::V][D],
                                               typename Fmt<FMT>::acc_t (&cacc)[U][Fmt<FMT>::V][D],
@@ -105,7 +113,6 @@ __device__ __forceinline__ void sym_tile_rows(const SymArgs &a, int strip0, int 
   const int nd = a.nd;
   const char *__restrict__ Ab = static_cast<const char *>(a.A);
   const char *__restrict__ Alo = static_cast<const char *>(a.A_lo);
-  const T *__restrict__ X = static_cast<const T *>(a.X_in);
 
   const int ridx = sym_tr_entry<N>(lane);
 
@@ -185,8 +192,11 @@ __device__ __forceinline__ void sym_tile_rows(const SymArgs &a, int strip0, int 
 // One tile per workgroup: blockIdx.x = chunk, blockIdx.y = strip; tiles left
 // of the strip's diagonal chunk return at once.  Dynamic LDS: waves * H * d
 // values of the accumulation type.
+// X (= a.X_in) is also a separate read-only argument, so the wave-uniform
+// reads of the panel rows' X_i can be scalar loads.
 template <int FMT, int D, int R, int U>
-__global__ void __launch_bounds__(kWave * kMaxWaves) sym_tile_kernel(SymArgs a) {
+__global__ void __launch_bounds__(kWave * kMaxWaves)
+sym_tile_kernel(SymArgs a, const typename Fmt<FMT>::acc_t *__restrict__ X) {
   using T = typename Fmt<FMT>::acc_t;
   constexpr int V = Fmt<FMT>::V;
   constexpr int WCOLS = kWave * V * U;
@@ -195,6 +205,9 @@ __global__ void __launch_bounds__(kWave * kMaxWaves) sym_tile_kernel(SymArgs a) 
   const int nd = a.nd, H = a.H, CW = a.CW;
   const int strip0 = s * H;
   if (j < strip0 / CW) return;                     // uniform
+  if (a.stop_flag) {
+    if (__atomic_load_n(a.stop_flag, __ATOMIC_RELAXED)) return;   // uniform
+  }
   const int strip1 = min(strip0 + H, nd);
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -203,7 +216,6 @@ __global__ void __launch_bounds__(kWave * kMaxWaves) sym_tile_kernel(SymArgs a) 
   const int cw0 = j * CW + wave * WCOLS;
   T *s_row = reinterpret_cast<T *>(sym_lds);
   T *myrow = s_row + (int64_t)wave * H * D;
-  const T *__restrict__ X = static_cast<const T *>(a.X_in);
 
   int col[U];
   T xc[U][V][D], cacc[U][V][D];
@@ -224,8 +236,8 @@ __global__ void __launch_bounds__(kWave * kMaxWaves) sym_tile_kernel(SymArgs a) 
   }
   // masked path for tiles that reach the block diagonal or the matrix edge
   const bool mask = (j * CW) / D <= (strip1 - 1) / D || (j + 1) * CW > nd || strip0 + H > nd;
-  if (mask) sym_tile_rows<FMT, D, R, U, true>(a, strip0, strip1, lane, cw0, col, xc, cacc, myrow);
-  else sym_tile_rows<FMT, D, R, U, false>(a, strip0, strip1, lane, cw0, col, xc, cacc, myrow);
+  if (mask) sym_tile_rows<FMT, D, R, U, true>(a, X, strip0, strip1, lane, cw0, col, xc, cacc, myrow);
+  else sym_tile_rows<FMT, D, R, U, false>(a, X, strip0, strip1, lane, cw0, col, xc, cacc, myrow);
   __syncthreads();
 
   // row sums: the waves' partials added in wave order
@@ -276,8 +288,11 @@ __global__ void __launch_bounds__(256) sym_epilogue_kernel(SymArgs a, StreamArgs
     const int row = row0 + e / D;
     const int rr = row < nd ? row : nd - 1;
     const int64_t o = (int64_t)rr * D + (e % D);
+    // unrolled so that several loads are in flight; the additions stay in order
     T sum = T(0);
+#pragma unroll 8
     for (int jj = j0; jj < a.nchunks; ++jj) sum += prow[jj * plane + o];
+#pragma unroll 8
     for (int ss = 0; ss <= s; ++ss) sum += pcol[ss * plane + o];
     const T x = X[o];
     sC[e] = row < nd ? sum : T(0);
@@ -289,14 +304,13 @@ __global__ void __launch_bounds__(256) sym_epilogue_kernel(SymArgs a, StreamArgs
                                 sM, s_scr);
 }
 
-template <int FMT, int D, int U>
-hipError_t sym_launch_d(const SymArgs &a, const StreamArgs &sa, int waves, hipStream_t s) {
+template <int FMT, int D, int R, int U>
+hipError_t sym_launch_shape(const SymArgs &a, const StreamArgs &sa, int waves, hipStream_t s) {
   using T = typename Fmt<FMT>::acc_t;
-  constexpr int R = sym_rows(D);
   constexpr int BE = sym_epi_blocks(D);
   const size_t lds = (size_t)waves * a.H * D * sizeof(T);
   hipLaunchKernelGGL((sym_tile_kernel<FMT, D, R, U>), dim3(a.nchunks, a.nstrips), dim3(kWave * waves), lds,
-                     s, a);
+                     s, a, static_cast<const T *>(a.X_in));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((sym_epilogue_kernel<FMT, D, BE>), dim3(sa.num_panels), dim3(256), 0, s, a, sa);
@@ -306,22 +320,15 @@ hipError_t sym_launch_d(const SymArgs &a, const StreamArgs &sa, int waves, hipSt
   return hipGetLastError();
 }
 
-// Dispatch over d (1 .. kSymMaxD) for one format.
+// Dispatch over the compiled (d, R, U) shapes for one format.
 template <int FMT>
-hipError_t sym_launch_fmt(int d, int unroll, const SymArgs &a, const StreamArgs &sa, int waves,
+hipError_t sym_launch_fmt(int d, int rows, int unroll, const SymArgs &a, const StreamArgs &sa, int waves,
                           hipStream_t s) {
-  if (unroll != 1) return hipErrorInvalidValue;
-  switch (d) {
-    case 1: return sym_launch_d<FMT, 1, 1>(a, sa, waves, s);
-    case 2: return sym_launch_d<FMT, 2, 1>(a, sa, waves, s);
-    case 3: return sym_launch_d<FMT, 3, 1>(a, sa, waves, s);
-    case 4: return sym_launch_d<FMT, 4, 1>(a, sa, waves, s);
-    case 5: return sym_launch_d<FMT, 5, 1>(a, sa, waves, s);
-    case 6: return sym_launch_d<FMT, 6, 1>(a, sa, waves, s);
-    case 7: return sym_launch_d<FMT, 7, 1>(a, sa, waves, s);
-    case 8: return sym_launch_d<FMT, 8, 1>(a, sa, waves, s);
-    default: return hipErrorInvalidValue;
-  }
+#define NSRGS_SYM_CASE(DD, RR, UU) \
+  if (d == DD && rows == RR && unroll == UU) return sym_launch_shape<FMT, DD, RR, UU>(a, sa, waves, s);
+  NSRGS_SYM_SHAPES(NSRGS_SYM_CASE)
+#undef NSRGS_SYM_CASE
+  return hipErrorInvalidValue;
 }
 
 }  // namespace nsrgs

@@ -110,6 +110,14 @@ def test_solve_and_init_reject_before_device_use():
     assert L.nsrgs_generate_measurement(16, 100, 3, 1.0, 0, 0, 1.0, P.BF16, 16, 304, None) == 1
     out = P._Matrix(P.F32, 16, None, None, 304)
     assert L.nsrgs_convert(16, 300, 304, ctypes.byref(out), None) == 1
+    # symmetric solves: flag values, FP8, and a workspace sized for sync_step only
+    ws_sym = L.sync_step_symmetric_workspace_bytes(100, 3, P.F32)
+    for flag, mat, ws, want in [(2, m, ws_sym, 1),
+                                (1, P._Matrix(P.FP8_E4M3, 16, None, 32, 304), ws_sym, 2),
+                                (1, m, L.sync_workspace_bytes(100, 3, P.F32), 3)]:
+        o = P._SolveOpts(0, 60, 0.0, 0, None, 16, flag)
+        assert L.sync_solve(ctypes.byref(mat), 100, 3, 0.0, 3, 10, 0.0, 4096, 256, ws, None, ctypes.byref(o),
+                            ctypes.byref(info)) == want, (flag, want)
 
 
 def test_symmetric_step_workspace_and_refusals():
@@ -123,8 +131,13 @@ def test_symmetric_step_workspace_and_refusals():
     base = L.sync_workspace_bytes(n, d, P.F32)
     sym = L.sync_step_symmetric_workspace_bytes(n, d, P.F32)
     nd = n * d
-    # strips of 384 rows and chunks of 1024 columns at the default shape
-    parts = (math.ceil(nd / 384) + math.ceil(nd / 1024)) * nd * d * 4
+    # sized for the FP32-accumulating formats' default shapes: FP32 strips of
+    # 1344 rows (the tallest whose per-wave row sums fit 64 KiB of LDS) and
+    # chunks of 1024 columns, BF16 strips of 768 rows and chunks of 2048
+    rows_sums = max(math.ceil(nd / 1024), math.ceil(nd / 2048)) * nd * d * 4
+    col_sums = max(math.ceil(nd / 1344), math.ceil(nd / 768)) * nd * d * 4
+    parts = rows_sums + col_sums
+    assert L.sync_step_symmetric_workspace_bytes(n, d, P.BF16) == sym
     assert parts <= sym - base <= parts + 1024
     assert sym - base < 0.02 * nd * nd * 4        # small next to the A it replaces reading
     m = _mat()

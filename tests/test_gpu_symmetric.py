@@ -139,3 +139,58 @@ def test_symmetric_step_iterates_like_the_oracle():
         Xr = O.rgs_step(As, Xr, d, mu=1.0 / n, Ts=3).X
     dF = np.linalg.norm(host(Xa) - Xr) / np.sqrt(n)
     assert dF <= 1e-5, dF
+
+
+@pytest.mark.parametrize("d,R,U", [(3, 12, 1), (3, 16, 1), (3, 12, 2), (3, 6, 2), (4, 12, 1), (4, 8, 2),
+                                   (4, 16, 1)])
+@pytest.mark.parametrize("fmt", [P.F32, P.BF16], ids=lambda f: FMT_NAME[f])
+def test_symmetric_compiled_panel_shapes(d, R, U, fmt, monkeypatch):
+    """Every compiled panel shape (R rows, U vectors per lane per row; chosen
+    by NSRGS_SYM_R / NSRGS_SYM_U) gives the oracle's step."""
+    require_gpu()
+    n = 613
+    print(f"symmetric panel shape d={d} R={R} U={U} fmt={FMT_NAME[fmt]}", flush=True)
+    monkeypatch.setenv("NSRGS_SYM_R", str(R))
+    monkeypatch.setenv("NSRGS_SYM_U", str(U))
+    Z, A64, X = _problem(n, d, seed=400 + R + U)
+    Ad = device_matrix(A64, fmt)
+    As = oracle_matrix(A64, fmt)
+    Xin = to_dev(X, torch.float32)
+    Xout, _ = _run(Ad, n, d, Xin, fmt)
+    ref = O.rgs_step(As, host(Xin), d, mu=1.0 / n, Ts=3)
+    assert np.abs(host(Xout) - ref.X).max() <= step_tolerance(As, host(Xin), n, fmt)
+
+
+@pytest.mark.parametrize("form", ["f32", "bf16+refine", "tol"])
+def test_symmetric_solve_matches_full_stream_solve(form):
+    """sync_solve with every iteration on the symmetric half-stream lands on the
+    full-stream solve's result (same spectral initialization, iterations
+    equal up to rounding), for a fixed budget, the BF16 form with FP32
+    refinement, and a tolerance stop."""
+    require_gpu()
+    n, d = 2000, 3
+    print(f"symmetric solve {form}", flush=True)
+    Z = synth.haar_blocks(n, d, 21)
+    A32 = P.generate(torch.from_numpy(Z).cuda(), synth.sigma_for(0.2, n, d), 22, fmt=P.F32)
+    Af = P.stored(A32, P.F32)
+    Am = P.convert(A32, P.BF16) if form == "bf16+refine" else Af
+    kw = dict(refine_iters=10, A_refine=Af) if form == "bf16+refine" else {}
+    tol, iters = (1e-6, 300) if form == "tol" else (0.0, 200)
+    out = {}
+    for sym in (False, True):
+        ws = P.workspace(n, d, Am.fmt, symmetric=sym)
+        X = torch.empty((n * d, d), dtype=torch.float32, device="cuda")
+        info = P.solve(Am, n, d, X, ws, max_iters=iters, tol=tol, symmetric=sym, **kw)
+        out[sym] = (host(X), info)
+    Xf, inf_f = out[False]
+    Xs, inf_s = out[True]
+    dF = O.dist_F(Xs, Xf) / np.sqrt(n)
+    ef, es = O.alignment_error(Xf, Z), O.alignment_error(Xs, Z)
+    print(f"  d_F/sqrt(n) {dF:.2e}, align err {ef:.9f} vs {es:.9f}, iters {inf_f['iters']} vs {inf_s['iters']}",
+          flush=True)
+    assert dF <= 1e-5
+    assert abs(es - ef) <= 1e-6 * ef
+    if form == "tol":
+        assert inf_s["converged"] == 1 and abs(inf_s["iters"] - inf_f["iters"]) <= 2
+    else:
+        assert inf_s["iters"] == inf_f["iters"] == iters
