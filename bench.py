@@ -31,24 +31,24 @@ SEED = 20000
 SOLVE_ITERS = 200
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(files=("stream_impl.h", "device.h")) -> str:
     h = hashlib.sha256()
-    for fn in ("stream_impl.h", "device.h"):
+    for fn in files:
         with open(os.path.join(ROOT, "paper_2604_07372_amd", "csrc", fn), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile():
-    """HBM bytes per launch of the FP32 step kernel from committed rocprofv3
-    counter summaries, or None when they were taken on another kernel source."""
-    path = os.path.join(ROOT, "profiles", "step_f32_n20000_d3_counters.json")
+def traffic_from_profile(name="step_f32_n20000_d3_counters.json", files=("stream_impl.h", "device.h")):
+    """HBM bytes per launch of a step kernel from committed rocprofv3 counter
+    summaries, or None when they were taken on another kernel source."""
+    path = os.path.join(ROOT, "profiles", name)
     try:
         with open(path) as f:
             rec = json.load(f)
     except OSError:
         return None
-    if rec.get("kernel_source_hash") != kernel_source_hash():
+    if rec.get("kernel_source_hash") != kernel_source_hash(files):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -348,6 +348,10 @@ def main(argv=None):
                                "alg_GBps": s_bytes / (ms * 1e-3) / 1e9,
                                "speedup_vs_full_stream": results[name]["ms_per_step"] / ms,
                                "workspace_bytes": ws.nbytes}
+            if name == "f32":
+                # tile kernel's HBM bytes (reads + partial-sum writes) from the committed counters
+                symmetric[name]["traffic"] = traffic_from_profile(
+                    "step_symmetric_f32_n20000_d3_counters.json", ("symmetric_impl.h", "stream_impl.h", "device.h"))
             print(f"[bench] symmetric {name}: {ms:.4f} ms/iter, {1e3 / ms:.1f} it/s, "
                   f"{symmetric[name]['alg_GBps']:.0f} GB/s, "
                   f"{symmetric[name]['speedup_vs_full_stream']:.2f}x the full stream", file=sys.stderr, flush=True)
