@@ -172,6 +172,44 @@ def batched_bench(iters: int = 100, base_iters: int = 10, count: int = 512, seed
     return res
 
 
+def masked_bench(Zd, sigma, dense_ms: float, steps: int, warmup: int, p: float = 0.5):
+    """Incomplete observations (Sec. 4.1) at the headline n, d with ratio p:
+    sync_step_bsr on block-sparse FP32 storage, mu = 1/(np), against the full
+    dense stream of the same size (which does not depend on how many blocks
+    are zero)."""
+    import torch
+    import paper_2604_07372_amd as P
+    import synth
+    nd, d = Zd.shape
+    n = nd // d
+    print(f"[bench] masked: generating block-sparse A, p={p}", file=sys.stderr, flush=True)
+    B = P.generate_bsr(Zd, sigma, SEED, p, fmt=P.F32)
+    X0 = torch.from_numpy(synth.perturbed_start(Zd.cpu().numpy(), 0.05, SEED + 1)).to(Zd.device, torch.float32)
+    ws = P.workspace(n, d, P.F32)
+    mu = 1.0 / (n * p)
+    Xa, Xb = X0.clone(), torch.empty_like(X0)
+    for _ in range(warmup):
+        P.step_bsr(B, n, d, Xa, Xb, ws, mu=mu)
+        Xa, Xb = Xb, Xa
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        P.step_bsr(B, n, d, Xa, Xb, ws, mu=mu)
+        Xa, Xb = Xb, Xa
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / steps
+    alg = B.nnzb * (d * d * 4 + 4) + (n + 1) * 8 + 2 * nd * d * 4
+    out = {"p": p, "nnzb": B.nnzb, "ms_per_step": ms, "iters_per_s": 1e3 / ms, "alg_bytes": alg,
+           "alg_GBps": alg / (ms * 1e-3) / 1e9, "speedup_vs_dense_stream": dense_ms / ms}
+    print(f"[bench] masked p={p}: {ms:.4f} ms/iter, {1e3 / ms:.1f} it/s, {out['alg_GBps']:.0f} GB/s, "
+          f"{out['speedup_vs_dense_stream']:.2f}x the dense stream", file=sys.stderr, flush=True)
+    del B, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def serving_bench(window_s: float = 10.0, rate: float = 50.0, seed0: int = 5000):
     """Poisson arrivals at `rate` requests/s for `window_s` seconds; each request:
     n log-uniform in [100, 20000], d in {3, 4}, sigma = 0.2 sqrt(n/d), Haar ground
@@ -248,6 +286,7 @@ def main(argv=None):
     ap.add_argument("--formats", default="f32,bf16,bf16_split,fp8")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-symmetric", action="store_true")
+    ap.add_argument("--no-masked", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-window", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -417,6 +456,7 @@ def main(argv=None):
     stores.clear()
     Am = A32 = None
     torch.cuda.empty_cache()
+    masked = None if a.no_masked else masked_bench(Zd, sigma, results["f32"]["ms_per_step"], a.steps, a.warmup)
     batched = None if a.no_batched else batched_bench()
     serving = None if a.no_serving else serving_bench(window_s=a.serving_window)
 
@@ -450,6 +490,7 @@ def main(argv=None):
                     for k, r in results.items()},
         "speedup_vs_f32": {k: results["f32"]["ms_per_step"] / r["ms_per_step"] for k, r in results.items()},
         "symmetric_step": symmetric,
+        "masked_step": masked,
         "solve": solve,
         "batched": batched,
         "serving": serving,

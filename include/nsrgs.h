@@ -161,6 +161,45 @@ int sync_step_symmetric(const nsrgs_matrix *A, int n, int d, double mu, int ns_s
                         const void *X_in, void *X_out, void *ws, size_t ws_bytes,
                         void *stream);
 
+/* ---- incomplete observations: block-sparse storage (Sec. 4.1) -------------
+ * Each off-diagonal block pair (i, j) is observed with probability p; the
+ * blocks that are not observed are zero.  Algorithm 2 is unchanged, with
+ * mu = 1/(np).  Only the observed blocks are stored:
+ *   row_ptr  n + 1 offsets: block row i holds blocks row_ptr[i] .. row_ptr[i+1]-1;
+ *   col_idx  their block columns, ascending, in [0, n) and != i (a stored
+ *            diagonal block, or an index outside [0, n), contributes nothing);
+ *   values   entry (a, b) of the k-th block of row i, with m = row_ptr[i+1] -
+ *            row_ptr[i], at values[row_ptr[i] d^2 + (a d + b) m + k]
+ *            (entry-major within a block row).
+ * All three are device arrays owned by the caller; fmt is NSRGS_A_F32 or
+ * NSRGS_A_BF16 (element type of values).  1 <= d <= 8. */
+typedef struct {
+  int32_t fmt;
+  int32_t reserved;
+  const int64_t *row_ptr;
+  const int32_t *col_idx;
+  const void *values;
+} nsrgs_bsr_matrix;
+
+/* Block-sparse inputs on the device for the same model and seed as
+ * nsrgs_generate_measurement (same observation mask, same element values).
+ * nsrgs_bsr_count writes row_ptr (n + 1 int64 entries) from the mask, using
+ * `counts` (n int64 entries of device scratch), and returns the number of
+ * stored blocks in *nnzb (host).  It waits for the stream.  The caller then
+ * allocates col_idx (nnzb int32) and values (nnzb d^2 elements) and calls
+ * nsrgs_bsr_fill, which is asynchronous. */
+int nsrgs_bsr_count(const double *Z, int n, int d, double p, uint64_t seed, int64_t *row_ptr,
+                    void *counts, int64_t *nnzb, void *stream);
+int nsrgs_bsr_fill(const double *Z, int n, int d, double sigma, double p, uint64_t seed,
+                   const nsrgs_bsr_matrix *A, void *stream);
+
+/* sync_step on block-sparse A: C_i = sum over stored j != i of A_ij X_j, then
+ * the per-block step of sync_step.  X_in / X_out are FP32.  mu <= 0 selects
+ * 1/n; for the incomplete observation model pass mu = 1/(np).  ws as for
+ * sync_step with fmt NSRGS_A_F32.  Asynchronous. */
+int sync_step_bsr(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_steps,
+                  const void *X_in, void *X_out, void *ws, size_t ws_bytes, void *stream);
+
 /* Copy the monitors of the last step / init on this workspace to *info
  * (waits for `stream`). */
 int sync_read_info(const void *ws, size_t ws_bytes, int n, int d, int fmt,

@@ -18,6 +18,7 @@ __all__ = [
     "init_spectral", "solve", "generate", "convert", "stored", "padded_ld",
     "Info", "solve_batched", "batch_rows_per_panel", "set_tuning", "get_tuning", "TuneEntry", "Server",
     "step_variants", "TuneResult", "step_symmetric", "symmetric_workspace_bytes",
+    "BsrMatrix", "generate_bsr", "step_bsr",
 ]
 
 F64, F32, BF16, BF16_SPLIT, FP8_E4M3 = 0, 1, 2, 3, 4
@@ -49,6 +50,11 @@ class Info(ctypes.Structure):
         out = {k: getattr(self, k) for k, _ in self._fields_ if k != "ritz"}
         out["ritz"] = list(self.ritz)[: (d or 16)]
         return out
+
+
+class _Bsr(ctypes.Structure):
+    _fields_ = [("fmt", ctypes.c_int32), ("reserved", ctypes.c_int32), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("values", ctypes.c_void_p)]
 
 
 class _SolveOpts(ctypes.Structure):
@@ -136,6 +142,9 @@ def lib() -> ctypes.CDLL:
         "sync_step": (i32, [pm, i32, i32, dbl, i32, vp, vp, vp, sz, vp]),
         "sync_step_symmetric_workspace_bytes": (sz, [i32, i32, i32]),
         "sync_step_symmetric": (i32, [pm, i32, i32, dbl, i32, vp, vp, vp, sz, vp]),
+        "nsrgs_bsr_count": (i32, [vp, i32, i32, dbl, ctypes.c_uint64, vp, vp, ctypes.POINTER(i64), vp]),
+        "nsrgs_bsr_fill": (i32, [vp, i32, i32, dbl, dbl, ctypes.c_uint64, ctypes.POINTER(_Bsr), vp]),
+        "sync_step_bsr": (i32, [ctypes.POINTER(_Bsr), i32, i32, dbl, i32, vp, vp, vp, sz, vp]),
         "sync_read_info": (i32, [vp, sz, i32, i32, i32, ctypes.POINTER(Info), vp]),
         "sync_init_spectral": (i32, [pm, i32, i32, vp, i32, dbl, vp, sz, vp, ctypes.POINTER(Info)]),
         "sync_solve": (i32, [pm, i32, i32, dbl, i32, i32, dbl, vp, vp, sz, vp,
@@ -318,6 +327,57 @@ def step_symmetric(A: StoredMatrix, n: int, d: int, X_in: torch.Tensor, X_out: t
 
 def symmetric_workspace_bytes(n: int, d: int, fmt: int) -> int:
     return int(lib().sync_step_symmetric_workspace_bytes(n, d, fmt))
+
+
+class BsrMatrix:
+    """Block-sparse A of the incomplete observation model (device arrays; layout
+    in include/nsrgs.h): row_ptr (n + 1, int64), col_idx (nnzb, int32), values
+    (nnzb d^2, FP32 or BF16 bits), entry-major within each block row."""
+
+    def __init__(self, fmt: int, row_ptr: torch.Tensor, col_idx: torch.Tensor, values: torch.Tensor,
+                 n: int, d: int, nnzb: int):
+        self.fmt, self.row_ptr, self.col_idx, self.values = fmt, row_ptr, col_idx, values
+        self.n, self.d, self.nnzb = n, d, nnzb
+
+    def c(self) -> _Bsr:
+        return _Bsr(self.fmt, 0, self.row_ptr.data_ptr(), self.col_idx.data_ptr(), self.values.data_ptr())
+
+    @property
+    def nbytes(self) -> int:
+        return (self.row_ptr.numel() * 8 + self.nnzb * 4
+                + self.nnzb * self.d * self.d * (4 if self.fmt == F32 else 2))
+
+
+def generate_bsr(Z: torch.Tensor, sigma: float, seed: int, p: float, fmt: int = F32) -> BsrMatrix:
+    """Block-sparse A on the device for the model and seed of generate(..., p=p)
+    (nsrgs_bsr_count + nsrgs_bsr_fill): the observed off-diagonal blocks only."""
+    if not Z.is_cuda or Z.dtype != torch.float64 or Z.dim() != 2 or not Z.is_contiguous():
+        raise ValueError("Z must be a contiguous float64 CUDA tensor (n*d, d)")
+    nd, d = Z.shape
+    n = nd // d
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device=Z.device)
+    counts = torch.empty(n, dtype=torch.int64, device=Z.device)
+    nnzb = ctypes.c_int64(0)
+    _check(lib().nsrgs_bsr_count(Z.data_ptr(), n, d, float(p), int(seed), row_ptr.data_ptr(), counts.data_ptr(),
+                                 ctypes.byref(nnzb), _stream()))
+    k = int(nnzb.value)
+    col_idx = torch.empty(max(k, 1), dtype=torch.int32, device=Z.device)
+    values = torch.empty(max(k, 1) * d * d, dtype=torch.float32 if fmt == F32 else torch.int16, device=Z.device)
+    A = BsrMatrix(fmt, row_ptr, col_idx, values, n, d, k)
+    m = A.c()
+    _check(lib().nsrgs_bsr_fill(Z.data_ptr(), n, d, float(sigma), float(p), int(seed), ctypes.byref(m), _stream()))
+    return A
+
+
+def step_bsr(A: BsrMatrix, n: int, d: int, X_in: torch.Tensor, X_out: torch.Tensor, ws: Workspace,
+             mu: float = 0.0, ns_steps: int = 3) -> None:
+    """sync_step_bsr: one iteration on block-sparse A (pass mu = 1/(n p) for the
+    incomplete observation model); ws = workspace(n, d, F32)."""
+    _check_x(X_in, n * d, d, F32, "X_in")
+    _check_x(X_out, n * d, d, F32, "X_out")
+    m = A.c()
+    _check(lib().sync_step_bsr(ctypes.byref(m), n, d, float(mu), int(ns_steps), X_in.data_ptr(), X_out.data_ptr(),
+                               ws.ptr, ws.nbytes, _stream()))
 
 
 def read_info(ws: Workspace) -> dict:

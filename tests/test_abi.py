@@ -156,3 +156,23 @@ def test_symmetric_step_workspace_and_refusals():
     assert L.sync_step_symmetric(ctypes.byref(m), 100, 3, 0.0, 3, 4096, 4096 + 64, 256, ws_bytes, None) == 1
     assert L.sync_step_symmetric(ctypes.byref(m), 100, 3, float("inf"), 3, 4096, 1 << 20, 256, ws_bytes,
                                  None) == 1
+
+
+def test_block_sparse_entry_points_reject_on_the_host():
+    L = P.lib()
+    b = P._Bsr(P.F32, 0, 256, 512, 1024)
+    ws = L.sync_workspace_bytes(100, 3, P.F32)
+    # d > 8, format, NULL arrays, overlap, small workspace, mu
+    assert L.sync_step_bsr(ctypes.byref(b), 100, 9, 0.0, 3, 4096, 1 << 20, 256, 1 << 30, None) == 2
+    f64 = P._Bsr(P.F64, 0, 256, 512, 1024)
+    assert L.sync_step_bsr(ctypes.byref(f64), 100, 3, 0.0, 3, 4096, 1 << 20, 256, ws, None) == 2
+    null = P._Bsr(P.F32, 0, 256, None, 1024)
+    assert L.sync_step_bsr(ctypes.byref(null), 100, 3, 0.0, 3, 4096, 1 << 20, 256, ws, None) == 1
+    assert L.sync_step_bsr(ctypes.byref(b), 100, 3, 0.0, 3, 4096, 4096 + 64, 256, ws, None) == 1
+    assert L.sync_step_bsr(ctypes.byref(b), 100, 3, 0.0, 3, 4096, 1 << 20, 256, ws - 1, None) == 3
+    assert L.sync_step_bsr(ctypes.byref(b), 100, 3, float("nan"), 3, 4096, 1 << 20, 256, ws, None) == 1
+    nnzb = ctypes.c_int64(0)
+    assert L.nsrgs_bsr_count(16, 100, 3, 1.5, 0, 256, 512, ctypes.byref(nnzb), None) == 1      # p > 1
+    assert L.nsrgs_bsr_count(None, 100, 3, 0.5, 0, 256, 512, ctypes.byref(nnzb), None) == 1
+    assert L.nsrgs_bsr_fill(16, 100, 3, 1.0, 0.5, 0, ctypes.byref(f64), None) == 2
+    assert L.nsrgs_bsr_fill(16, 100, 3, float("inf"), 0.5, 0, ctypes.byref(b), None) == 1

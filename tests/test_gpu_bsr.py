@@ -1,0 +1,183 @@
+"""GPU parity of the incomplete observation model (Sec. 4.1) on block-sparse
+storage: the generator against its host twin, and sync_step_bsr against the
+FP64 oracle's step on the dense masked A with mu = 1/(np)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2604_07372_amd as P
+import synth
+from oracle import nsrgs as O
+
+from gpu_common import FMT_NAME, host, oracle_matrix, require_gpu, step_tolerance, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _masked(n, d, c, seed, p):
+    """Noise sigma = c sqrt(p) sqrt(n/d): a block row then sees about the same
+    noise-to-signal ratio c at every p (signal ~ n p, noise ~ sigma sqrt(n p d))."""
+    Z = synth.haar_blocks(n, d, seed)
+    sigma = synth.sigma_for(c * math.sqrt(p), n, d) if p > 0 else synth.sigma_for(c, n, d)
+    A64 = synth.measurement_matrix(Z, sigma, seed + 1, p=p)
+    return Z, sigma, A64
+
+
+def _orthogonal_start(Z, eps, seed):
+    """Perturbed ground truth with each block replaced by its polar factor.  The
+    masked model's step 1/(np) multiplies the orthogonality defect of a start by
+    about 1/p (through the (n - 1) X_i term), so, as in the paper, the start
+    lies on O(d)^n."""
+    X = synth.perturbed_start(Z, eps, seed)
+    d = X.shape[1]
+    out = np.empty_like(X)
+    for i in range(X.shape[0] // d):
+        U, _, Vt = np.linalg.svd(X[i * d:(i + 1) * d])
+        out[i * d:(i + 1) * d] = U @ Vt
+    return out
+
+
+def _dense_from_bsr(B: P.BsrMatrix, n, d):
+    """Expand the device arrays on the host (test-side reading of the layout)."""
+    rp = B.row_ptr.cpu().numpy()
+    ci = B.col_idx.cpu().numpy()
+    if B.fmt == P.F32:
+        vals = B.values.cpu().numpy().astype(np.float64)
+    else:
+        bits = B.values.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+        vals = bits.view(np.float32).astype(np.float64)
+    A = np.zeros((n * d, n * d))
+    for i in range(n):
+        m = rp[i + 1] - rp[i]
+        for k in range(m):
+            j = ci[rp[i] + k]
+            blk = np.array([vals[rp[i] * d * d + e * m + k] for e in range(d * d)]).reshape(d, d)
+            A[i * d:(i + 1) * d, j * d:(j + 1) * d] = blk
+    return A, rp, ci
+
+
+@pytest.mark.parametrize("p", [0.0, 0.3, 0.5, 1.0])
+@pytest.mark.parametrize("d", [1, 3, 5])
+def test_bsr_generator_matches_host_twin_and_dense_generator(d, p):
+    require_gpu()
+    n, seed = 60, 300 + d
+    print(f"bsr generator n={n} d={d} p={p}", flush=True)
+    Z, sigma, A64 = _masked(n, d, 0.3, seed, p)
+    Zd = torch.from_numpy(Z).cuda()
+    B = P.generate_bsr(Zd, sigma, seed + 1, p, fmt=P.F32)
+    A, rp, ci = _dense_from_bsr(B, n, d)
+    blk = np.arange(n * d) // d
+    off = blk[:, None] != blk[None, :]
+    # the observation pattern is the host twin's, block for block
+    obs_host = (np.abs(A64) > 0).reshape(n, d, n, d).any(axis=(1, 3)) & ~np.eye(n, dtype=bool)
+    obs_dev = np.zeros((n, n), dtype=bool)
+    for i in range(n):
+        cols = ci[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(cols) > 0) and not np.any(cols == i)
+        obs_dev[i, cols] = True
+    assert np.array_equal(obs_dev, obs_host)
+    assert B.nnzb == int(obs_host.sum())
+    # elements: FP32 rounding of the host twin's FP64 values (the twin's Z Z^T may differ in its last bit)
+    ref = np.where(off, A64, 0.0)
+    assert np.allclose(A, ref.astype(np.float32).astype(np.float64), rtol=2 ** -22, atol=1e-12)
+    # and bitwise the dense device generator's off-diagonal blocks (which takes p in (0, 1])
+    if p == 0.0:
+        return
+    Ad = P.generate(Zd, sigma, seed + 1, fmt=P.F32, p=p)
+    dense = Ad[:, :n * d].cpu().numpy().astype(np.float64)
+    assert np.array_equal(A, np.where(off, dense, 0.0))
+
+
+@pytest.mark.parametrize("fmt", [P.F32, P.BF16], ids=lambda f: FMT_NAME[f])
+@pytest.mark.parametrize("p", [0.05, 0.5, 0.8, 1.0])
+@pytest.mark.parametrize("n,d", [(2, 1), (37, 3), (300, 3), (130, 4), (61, 5), (40, 8), (700, 2)])
+def test_bsr_step_parity(n, d, p, fmt):
+    require_gpu()
+    seed = 7000 + 31 * n + d
+    print(f"bsr step parity n={n} d={d} p={p} fmt={FMT_NAME[fmt]}", flush=True)
+    Z, sigma, A64 = _masked(n, d, 0.3, seed, p)
+    B = P.generate_bsr(torch.from_numpy(Z).cuda(), sigma, seed + 1, p, fmt=fmt)
+    X = _orthogonal_start(Z, 0.05, seed + 2)
+    Xin = to_dev(X, torch.float32)
+    Xout = torch.empty_like(Xin)
+    ws = P.workspace(n, d, P.F32)
+    mu = 1.0 / (n * p) if n * p >= 2 else 1.0 / n     # the paper's 1/(np) where it is a sensible step
+    P.step_bsr(B, n, d, Xin, Xout, ws, mu=mu)
+    torch.cuda.synchronize()
+    As = oracle_matrix(A64, fmt)
+    ref = O.rgs_step(As, host(Xin), d, mu=mu, Ts=3)
+    err = np.abs(host(Xout) - ref.X).max()
+    # a BF16 element can round the other way when the host twin's last FP64 bit differs
+    tol = step_tolerance(As, host(Xin), n, fmt) * (4.0 if fmt == P.BF16 else 1.0)
+    assert err <= tol, (err, tol)
+    info = P.read_info(ws)
+    assert abs(info["rel_change"] - ref.rel_change) <= 1e-3 * ref.rel_change + 1e-6
+    assert info["nonfinite"] == 0
+
+
+def test_bsr_step_equals_dense_step_on_the_masked_matrix():
+    """The block-sparse step and sync_step on the dense masked A of the same
+    generator agree to the accumulation rounding."""
+    require_gpu()
+    n, d, p = 900, 3, 0.5
+    Z, sigma, A64 = _masked(n, d, 0.3, 11, p)
+    Zd = torch.from_numpy(Z).cuda()
+    B = P.generate_bsr(Zd, sigma, 12, p)
+    Ad = P.stored(P.generate(Zd, sigma, 12, fmt=P.F32, p=p), P.F32)
+    Xin = to_dev(_orthogonal_start(Z, 0.05, 13), torch.float32)
+    out_b, out_d = torch.empty_like(Xin), torch.empty_like(Xin)
+    ws = P.workspace(n, d, P.F32)
+    mu = 1.0 / (n * p)
+    P.step_bsr(B, n, d, Xin, out_b, ws, mu=mu)
+    P.step(Ad, n, d, Xin, out_d, ws, mu=mu)
+    out_b2 = torch.empty_like(Xin)
+    P.step_bsr(B, n, d, Xin, out_b2, ws, mu=mu)
+    torch.cuda.synchronize()
+    assert torch.equal(out_b, out_b2)
+    As = oracle_matrix(A64, P.F32)
+    assert np.abs(host(out_b) - host(out_d)).max() <= 2 * step_tolerance(As, host(Xin), n, P.F32)
+
+
+def test_bsr_stored_diagonal_and_out_of_range_blocks_count_nothing():
+    """A hand-built block-sparse matrix with a NaN diagonal block and a NaN
+    block at an out-of-range column gives the oracle's step without them."""
+    require_gpu()
+    n, d = 6, 2
+    rng = np.random.default_rng(3)
+    pairs = [(0, 1), (0, 4), (1, 3), (2, 5), (3, 4)]
+    A = np.zeros((n * d, n * d))
+    for i, j in pairs:
+        b = rng.standard_normal((d, d))
+        A[i * d:(i + 1) * d, j * d:(j + 1) * d] = b
+        A[j * d:(j + 1) * d, i * d:(i + 1) * d] = b.T
+    rows = []
+    for i in range(n):
+        cols = [j for j in range(n) if np.any(A[i * d:(i + 1) * d, j * d:(j + 1) * d])]
+        extra = [i] if i % 2 == 0 else []          # stored diagonal blocks
+        bad = [n + 3] if i == 1 else []             # an index outside [0, n)
+        rows.append(sorted(cols + extra) + bad)
+    rp = np.zeros(n + 1, dtype=np.int64)
+    for i, cols in enumerate(rows):
+        rp[i + 1] = rp[i] + len(cols)
+    ci = np.concatenate([np.array(c, dtype=np.int32) for c in rows])
+    vals = np.zeros(rp[-1] * d * d, dtype=np.float32)
+    for i, cols in enumerate(rows):
+        m = len(cols)
+        for k, j in enumerate(cols):
+            blk = (np.full((d, d), np.nan) if (j == i or j >= n)
+                   else A[i * d:(i + 1) * d, j * d:(j + 1) * d])
+            for e in range(d * d):
+                vals[rp[i] * d * d + e * m + k] = blk.flat[e]
+    B = P.BsrMatrix(P.F32, torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(), torch.from_numpy(vals).cuda(),
+                    n, d, int(rp[-1]))
+    Z = synth.haar_blocks(n, d, 5)
+    Xin = to_dev(synth.perturbed_start(Z, 0.05, 6), torch.float32)
+    Xout = torch.empty_like(Xin)
+    ws = P.workspace(n, d, P.F32)
+    P.step_bsr(B, n, d, Xin, Xout, ws, mu=0.3)
+    torch.cuda.synchronize()
+    ref = O.rgs_step(A.astype(np.float32).astype(np.float64), host(Xin), d, mu=0.3, Ts=3)
+    assert np.isfinite(host(Xout)).all()
+    assert np.abs(host(Xout) - ref.X).max() <= 1e-5
