@@ -172,7 +172,8 @@ bsr_step_kernel(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__
     const int64_t k = k0 + lane;
     const bool ok = k < m;
     const int64_t kc = ok ? k : m - 1;                  // clamped: in-bounds, masked below
-    const int jr = col_idx[base + kc];
+    // streamed once, non-temporal like the values, so that X stays in cache
+    const int jr = __builtin_nontemporal_load(col_idx + base + kc);
     const int j = jr < 0 ? 0 : (jr < n ? jr : n - 1);   // out-of-range indices read in bounds
     const bool use = ok && jr == j && j != ic;          // and, like a stored diagonal block, count 0
     float a[D2], x[D2];
