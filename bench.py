@@ -456,7 +456,9 @@ def main(argv=None):
     stores.clear()
     Am = A32 = None
     torch.cuda.empty_cache()
-    masked = None if a.no_masked else masked_bench(Zd, sigma, results["f32"]["ms_per_step"], a.steps, a.warmup)
+    masked = None if a.no_masked else {
+        f"p={pm}": masked_bench(Zd, sigma, results["f32"]["ms_per_step"], a.steps, a.warmup, p=pm)
+        for pm in (0.5, 0.2)}
     batched = None if a.no_batched else batched_bench()
     serving = None if a.no_serving else serving_bench(window_s=a.serving_window)
 
