@@ -2,6 +2,7 @@
 // checks, tile shape, workspace carve-up and dispatch by format.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <numeric>
 
