@@ -145,7 +145,7 @@ int sync_step(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps,
  * Values on and below the block diagonal are never used.  Cache lines
  * near the diagonal may still be loaded, so they must be readable memory;
  * their contents do not matter.
- * Formats F64, F32, BF16 and BF16_SPLIT; 1 <= d <= 8.  FP8_E4M3 is refused
+ * Formats F64, F32, BF16 and BF16_SPLIT; 1 <= d <= 16.  FP8_E4M3 is refused
  * with NSRGS_ERR_UNSUPPORTED: its per-row scales make the stored A_ij and
  * A_ji differ.
  * ws must hold sync_step_symmetric_workspace_bytes(n, d, fmt) bytes: the

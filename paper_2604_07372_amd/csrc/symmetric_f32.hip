@@ -1,4 +1,4 @@
-// Instantiations of the symmetric half-stream step kernels: format NSRGS_A_F32, d in [1, 8].
+// Instantiations of the symmetric half-stream step kernels: format NSRGS_A_F32, d in [1, 16].
 #include "symmetric_impl.h"
 
 namespace nsrgs {

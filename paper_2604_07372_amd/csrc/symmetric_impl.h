@@ -42,14 +42,15 @@ struct SymArgs {
 
 // Compiled tile shapes (d, R panel rows, U vectors per lane per row); the
 // first one of each d is the default.  R d accumulators and R U loads per
-// lane per panel; R d <= 64.
+// lane per panel; R d <= 64 (one value per lane after the transpose-reduce).
 #define NSRGS_SYM_SHAPES(X)                                                                  \
   X(1, 16, 1) X(2, 16, 1) X(3, 12, 1) X(3, 16, 1) X(3, 12, 2) X(3, 6, 2) X(4, 12, 1) X(4, 8, 2) \
-  X(4, 16, 1) X(5, 10, 1) X(6, 8, 1) X(7, 7, 1) X(8, 8, 1)
+  X(4, 16, 1) X(5, 10, 1) X(6, 8, 1) X(7, 7, 1) X(8, 8, 1) X(9, 4, 1) X(10, 4, 1) X(11, 4, 1)    \
+  X(12, 4, 1) X(13, 4, 1) X(14, 4, 1) X(15, 4, 1) X(16, 4, 1)
 
 // Blocks per epilogue workgroup, per d.
 constexpr int sym_epi_blocks(int d) { return d == 1 ? 64 : d == 2 ? 32 : d <= 4 ? 16 : d == 5 ? 8 : d == 6 ? 6 : 4; }
-constexpr int kSymMaxD = 8;
+constexpr int kSymMaxD = 16;
 
 // ---- transpose-reduce over the 64 lanes of a wave ------------------------
 // Each of 6 steps pairs lanes that differ in one bit: one lane of the pair

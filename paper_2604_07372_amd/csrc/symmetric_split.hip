@@ -1,4 +1,4 @@
-// Instantiations of the symmetric half-stream step kernels: format NSRGS_A_BF16_SPLIT, d in [1, 8].
+// Instantiations of the symmetric half-stream step kernels: format NSRGS_A_BF16_SPLIT, d in [1, 16].
 #include "symmetric_impl.h"
 
 namespace nsrgs {

@@ -124,7 +124,8 @@ def test_symmetric_step_workspace_and_refusals():
     """sync_step_symmetric: workspace sizes from the tile shape (the partial sums
     grow like (n d)^2 d / H), and every refusal happens on the host."""
     L = P.lib()
-    assert L.sync_step_symmetric_workspace_bytes(100, 9, P.F32) == 0          # d <= 8
+    assert L.sync_step_symmetric_workspace_bytes(100, 17, P.F32) == 0         # d <= 16
+    assert L.sync_step_symmetric_workspace_bytes(100, 16, P.F32) > 0
     assert L.sync_step_symmetric_workspace_bytes(100, 3, P.FP8_E4M3) == 0     # not symmetric storage
     assert L.sync_step_symmetric_workspace_bytes(1, 3, P.F32) == 0
     n, d = 20000, 3
@@ -146,9 +147,9 @@ def test_symmetric_step_workspace_and_refusals():
     f8 = P._Matrix(P.FP8_E4M3, 16, None, 32, 304)
     st = L.sync_step_symmetric(ctypes.byref(f8), 100, 3, 0.0, 3, 4096, 1 << 20, 256, ws_bytes, None)
     assert st == 2 and "FP8" in L.nsrgs_last_error().decode()
-    # d > 8 is unsupported; the sync_step workspace alone is too small
-    st = L.sync_step_symmetric(ctypes.byref(m), 30, 10, 0.0, 3, 4096, 1 << 20, 256, 1 << 30, None)
-    assert st == 2
+    # d > 16 is refused by the common checks; the sync_step workspace alone is too small
+    st = L.sync_step_symmetric(ctypes.byref(m), 30, 17, 0.0, 3, 4096, 1 << 20, 256, 1 << 30, None)
+    assert st == 1
     st = L.sync_step_symmetric(ctypes.byref(m), 100, 3, 0.0, 3, 4096, 1 << 20, 256,
                                L.sync_workspace_bytes(100, 3, P.F32), None)
     assert st == 3 and "sync_step_symmetric" in L.nsrgs_last_error().decode()

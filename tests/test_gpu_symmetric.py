@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 SYM_FMTS = [P.F64, P.F32, P.BF16, P.BF16_SPLIT]
 # several strips and chunks with ragged ends, every d the call supports
 SHAPES = [(2, 1), (2, 3), (5, 2), (37, 3), (341, 3), (700, 3), (1500, 1), (100, 4), (300, 4),
-          (61, 5), (47, 7), (150, 6), (400, 8), (3, 8)]
+          (61, 5), (47, 7), (150, 6), (400, 8), (3, 8), (33, 10), (130, 10), (90, 12), (20, 16), (70, 16)]
 
 
 def _problem(n, d, c=0.3, seed=0, eps=0.05):
@@ -80,7 +80,7 @@ def test_symmetric_tile_shapes_agree(W, H, monkeypatch):
     assert np.abs(host(Xout) - ref.X).max() <= step_tolerance(As, host(Xin), n, P.F32)
 
 
-@pytest.mark.parametrize("d", [1, 3, 5, 8])
+@pytest.mark.parametrize("d", [1, 3, 5, 8, 16])
 def test_values_on_and_below_the_block_diagonal_are_never_used(d):
     """NaN in every block on or below the block diagonal, and in the padding
     columns, must not reach the result."""
