@@ -30,7 +30,7 @@ __all__ = [
     "euclidean_gradient", "tangent_projection", "rgs_step", "StepResult", "block_step",
     "spectral_subspace", "spectral_init", "solve", "SolveResult", "objective",
     "partial_objective", "procrustes", "dist_F", "alignment_error", "rel_err",
-    "mse", "rel_change", "objective_ratio",
+    "mse", "rel_change", "objective_ratio", "gpm_step", "block_gradient",
 ]
 
 
@@ -173,13 +173,43 @@ def block_step(A_rows_i: np.ndarray, X: np.ndarray, d: int, i: int, mu: float | 
     n = Xb.shape[0]
     if mu is None:
         mu = 1.0 / n
-    Ai = np.asarray(A_rows_i, dtype=np.float64)                        # [A_i1 ... A_in]
-    s = slice(i * d, (i + 1) * d)
-    C = Ai @ X - Ai[:, s] @ Xb[i]                                      # sum over j != i
-    G = (n - 1) * Xb[i] - C
+    G = block_gradient(A_rows_i, X, d, i)
     P = 0.5 * (G - Xb[i] @ G.T @ Xb[i])
     F = Xb[i] - mu * P
     return newton_schulz(F, Ts)
+
+
+def block_gradient(A_rows_i: np.ndarray, X: np.ndarray, d: int, i: int) -> np.ndarray:
+    """G_i = (n - 1) X_i - sum_{j != i} A_ij X_j for one block i, from its d rows
+    of A (shape (d, n*d)) and the whole iterate (the gradient of Algorithm 2)."""
+    X = np.asarray(X, dtype=np.float64)
+    Xb = as_blocks(X, d)
+    n = Xb.shape[0]
+    Ai = np.asarray(A_rows_i, dtype=np.float64)                        # [A_i1 ... A_in]
+    s = slice(i * d, (i + 1) * d)
+    C = Ai @ X - Ai[:, s] @ Xb[i]                                      # sum over j != i
+    return (n - 1) * Xb[i] - C
+
+
+def gpm_step(A: np.ndarray, X: np.ndarray, d: int) -> StepResult:
+    """One step of the generalized power method that Sec. 4.1 compares against:
+    X_i^{t+1} = sgn((A X^t)_i) for every block i.
+
+    The paper cites the method and does not print it; this is its usual form
+    (the projection of the power iterate A X^t onto O(d)^n, block by block),
+    with the whole block row of A, the diagonal block included (A_ii = I in
+    the paper's model, so (A X)_i = X_i + sum_{j != i} A_ij X_j).  The
+    returned G and F are the power iterate A X^t; max_orth_defect is that of
+    the new iterate.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    P = np.asarray(A, dtype=np.float64) @ X
+    Xn = sgn_blocks(P, d)
+    Xb = as_blocks(Xn, d)
+    eye = np.eye(d)
+    defect = np.linalg.norm(eye - np.swapaxes(Xb, -1, -2) @ Xb, axis=(1, 2))
+    return StepResult(X=Xn, F=P, G=P, max_orth_defect=float(defect.max()),
+                      rel_change=rel_change(Xn, X))
 
 
 # ---------------------------------------------------------------------------
@@ -245,7 +275,13 @@ def partial_objective(A: np.ndarray, X: np.ndarray, d: int, i: int) -> float:
 
 
 def rel_change(Xn: np.ndarray, X: np.ndarray) -> float:
-    """||X^{t+1} - X^t||_F / ||X^t||_F."""
+    """||X^{t+1} - X^t||_F / ||X^t||_F.
+
+    The relative change of the iterate, the stop rule the serving workload
+    names ("relative-change tolerance").  The paper's own rule is the
+    objective ratio R^t below; this reading of "relative change" as a
+    Frobenius ratio of iterates is the library's, not the paper's.
+    """
     return float(np.linalg.norm(Xn - X) / np.linalg.norm(X))
 
 
@@ -271,8 +307,14 @@ class SolveResult:
 def solve(A: np.ndarray, d: int, mu: float | None = None, Ts: int = 3,
           T: int = 100, retraction: str = "ns", stop: str = "fixed",
           tol: float = 0.0, X0: np.ndarray | None = None,
-          dense_limit: int = 3000) -> SolveResult:
+          dense_limit: int = 3000, method: str = "rgs") -> SolveResult:
     """Algorithm 2: spectral initialization, then at most T Jacobi sweeps.
+
+    method="rgs" : the Riemannian gradient step of Algorithm 2 with the
+                   given retraction.
+    method="gpm" : the generalized power method of the Sec. 4.1 comparison
+                   (``gpm_step``) from the same initialization and with the
+                   same stop rules; mu, Ts and retraction are unused.
 
     stop="fixed"      : run exactly T iterations.
     stop="rel_change" : stop after the first iteration with
@@ -286,7 +328,12 @@ def solve(A: np.ndarray, d: int, mu: float | None = None, Ts: int = 3,
     res = SolveResult(X=X, X0=np.array(X0, copy=True), iters=0)
     F_prev = objective(A, X, d) if stop == "objective" else None
     for t in range(int(T)):
-        st = rgs_step(A, X, d, mu=mu, Ts=Ts, retraction=retraction)
+        if method == "rgs":
+            st = rgs_step(A, X, d, mu=mu, Ts=Ts, retraction=retraction)
+        elif method == "gpm":
+            st = gpm_step(A, X, d)
+        else:
+            raise ValueError(method)
         X = st.X
         res.iters = t + 1
         res.rel_changes.append(st.rel_change)
