@@ -49,7 +49,7 @@ def host(t: torch.Tensor) -> np.ndarray:
     return t.detach().cpu().double().numpy()
 
 
-def step_tolerance(As: np.ndarray, X: np.ndarray, n: int, fmt: int) -> float:
+def step_tolerance(As: np.ndarray, X: np.ndarray, n: int, fmt: int, mu: float | None = None) -> float:
     """Absolute error bound for one step, from the arithmetic.
 
     The product sum_j A_ij X_j accumulates in the format's accumulation
@@ -60,7 +60,7 @@ def step_tolerance(As: np.ndarray, X: np.ndarray, n: int, fmt: int) -> float:
     few eps of the O(1) entries.
     """
     eps = EPS.get(fmt, EPS32)
-    mu = 1.0 / n
+    mu = 1.0 / n if mu is None else mu
     prod = np.abs(As) @ np.abs(X)
     return 16.0 * eps * mu * float(prod.max()) * 8.0 + 64.0 * eps * max(1.0, float(np.abs(X).max()))
 
@@ -76,3 +76,20 @@ def rel(a, b):
 
 def sqrt_n(n):
     return math.sqrt(n)
+
+
+def check_stop_iteration(gpu_iters: int, ref, tol: float, slack: float) -> None:
+    """The GPU's relative-change stop fired where the oracle's sequence says it
+    should: at the oracle's own stop iteration, or, when the oracle's relative
+    change lies within a factor (1 +- slack) of tol at the boundary, at the
+    neighbouring one.  ``slack`` states how far rounding can move the monitor:
+    ~1e-6 for FP64 arithmetic, a few tens of percent for FP32 accumulation,
+    whose iterate noise (~2^-24 relative) is a visible fraction of a 1e-6 change.
+    ``ref`` is an oracle solve run with stop="rel_change" and the same tol,
+    long enough to cover gpu_iters."""
+    if gpu_iters == ref.iters:
+        return
+    rc = ref.rel_changes
+    assert abs(gpu_iters - ref.iters) == 1, (gpu_iters, ref.iters)
+    k = min(gpu_iters, ref.iters) - 1          # the iteration the two disagree on
+    assert abs(rc[k] / tol - 1.0) <= slack, (gpu_iters, ref.iters, rc[k], tol)

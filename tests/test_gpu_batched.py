@@ -10,7 +10,7 @@ import paper_2604_07372_amd as P
 import synth
 from oracle import nsrgs as O
 
-from gpu_common import FMT_NAME, device_matrix, host, oracle_matrix, require_gpu, to_dev, xdtype
+from gpu_common import FMT_NAME, check_stop_iteration, device_matrix, host, oracle_matrix, require_gpu, to_dev, xdtype
 
 # Largest d is 16 (the widest kernel class).
 MIX = [(2, 1), (5, 2), (37, 3), (100, 4), (61, 10), (341, 3), (20, 16), (130, 2), (47, 7), (700, 3)]
@@ -99,7 +99,8 @@ def test_persistent_budgets_tolerance_and_nonfinite():
     assert st == 6                                        # the non-finite problem
     assert infos[0]["iters"] == 5
     ref1 = O.solve(refs[1][1], 2, Ts=3, T=200, stop="rel_change", tol=1e-7, X0=X0[1])
-    assert infos[1]["converged"] == 1 and abs(infos[1]["iters"] - ref1.iters) <= 1
+    assert infos[1]["converged"] == 1
+    check_stop_iteration(infos[1]["iters"], ref1, 1e-7, slack=1e-6)
     assert infos[2]["iters"] == 200
     assert infos[3]["nonfinite"] == 1 and infos[3]["iters"] == 1
     for k, T in ((0, 5), (2, 200), (1, infos[1]["iters"])):
@@ -215,7 +216,8 @@ def test_grouped_per_problem_budgets_and_tolerance():
     assert st == 0
     assert infos[0]["iters"] == 5
     ref1 = O.solve(refs[1][1], 2, Ts=3, T=200, stop="rel_change", tol=1e-7, X0=X0[1])
-    assert infos[1]["converged"] == 1 and abs(infos[1]["iters"] - ref1.iters) <= 1
+    assert infos[1]["converged"] == 1
+    check_stop_iteration(infos[1]["iters"], ref1, 1e-7, slack=1e-6)
     assert infos[2]["iters"] == 200
     for k, T in ((0, 5), (2, 200)):
         ref = O.solve(refs[k][1], probs[k]["d"], Ts=3, T=T, X0=X0[k])

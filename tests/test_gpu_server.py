@@ -10,7 +10,7 @@ import synth
 from oracle import nsrgs as O
 from oracle import quantize as Q
 
-from gpu_common import require_gpu
+from gpu_common import check_stop_iteration, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -55,7 +55,18 @@ def test_served_result_matches_oracle(fmt):
     e_g, e_o = O.alignment_error(X.astype(np.float64), Z), O.alignment_error(ref.X, Z)
     print(f"served fmt={fmt}: iters {r['iters']} (oracle {ref.iters}), e {e_g:.6f} vs {e_o:.6f}", flush=True)
     assert abs(e_g - e_o) <= 1e-4 * e_o
-    assert abs(r["iters"] - ref.iters) <= 3
+    # FP32 accumulation: the iterate's rounding noise (~2^-24 relative) is a
+    # few percent of a 1e-6 relative change, so the stop may move by one
+    # iteration only where the oracle's change is that close to the tolerance.
+    check_stop_iteration(r["iters"], ref, 1e-6, slack=0.25)
+    # the served result is the oracle's iterate at the served iteration count
+    X0 = O.spectral_init(A, d)
+    exact = O.solve(A, d, Ts=3, T=r["iters"], X0=X0)
+    dist = O.dist_F(X.astype(np.float64), exact.X) / math.sqrt(n)
+    e_x = O.alignment_error(exact.X, Z)
+    print(f"served fmt={fmt}: d_F to the oracle at the same count {dist:.3e}", flush=True)
+    assert abs(e_g - e_x) <= 1e-4 * e_x
+    assert dist <= 1e-4 * e_x
 
 
 def test_admission_by_footprint_and_oversize_rejection():
