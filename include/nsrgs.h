@@ -133,6 +133,30 @@ int sync_step(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps,
               const void *X_in, void *X_out, void *ws, size_t ws_bytes,
               void *stream);
 
+/* ---- sync_step_noalloc: sync_step without a caller workspace -------------
+ * For callers that cannot allocate device memory or pass a workspace: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Computes exactly what sync_step computes (same kernels, same
+ * launch shape, bitwise the same X_out), but its scratch -- the control block
+ * and one 32-byte monitor record per panel -- is a fixed library-owned array
+ * of NSRGS_NOALLOC_SCRATCH_BYTES bytes of device memory, one copy per GPU,
+ * held until the process ends.  The call allocates nothing (no hipMalloc, no
+ * hipFree, no allocating library routine); on its first use on a device it
+ * looks up that device's copy of the array (hipGetSymbolAddress).
+ * Limits: the sync_step checks, and at most (NSRGS_NOALLOC_SCRATCH_BYTES -
+ * 4352) / 32 panels (panels = ceil(n d / (B d)), B the launch shape's blocks
+ * per panel, so n <= 130000 for every shape); a larger problem is refused
+ * with NSRGS_ERR_OUT_OF_MEMORY before any device work.
+ * The monitors are not readable through sync_read_info (they live in the
+ * library's array, not in a caller workspace).
+ * Every call on one GPU shares that GPU's array and the array keeps the last
+ * call's contents: calls on the same stream are ordered and safe, calls that
+ * overlap on one GPU (different streams or threads without ordering) race.
+ * Asynchronous, like sync_step. */
+#define NSRGS_NOALLOC_SCRATCH_BYTES (4u << 20)
+int sync_step_noalloc(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps,
+                      const void *X_in, void *X_out, void *stream);
+
 /* ---- sync_step_symmetric: sync_step reading half of A ---------------------
  * The measurement matrix is symmetric, A_ji = A_ij^T (Sec. 2.2), so every
  * product term of the step is available from the blocks above the block

@@ -140,6 +140,7 @@ def lib() -> ctypes.CDLL:
         "sync_workspace_bytes": (sz, [i32, i32, i32]),
         "sync_workspace_init": (i32, [vp, sz, vp]),
         "sync_step": (i32, [pm, i32, i32, dbl, i32, vp, vp, vp, sz, vp]),
+        "sync_step_noalloc": (i32, [pm, i32, i32, dbl, i32, vp, vp, vp]),
         "sync_step_symmetric_workspace_bytes": (sz, [i32, i32, i32]),
         "sync_step_symmetric": (i32, [pm, i32, i32, dbl, i32, vp, vp, vp, sz, vp]),
         "nsrgs_bsr_count": (i32, [vp, i32, i32, dbl, ctypes.c_uint64, vp, vp, ctypes.POINTER(i64), vp]),
@@ -312,6 +313,17 @@ def step(A: StoredMatrix, n: int, d: int, X_in: torch.Tensor, X_out: torch.Tenso
     m = A.c()
     _check(lib().sync_step(ctypes.byref(m), n, d, float(mu), int(ns_steps), X_in.data_ptr(),
                            X_out.data_ptr(), ws.ptr, ws.nbytes, _stream()))
+
+
+def step_noalloc(A: StoredMatrix, n: int, d: int, X_in: torch.Tensor, X_out: torch.Tensor,
+                 mu: float = 0.0, ns_steps: int = 3) -> None:
+    """sync_step_noalloc: sync_step with the library's fixed scratch instead of a
+    workspace (allocates nothing); asynchronous on the current stream."""
+    _check_x(X_in, n * d, d, A.fmt, "X_in")
+    _check_x(X_out, n * d, d, A.fmt, "X_out")
+    m = A.c()
+    _check(lib().sync_step_noalloc(ctypes.byref(m), n, d, float(mu), int(ns_steps), X_in.data_ptr(),
+                                   X_out.data_ptr(), _stream()))
 
 
 def step_symmetric(A: StoredMatrix, n: int, d: int, X_in: torch.Tensor, X_out: torch.Tensor,

@@ -63,6 +63,12 @@ int step_with_config(const nsrgs_matrix *A, int n, int d, double mu, int ns_step
 int check_step_args(const nsrgs_matrix *A, int n, int d, int ns_steps, const void *X_in, void *X_out,
                     void *ws, size_t ws_bytes);
 
+// sync_step with its argument checks, the control block at `ctl` and room
+// for stats_bytes of panel monitors at `stats` (runtime.hip).
+struct DevCtl;
+int step_checked_into(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
+                      void *X_out, DevCtl *ctl, void *stats, size_t stats_bytes, hipStream_t s);
+
 // Bytes of the single-problem workspace (control block, panel monitors,
 // iterate and initialization buffers) and the offset of its panel monitors
 // (runtime.hip).

@@ -238,19 +238,19 @@ int sync_workspace_init(void *ws, size_t ws_bytes, void *stream) {
   return NSRGS_OK;
 }
 
-// One step launch; `force` (nullable) replaces the chosen launch shape.
-static int step_impl(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps,
-                     const void *X_in, void *X_out, void *ws, hipStream_t s, int iter,
-                     double tol, bool check_done, const StreamConfig *force = nullptr) {
+// One step launch with the control block and panel monitors at given
+// addresses; `force` (nullable) replaces the chosen launch shape.
+static int step_into(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps,
+                     const void *X_in, void *X_out, DevCtl *ctl, void *stats, hipStream_t s,
+                     int iter, double tol, bool check_done, const StreamConfig *force = nullptr) {
   const StreamConfig cfg = force ? *force : choose_stream_config(A->fmt, d, n * d, 0);
   StreamArgs a = make_args(A, n, d, cfg);
-  const WsLayout L = layout(n, d, A->fmt);
   a.X_in = X_in;
   a.X_out = X_out;
   a.mu = mu > 0.0 ? mu : 1.0 / n;
   a.ns_steps = ns_steps;
-  a.partials = static_cast<char *>(ws) + L.stats;
-  a.ctl = static_cast<DevCtl *>(ws);
+  a.partials = stats;
+  a.ctl = ctl;
   a.iter = iter;
   a.tol = tol;
   a.stop_flag = check_done ? &a.ctl->done : nullptr;
@@ -258,24 +258,56 @@ static int step_impl(const nsrgs_matrix *A, int n, int d, double mu, int ns_step
   return NSRGS_OK;
 }
 
-int sync_step(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
-              void *X_out, void *ws, size_t ws_bytes, void *stream) {
+static int step_impl(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps,
+                     const void *X_in, void *X_out, void *ws, hipStream_t s, int iter,
+                     double tol, bool check_done, const StreamConfig *force = nullptr) {
+  const WsLayout L = layout(n, d, A->fmt);
+  return step_into(A, n, d, mu, ns_steps, X_in, X_out, static_cast<DevCtl *>(ws),
+                   static_cast<char *>(ws) + L.stats, s, iter, tol, check_done, force);
+}
+
+// sync_step's checks of everything but the workspace.
+static int check_step_io(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps,
+                         const void *X_in, const void *X_out) {
   int st;
   if ((st = check_common(n, d))) return st;
   if ((st = check_matrix(A, n, d))) return st;
-  if ((st = check_ws(ws, ws_bytes, n, d, A->fmt))) return st;
   if (!X_in || !X_out) return fail(NSRGS_ERR_INVALID_ARG, "X_in / X_out is NULL");
   if (!aligned16(X_in) || !aligned16(X_out)) return fail(NSRGS_ERR_INVALID_ARG, "X buffers must be 16-byte aligned");
   if (ns_steps < 0 || ns_steps > 64) return fail(NSRGS_ERR_INVALID_ARG, "ns_steps must be in [0, 64]");
   if (!std::isfinite(mu)) return fail(NSRGS_ERR_INVALID_ARG, "mu must be finite");
   const size_t xb = (size_t)n * d * d * xbytes(A->fmt);
   if (overlap(X_in, X_out, xb)) return fail(NSRGS_ERR_INVALID_ARG, "X_in and X_out overlap");
+  return NSRGS_OK;
+}
+
+int sync_step(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
+              void *X_out, void *ws, size_t ws_bytes, void *stream) {
+  int st;
+  if ((st = check_step_io(A, n, d, mu, ns_steps, X_in, X_out))) return st;
+  if ((st = check_ws(ws, ws_bytes, n, d, A->fmt))) return st;
   return step_impl(A, n, d, mu, ns_steps, X_in, X_out, ws, (hipStream_t)stream, 0, 0.0, false);
 }
 
 }  // extern "C"
 
 namespace nsrgs {
+// sync_step with caller-placed control block and panel monitors: the
+// no-allocation entry point's path.  The arguments are checked here.
+int step_checked_into(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
+                      void *X_out, DevCtl *ctl, void *stats, size_t stats_bytes, hipStream_t s) {
+  int st;
+  if ((st = check_step_io(A, n, d, mu, ns_steps, X_in, X_out))) return st;
+  const StreamConfig cfg = choose_stream_config(A->fmt, d, n * d, 0);
+  const int R = cfg.blocks_per_panel * d;
+  const size_t panels = (size_t)(n * d + R - 1) / R;
+  if (panels * sizeof(PanelStat) > stats_bytes)
+    return fail(NSRGS_ERR_OUT_OF_MEMORY,
+                "problem too large for the fixed scratch: %zu panel monitors need %zu bytes, %zu available",
+                panels, panels * sizeof(PanelStat), stats_bytes);
+  return step_into(A, n, d, mu, ns_steps, X_in, X_out, ctl, stats, s, 0, 0.0, false, &cfg);
+}
+
 size_t step_ws_bytes(int n, int d, int fmt) { return layout(n, d, fmt).total; }
 size_t step_ws_stats_offset(int n, int d, int fmt) { return layout(n, d, fmt).stats; }
 
