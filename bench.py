@@ -254,6 +254,93 @@ def serving_bench(window_s: float = 10.0, rate: float = 50.0, seed0: int = 5000)
     return out
 
 
+def table1_bench(steps: int = 50, warmup: int = 5, seed: int = 61):
+    """The paper's own comparison (Sec. 4.1, Table 1) at its shape, n = 500,
+    d = 25, p = 1, W_ii = 0, on the matrix-core path: time per iteration of
+    NS-RGS (one Newton-Schulz step), the exact polar retraction and GPM, with A
+    in FP64 (the paper's MATLAB precision) and FP32; then the whole Table 1
+    protocol per method in FP64 (spectral initialization, iterations until
+    R^t < 1e-8 or 100, mu = 1/n) at sigma = 0.02, 0.1, 0.2 with its Rel. Err.
+    The paper's CPU times (Intel i9-14900HX, MATLAB) are quoted as context."""
+    import torch
+    import paper_2604_07372_amd as P
+    import synth
+    from oracle import nsrgs as O
+    n, d = 500, 25
+    nd = n * d
+    Z = synth.haar_blocks(n, d, seed)
+    Zd = torch.from_numpy(Z).cuda()
+    paper_s = {"ns_rgs": {0.02: 0.154, 0.1: 0.158, 0.2: 0.161}, "gpm": {0.02: 0.282, 0.1: 0.287, 0.2: 0.289}}
+    out = {"n": n, "d": d, "per_iteration": {}, "protocol": {}, "paper_cpu_s_p1": paper_s}
+    for fname, fmt, eb in (("f64", P.F64, 8), ("f32", P.F32, 4)):
+        A = P.generate(Zd, 0.1, seed + 1, fmt=fmt, zero_diag_blocks=True)
+        Am = P.stored(A, fmt)
+        ws = P.workspace(n, d, fmt)
+        dt = torch.float64 if fmt == P.F64 else torch.float32
+        X0 = torch.from_numpy(synth.perturbed_start(Z, 0.02, seed + 2)).to("cuda", dt)
+        res = {}
+        for method in ("ns_rgs", "polar", "gpm"):
+            def one(xi, xo):
+                if method == "ns_rgs":
+                    P.step(Am, n, d, xi, xo, ws, ns_steps=1)
+                elif method == "polar":
+                    P.step_polar(Am, n, d, xi, xo, ws)
+                else:
+                    P.step_gpm(Am, n, d, xi, xo, ws)
+            Xa, Xb = X0.clone(), torch.empty_like(X0)
+            for _ in range(warmup):
+                one(Xa, Xb)
+                Xa, Xb = Xb, Xa
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                one(Xa, Xb)
+                Xa, Xb = Xb, Xa
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            alg = nd * nd * eb + 2 * nd * d * eb
+            res[method] = {"ms_per_iter": ms, "iters_per_s": 1e3 / ms, "alg_GBps": alg / (ms * 1e-3) / 1e9,
+                           "product_TFLOPs_algorithmic": 2.0 * nd * nd * d / (ms * 1e-3) / 1e12}
+            print(f"[bench] table1 shape {fname} {method}: {ms * 1e3:.1f} us/iter, {res[method]['alg_GBps']:.0f} GB/s",
+                  file=sys.stderr, flush=True)
+        res["ns_rgs_speedup_vs_gpm"] = res["gpm"]["ms_per_iter"] / res["ns_rgs"]["ms_per_iter"]
+        res["ns_rgs_speedup_vs_polar"] = res["polar"]["ms_per_iter"] / res["ns_rgs"]["ms_per_iter"]
+        out["per_iteration"][fname] = res
+        del A, Am, ws
+        torch.cuda.empty_cache()
+    for sigma in (0.02, 0.1, 0.2):
+        A = P.generate(Zd, sigma, seed + 3, fmt=P.F64, zero_diag_blocks=True)
+        Am = P.stored(A, P.F64)
+        ws = P.workspace(n, d, P.F64)
+        X0 = torch.empty((nd, d), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        init = P.init_spectral(Am, n, d, X0, ws, max_iters=300)
+        t_init = time.perf_counter() - t0
+        row = {"init_s": t_init, "init_iters": init["iters"]}
+        for method in ("ns_rgs", "gpm"):
+            X = X0.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = P.solve(Am, n, d, X, ws, ns_steps=1, max_iters=100, tol=1e-8, init=False, method=method,
+                           stop="objective", check=False)
+            t = time.perf_counter() - t0
+            row[method] = {"iterate_s": t, "iters": info["iters"], "status": info["status"],
+                           "rel_err": O.rel_err(X.cpu().numpy(), Z, form="gram"),
+                           "paper_cpu_s": paper_s[method][sigma]}
+        row["ns_rgs_speedup_vs_gpm_iterations"] = row["gpm"]["iterate_s"] / row["ns_rgs"]["iterate_s"]
+        out["protocol"][f"sigma={sigma}"] = row
+        print(f"[bench] table1 protocol sigma={sigma}: init {t_init * 1e3:.1f} ms; NS-RGS {row['ns_rgs']['iters']} it "
+              f"{row['ns_rgs']['iterate_s'] * 1e3:.1f} ms Rel.Err {row['ns_rgs']['rel_err']:.3e}; GPM "
+              f"{row['gpm']['iters']} it {row['gpm']['iterate_s'] * 1e3:.1f} ms Rel.Err {row['gpm']['rel_err']:.3e}",
+              file=sys.stderr, flush=True)
+        del A, Am, ws
+        torch.cuda.empty_cache()
+    return out
+
+
 def alignment_error(X, Z) -> float:
     """min over Q in O(d) of ||X - Z Q||_F / sqrt(n), Q from the SVD of Z^T X."""
     import numpy as np
@@ -288,6 +375,7 @@ def main(argv=None):
     ap.add_argument("--no-symmetric", action="store_true")
     ap.add_argument("--no-masked", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-table1", action="store_true")
     ap.add_argument("--serving-window", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (counter calibration)")
@@ -459,6 +547,7 @@ def main(argv=None):
     masked = None if a.no_masked else {
         f"p={pm}": masked_bench(Zd, sigma, results["f32"]["ms_per_step"], a.steps, a.warmup, p=pm)
         for pm in (0.5, 0.2)}
+    table1 = None if a.no_table1 else table1_bench()
     batched = None if a.no_batched else batched_bench()
     serving = None if a.no_serving else serving_bench(window_s=a.serving_window)
 
@@ -494,6 +583,7 @@ def main(argv=None):
         "symmetric_step": symmetric,
         "masked_step": masked,
         "solve": solve,
+        "table1_shape": table1,
         "batched": batched,
         "serving": serving,
     }

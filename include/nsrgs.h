@@ -29,7 +29,11 @@
  * - Return value: an nsrgs_status.  On error nothing has been enqueued and
  *   nsrgs_last_error() (per calling thread) describes the problem.  Device
  *   errors of earlier asynchronous work surface as NSRGS_ERR_DEVICE.
- * - Limits: 2 <= n, 1 <= d <= 16, n*d < 2^31.
+ * - Limits: 2 <= n, 1 <= d <= 16, n*d < 2^31.  sync_step, sync_step_polar,
+ *   sync_step_gpm, sync_init_spectral, sync_solve, sync_read_info,
+ *   sync_workspace_bytes and nsrgs_generate_measurement also take
+ *   16 < d <= 32 with F64 or F32 storage (the matrix-core path; other formats
+ *   are refused with NSRGS_ERR_UNSUPPORTED).
  * - The library never allocates device memory inside sync_step / sync_solve /
  *   sync_init_spectral: scratch space is the caller's workspace `ws` of
  *   sync_workspace_bytes() bytes, prepared once by sync_workspace_init().
@@ -89,7 +93,33 @@ typedef struct {
   double init_residual;     /* init: ||A Y - Y T||_F / ||T||_F of the last iteration */
   double ritz[16];          /* init: top-d Ritz values (descending)                 */
   double ritz_next;         /* reserved (NaN)                                        */
+  double objective;         /* F(X^t) of eq. (def:f) at the last evaluation, on the
+                               matrix-core path with the objective stop rule (else NaN) */
+  double objective_ratio;   /* R^{t-1} = (F(X^{t-1}) - F(X^t)) / F(X^t) (Sec. 4.1),
+                               same conditions (NaN before two evaluations)        */
+  double ritz_more[16];     /* init with d > 16: Ritz values 17 .. d               */
 } nsrgs_info;
+
+/* Retraction of sync_solve (Sec. 4.1 compares the three):
+ *   NS_RGS: X_i <- Ts Newton-Schulz steps from F_i (Algorithms 1 and 2);
+ *   POLAR : X_i <- sgn(F_i), the exact retraction (the sequence with a tilde
+ *           in Sec. 3), F_i as in NS-RGS;
+ *   GPM   : X_i <- sgn((A X)_i), the generalized power method, whole block
+ *           row including the diagonal block.
+ * sgn(M) = U V^T for M = U Sigma V^T (Sec. 2.1) is computed to FP64 accuracy. */
+typedef enum { NSRGS_METHOD_NS_RGS = 0, NSRGS_METHOD_POLAR = 1, NSRGS_METHOD_GPM = 2 } nsrgs_method;
+
+/* Stop rule of sync_solve when tol > 0:
+ *   REL_CHANGE: after the first iteration with ||X^{t+1}-X^t||_F/||X^t||_F <= tol;
+ *   OBJECTIVE : the paper's rule (Sec. 4.1), after the first iteration t with
+ *               R^t = (F(X^t) - F(X^{t+1})) / F(X^{t+1}) < tol, returning X^{t+1}.
+ *               F (eq. def:f) is evaluated in FP64 from per-block pieces of
+ *               the product the step computes anyway, plus X^T X and, once per
+ *               solve, sum_{i != j} ||A_ij||_F^2; the evaluation of F(X^{t+1})
+ *               happens inside the next iteration, whose own output is then
+ *               discarded.  With F32 storage the product's rounding (about
+ *               1e-7 of its terms) limits how small a ratio can be resolved. */
+typedef enum { NSRGS_STOP_REL_CHANGE = 0, NSRGS_STOP_OBJECTIVE = 1 } nsrgs_stop_rule;
 
 /* Options of sync_solve beyond the arguments named in its signature.
  * Pass NULL for the defaults given in brackets. */
@@ -104,6 +134,9 @@ typedef struct {
   int32_t symmetric;        /* 1: every iteration is sync_step_symmetric's (A and
                                A_refine exactly symmetric, formats and d as there;
                                ws of sync_step_symmetric_workspace_bytes) [0]      */
+  int32_t method;           /* nsrgs_method [NS_RGS]; POLAR and GPM need F64 or F32 */
+  int32_t stop_rule;        /* nsrgs_stop_rule [REL_CHANGE]; OBJECTIVE needs F64 or
+                               F32 storage and no refinement                      */
 } nsrgs_solve_opts;
 
 /* ---- status and version ------------------------------------------------ */
@@ -127,11 +160,32 @@ int sync_workspace_init(void *ws, size_t ws_bytes, void *stream);
  * A is streamed from memory once; C, G and F stay on chip.
  * mu <= 0 selects mu = 1/n (Theorem 3.1).  ns_steps in [0, 64].
  * X_in and X_out are n*d x d device arrays that must not overlap.
+ * For d > 16 (F64 / F32 storage) the product runs on the matrix cores
+ * (v_mfma 16x16x4 tiles over column chunks, partial sums in the workspace)
+ * and the per-block part in FP64.
  * Monitors (rel_change, max_orth_defect, nonfinite) go to the workspace and
  * can be read with sync_read_info.  Asynchronous. */
 int sync_step(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps,
               const void *X_in, void *X_out, void *ws, size_t ws_bytes,
               void *stream);
+
+/* ---- the retractions the paper compares (Sec. 4.1) ------------------------
+ * sync_step_polar: one step of Algorithm 2 with the exact retraction,
+ *   X_out_i = sgn(F_i), F_i = X_in_i - mu (G_i - X_in_i G_i^T X_in_i)/2 as in
+ *   sync_step (the sequence with a tilde in Sec. 3).
+ * sync_step_gpm: one step of the generalized power method,
+ *   X_out_i = sgn(sum_j A_ij X_in_j) over the whole block row (diagonal
+ *   block included).
+ * sgn(M) = U V^T (Sec. 2.1) is formed to FP64 accuracy by Newton-Schulz from
+ * M scaled by the Gershgorin bound of M^T M, iterated to convergence (a
+ * singular or non-finite M is reported as non-finite).  Both use the
+ * matrix-core product (F64 or F32 storage, 1 <= d <= 32), allocate nothing,
+ * take the sync_step workspace and are asynchronous; monitors as sync_step's
+ * (for GPM, max_orth_defect is that of the output). */
+int sync_step_polar(const nsrgs_matrix *A, int n, int d, double mu, const void *X_in, void *X_out,
+                    void *ws, size_t ws_bytes, void *stream);
+int sync_step_gpm(const nsrgs_matrix *A, int n, int d, const void *X_in, void *X_out, void *ws,
+                  size_t ws_bytes, void *stream);
 
 /* ---- sync_step_noalloc: sync_step without a caller workspace -------------
  * For callers that cannot allocate device memory or pass a workspace: code
@@ -450,7 +504,7 @@ int nsrgs_autotune_batched(const nsrgs_problem *probs, int count, int ns_steps, 
  * zero_diag_blocks != 0 sets W_ii = 0 (paper's model, A_ii = I).  p < 1 keeps
  * an off-diagonal block pair with probability p (counter (j, i, 1, 0) for
  * blocks i < j, uniform from the first output word), else A_ij = A_ji = 0.
- * Z is an n*d x d double device array.  Asynchronous. */
+ * Z is an n*d x d double device array; 1 <= d <= 32.  Asynchronous. */
 int nsrgs_generate_measurement(const double *Z, int n, int d, double sigma,
                                uint64_t seed, int zero_diag_blocks, double p,
                                int fmt, void *A, int64_t ld, void *stream);

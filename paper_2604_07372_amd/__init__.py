@@ -44,11 +44,12 @@ class Info(ctypes.Structure):
                 ("converged", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("rel_change", ctypes.c_double), ("max_orth_defect", ctypes.c_double),
                 ("init_residual", ctypes.c_double), ("ritz", ctypes.c_double * 16),
-                ("ritz_next", ctypes.c_double)]
+                ("ritz_next", ctypes.c_double), ("objective", ctypes.c_double),
+                ("objective_ratio", ctypes.c_double), ("ritz_more", ctypes.c_double * 16)]
 
     def as_dict(self, d: int | None = None) -> dict:
-        out = {k: getattr(self, k) for k, _ in self._fields_ if k != "ritz"}
-        out["ritz"] = list(self.ritz)[: (d or 16)]
+        out = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("ritz", "ritz_more")}
+        out["ritz"] = (list(self.ritz) + list(self.ritz_more))[: (d or 16)]
         return out
 
 
@@ -61,7 +62,7 @@ class _SolveOpts(ctypes.Structure):
     _fields_ = [("init", ctypes.c_int32), ("init_iters", ctypes.c_int32),
                 ("init_tol", ctypes.c_double), ("refine_iters", ctypes.c_int32),
                 ("A_refine", ctypes.POINTER(_Matrix)), ("check_every", ctypes.c_int32),
-                ("symmetric", ctypes.c_int32)]
+                ("symmetric", ctypes.c_int32), ("method", ctypes.c_int32), ("stop_rule", ctypes.c_int32)]
 
 
 class _Problem(ctypes.Structure):
@@ -141,6 +142,8 @@ def lib() -> ctypes.CDLL:
         "sync_workspace_init": (i32, [vp, sz, vp]),
         "sync_step": (i32, [pm, i32, i32, dbl, i32, vp, vp, vp, sz, vp]),
         "sync_step_noalloc": (i32, [pm, i32, i32, dbl, i32, vp, vp, vp]),
+        "sync_step_polar": (i32, [pm, i32, i32, dbl, vp, vp, vp, sz, vp]),
+        "sync_step_gpm": (i32, [pm, i32, i32, vp, vp, vp, sz, vp]),
         "sync_step_symmetric_workspace_bytes": (sz, [i32, i32, i32]),
         "sync_step_symmetric": (i32, [pm, i32, i32, dbl, i32, vp, vp, vp, sz, vp]),
         "nsrgs_bsr_count": (i32, [vp, i32, i32, dbl, ctypes.c_uint64, vp, vp, ctypes.POINTER(i64), vp]),
@@ -315,6 +318,25 @@ def step(A: StoredMatrix, n: int, d: int, X_in: torch.Tensor, X_out: torch.Tenso
                            X_out.data_ptr(), ws.ptr, ws.nbytes, _stream()))
 
 
+def step_polar(A: StoredMatrix, n: int, d: int, X_in: torch.Tensor, X_out: torch.Tensor,
+               ws: Workspace, mu: float = 0.0) -> None:
+    """sync_step_polar: one step with the exact retraction sgn(F_i)."""
+    _check_x(X_in, n * d, d, A.fmt, "X_in")
+    _check_x(X_out, n * d, d, A.fmt, "X_out")
+    m = A.c()
+    _check(lib().sync_step_polar(ctypes.byref(m), n, d, float(mu), X_in.data_ptr(), X_out.data_ptr(),
+                                 ws.ptr, ws.nbytes, _stream()))
+
+
+def step_gpm(A: StoredMatrix, n: int, d: int, X_in: torch.Tensor, X_out: torch.Tensor, ws: Workspace) -> None:
+    """sync_step_gpm: one generalized-power-method step X_i <- sgn((A X)_i)."""
+    _check_x(X_in, n * d, d, A.fmt, "X_in")
+    _check_x(X_out, n * d, d, A.fmt, "X_out")
+    m = A.c()
+    _check(lib().sync_step_gpm(ctypes.byref(m), n, d, X_in.data_ptr(), X_out.data_ptr(), ws.ptr, ws.nbytes,
+                               _stream()))
+
+
 def step_noalloc(A: StoredMatrix, n: int, d: int, X_in: torch.Tensor, X_out: torch.Tensor,
                  mu: float = 0.0, ns_steps: int = 3) -> None:
     """sync_step_noalloc: sync_step with the library's fixed scratch instead of a
@@ -413,18 +435,25 @@ def init_spectral(A: StoredMatrix, n: int, d: int, X0: torch.Tensor, ws: Workspa
     return out
 
 
+METHODS = {"ns_rgs": 0, "polar": 1, "gpm": 2}
+STOP_RULES = {"rel_change": 0, "objective": 1}
+
+
 def solve(A: StoredMatrix, n: int, d: int, X: torch.Tensor, ws: Workspace, mu: float = 0.0,
           ns_steps: int = 3, max_iters: int = 100, tol: float = 0.0, init: bool = True,
           init_iters: int = 60, init_tol: float = 0.0, refine_iters: int = 0,
           A_refine: StoredMatrix | None = None, check_every: int = 16, check: bool = True,
-          symmetric: bool = False) -> dict:
+          symmetric: bool = False, method: str = "ns_rgs", stop: str = "rel_change") -> dict:
     """Algorithm 2 end to end (sync_solve).  X receives the result (and holds X0 if init=False).
-    symmetric=True runs every iteration as step_symmetric (ws from workspace(..., symmetric=True))."""
+    symmetric=True runs every iteration as step_symmetric (ws from workspace(..., symmetric=True)).
+    method: "ns_rgs", "polar" (exact retraction) or "gpm"; stop: "rel_change" or "objective"
+    (the paper's R^t rule), used when tol > 0."""
     _check_x(X, n * d, d, A.fmt, "X")
     m = A.c()
     mref = A_refine.c() if A_refine is not None else None
     opts = _SolveOpts(int(init), int(init_iters), float(init_tol), int(refine_iters),
-                      ctypes.pointer(mref) if mref is not None else None, int(check_every), int(symmetric))
+                      ctypes.pointer(mref) if mref is not None else None, int(check_every), int(symmetric),
+                      METHODS[method], STOP_RULES[stop])
     info = Info()
     st = lib().sync_solve(ctypes.byref(m), n, d, float(mu), int(ns_steps), int(max_iters), float(tol),
                           X.data_ptr(), ws.ptr, ws.nbytes, _stream(), ctypes.byref(opts), ctypes.byref(info))

@@ -288,7 +288,7 @@ BatchLayout batch_layout(const nsrgs_problem *probs, int count, int with_init) {
     off += align256(nd * probs[k].d * xb);
     L.stats_off[k] = off;
     off += align256((size_t)batch_panels(probs[k].n, probs[k].d) * sizeof(PanelStat));
-    if (with_init) init_need = std::max(init_need, sync_workspace_bytes(probs[k].n, probs[k].d, probs[k].A.fmt));
+    if (with_init) init_need = std::max(init_need, narrow_ws_bytes(probs[k].n, probs[k].d, probs[k].A.fmt));
   }
   L.init = off;
   off += align256(init_need);

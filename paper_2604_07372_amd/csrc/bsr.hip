@@ -296,7 +296,7 @@ int sync_step_bsr(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_ste
   const uintptr_t xi = (uintptr_t)X_in, xo = (uintptr_t)X_out;
   if (xi < xo + xb && xo < xi + xb) return fail(NSRGS_ERR_INVALID_ARG, "X_in and X_out overlap");
   if (!ws || ((uintptr_t)ws & 255u)) return fail(NSRGS_ERR_INVALID_ARG, "workspace must be non-NULL and 256-byte aligned");
-  const size_t need = step_ws_bytes(n, d, NSRGS_A_F32);
+  const size_t need = narrow_ws_bytes(n, d, NSRGS_A_F32);
   if (ws_bytes < need) return fail(NSRGS_ERR_OUT_OF_MEMORY, "workspace too small: %zu < %zu bytes", ws_bytes, need);
   StreamArgs sa{};
   sa.X_in = X_in;

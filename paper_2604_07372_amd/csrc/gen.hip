@@ -4,6 +4,7 @@
 // FP32 A into the reduced storage formats of the precision forms.
 #include "device.h"
 #include "kernels.h"
+#include "wide.h"
 
 namespace nsrgs {
 
@@ -15,7 +16,7 @@ generate_kernel(const double *__restrict__ Z, int n, int d, double sigma, uint32
                 uint32_t k1, int zero_diag, double p, T *__restrict__ A, int64_t ld, int row0) {
   const int nd = n * d;
   const int r = row0 + (int)blockIdx.x;     // global row; A points at row row0
-  double zr[kMaxD];
+  double zr[kWideMaxD];
   for (int k = 0; k < d; ++k) zr[k] = Z[(int64_t)r * d + k];
   const int br = r / d;
   T *out = A + (int64_t)blockIdx.x * ld;

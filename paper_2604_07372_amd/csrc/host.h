@@ -66,6 +66,8 @@ int check_step_args(const nsrgs_matrix *A, int n, int d, int ns_steps, const voi
 // sync_step with its argument checks, the control block at `ctl` and room
 // for stats_bytes of panel monitors at `stats` (runtime.hip).
 struct DevCtl;
+int check_step_inputs(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
+                      const void *X_out);
 int step_checked_into(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
                       void *X_out, DevCtl *ctl, void *stats, size_t stats_bytes, hipStream_t s);
 
@@ -73,6 +75,8 @@ int step_checked_into(const nsrgs_matrix *A, int n, int d, double mu, int ns_ste
 // iterate and initialization buffers) and the offset of its panel monitors
 // (runtime.hip).
 size_t step_ws_bytes(int n, int d, int fmt);
+// The part of it the streaming-kernel calls use (d <= 16, NS-RGS).
+size_t narrow_ws_bytes(int n, int d, int fmt);
 size_t step_ws_stats_offset(int n, int d, int fmt);
 
 // Symmetric half-stream step (symmetric.hip): its own argument checks and

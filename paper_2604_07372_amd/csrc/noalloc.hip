@@ -53,6 +53,7 @@ int sync_step_noalloc(const nsrgs_matrix *A, int n, int d, double mu, int ns_ste
                       void *X_out, void *stream) {
   char *base = nullptr;
   int st;
+  if ((st = check_step_inputs(A, n, d, mu, ns_steps, X_in, X_out))) return st;
   if ((st = scratch_on_current_device(&base))) return st;
   // Nothing in the scratch has to start at zero: every panel writes its
   // monitors before the same call's reduction reads them, and the reduction

@@ -16,6 +16,7 @@
 #include "host.h"
 #include "kernels.h"
 #include "nsrgs.h"
+#include "wide.h"
 
 namespace nsrgs {
 
@@ -52,9 +53,13 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // ---- workspace layout ------------------------------------------------------
 struct WsLayout {
-  size_t ctl, stats, xalt, y0, y1, w, parts, total;
+  size_t ctl, stats, xalt, y0, y1, w, parts, wide, total;
 };
 
+// The workspace of one problem.  It ends with the matrix-core path's region
+// (partial products, per-block records, objective pieces), sized by the
+// iterate precision only, so one workspace serves every retraction, every
+// d <= 32, and every storage format with the same iterate precision.
 static WsLayout layout(int n, int d, int fmt) {
   const size_t nd = (size_t)n * d;
   const size_t xb = xbytes(fmt);
@@ -69,6 +74,8 @@ static WsLayout layout(int n, int d, int fmt) {
   const size_t gram = (size_t)n * 2 * d * d * xb;                 // <= n panels
   const size_t apply = ((nd + 255) / 256) * 2 * sizeof(double);
   L.parts = off; off += align256(std::max(gram, apply));
+  L.wide = off;
+  off += align256(wide_layout(n, d, fmt).total);
   L.total = off;
   return L;
 }
@@ -78,6 +85,20 @@ int check_common(int n, int d) {
   if (d < 1 || d > kMaxD) return fail(NSRGS_ERR_INVALID_ARG, "d must be in [1, %d] (got %d)", kMaxD, d);
   if ((int64_t)n * d >= (int64_t)1 << 31) return fail(NSRGS_ERR_INVALID_ARG, "n*d too large");
   return NSRGS_OK;
+}
+
+// The single-problem calls also take 16 < d <= 32 (matrix-core path, F64 and
+// F32 storage).
+static int check_common_wide(int n, int d, int fmt) {
+  if (d > kMaxD && d <= kWideMaxD) {
+    if (n < 2) return fail(NSRGS_ERR_INVALID_ARG, "n must be >= 2 (got %d)", n);
+    if ((int64_t)n * d >= (int64_t)1 << 31) return fail(NSRGS_ERR_INVALID_ARG, "n*d too large");
+    if (!wide_supported_fmt(fmt))
+      return fail(NSRGS_ERR_UNSUPPORTED, "d = %d (> %d) needs F64 or F32 storage", d, kMaxD);
+    return NSRGS_OK;
+  }
+  if (d > kWideMaxD || d < 1) return fail(NSRGS_ERR_INVALID_ARG, "d must be in [1, %d] (got %d)", kWideMaxD, d);
+  return check_common(n, d);
 }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
@@ -99,10 +120,14 @@ int check_matrix(const nsrgs_matrix *A, int n, int d) {
   return NSRGS_OK;
 }
 
-static int check_ws(const void *ws, size_t ws_bytes, int n, int d, int fmt) {
+// A workspace of sync_workspace_bytes() serves every call; the calls that
+// stay on the streaming kernels (d <= 16, NS-RGS, relative-change stop) only
+// touch the part before the matrix-core region and accept that much.
+static int check_ws(const void *ws, size_t ws_bytes, int n, int d, int fmt, bool wide = false) {
   if (!ws) return fail(NSRGS_ERR_INVALID_ARG, "workspace is NULL");
   if (((uintptr_t)ws & 255u) != 0) return fail(NSRGS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-  const size_t need = layout(n, d, fmt).total;
+  const WsLayout L = layout(n, d, fmt);
+  const size_t need = wide ? L.total : L.wide;
   if (ws_bytes < need)
     return fail(NSRGS_ERR_OUT_OF_MEMORY, "workspace too small: %zu < %zu bytes", ws_bytes, need);
   return NSRGS_OK;
@@ -227,7 +252,8 @@ const char *nsrgs_last_error(void) { return g_last_error.c_str(); }
 int nsrgs_version(void) { return NSRGS_VERSION; }
 
 size_t sync_workspace_bytes(int n, int d, int fmt) {
-  if (n < 2 || d < 1 || d > kMaxD || !valid_fmt(fmt)) return 0;
+  if (n < 2 || d < 1 || d > kWideMaxD || !valid_fmt(fmt)) return 0;
+  if (d > kMaxD && !wide_supported_fmt(fmt)) return 0;
   return layout(n, d, fmt).total;
 }
 
@@ -266,11 +292,16 @@ static int step_impl(const nsrgs_matrix *A, int n, int d, double mu, int ns_step
                    static_cast<char *>(ws) + L.stats, s, iter, tol, check_done, force);
 }
 
-// sync_step's checks of everything but the workspace.
+// sync_step's checks of everything but the workspace (wide: 16 < d <= 32
+// allowed for F64 / F32 storage).
 static int check_step_io(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps,
-                         const void *X_in, const void *X_out) {
+                         const void *X_in, const void *X_out, bool wide = false) {
   int st;
-  if ((st = check_common(n, d))) return st;
+  if (wide && A && valid_fmt(A->fmt)) {
+    if ((st = check_common_wide(n, d, A->fmt))) return st;
+  } else if ((st = check_common(n, d))) {
+    return st;
+  }
   if ((st = check_matrix(A, n, d))) return st;
   if (!X_in || !X_out) return fail(NSRGS_ERR_INVALID_ARG, "X_in / X_out is NULL");
   if (!aligned16(X_in) || !aligned16(X_out)) return fail(NSRGS_ERR_INVALID_ARG, "X buffers must be 16-byte aligned");
@@ -281,17 +312,93 @@ static int check_step_io(const nsrgs_matrix *A, int n, int d, double mu, int ns_
   return NSRGS_OK;
 }
 
+// ---- matrix-core path (wide.h): d up to 32 and the three retractions ------
+static WideArgs wide_args(const nsrgs_matrix *A, int n, int d, void *ws) {
+  const WsLayout L = layout(n, d, A->fmt);
+  const WideLayout W = wide_layout(n, d, A->fmt);
+  char *base = static_cast<char *>(ws) + L.wide;
+  WideArgs a{};
+  a.A = A->data;
+  a.ld = A->ld;
+  a.n = n;
+  a.d = d;
+  a.nd = n * d;
+  a.part = base + W.part;
+  a.stats = reinterpret_cast<WideStat *>(base + W.stats);
+  a.igram = reinterpret_cast<double *>(base + W.igram);
+  a.gram = reinterpret_cast<double *>(base + W.gram);
+  a.sumsq = nullptr;
+  a.ctl = static_cast<DevCtl *>(ws);
+  a.wctl = reinterpret_cast<WideCtl *>(base + W.ctl);
+  a.g = wide_geom(n, d, A->fmt);
+  return a;
+}
+
+static WideCtl *wide_ctl(void *ws, int n, int d, int fmt) {
+  return reinterpret_cast<WideCtl *>(static_cast<char *>(ws) + layout(n, d, fmt).wide + wide_layout(n, d, fmt).ctl);
+}
+
+// One iteration on the matrix-core path.  objective: evaluate F(X^t) (the
+// constant part of F is computed from A on the solve's first iteration).
+static int wide_step_impl(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, int method,
+                          const void *X_in, void *X_out, void *ws, hipStream_t s, int iter, double tol,
+                          int stop_rule, bool objective, bool check_done) {
+  WideArgs a = wide_args(A, n, d, ws);
+  a.X_in = X_in;
+  a.X_out = X_out;
+  a.mu = mu > 0.0 ? mu : 1.0 / n;
+  a.ns_steps = ns_steps;
+  a.method = method;
+  a.mode = WIDE_STEP;
+  a.iter = iter;
+  a.tol = tol;
+  a.stop_rule = stop_rule;
+  a.objective = objective ? 1 : 0;
+  if (objective && iter == 0) {
+    const WsLayout L = layout(n, d, A->fmt);
+    a.sumsq = reinterpret_cast<double *>(static_cast<char *>(ws) + L.wide + wide_layout(n, d, A->fmt).sumsq);
+  }
+  a.stop_flag = check_done ? &a.ctl->done : nullptr;
+  NSRGS_HIP(launch_wide_step(A->fmt, a, s), "matrix-core step launch");
+  return NSRGS_OK;
+}
+
+static int step_method_entry(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, int method,
+                             const void *X_in, void *X_out, void *ws, size_t ws_bytes, void *stream) {
+  int st;
+  if ((st = check_step_io(A, n, d, mu, ns_steps, X_in, X_out, true))) return st;
+  if ((st = check_ws(ws, ws_bytes, n, d, A->fmt, method != WIDE_NS || d > kMaxD))) return st;
+  if (method == WIDE_NS && d <= kMaxD)
+    return step_impl(A, n, d, mu, ns_steps, X_in, X_out, ws, (hipStream_t)stream, 0, 0.0, false);
+  if (!wide_supported_fmt(A->fmt))
+    return fail(NSRGS_ERR_UNSUPPORTED, "this retraction / block size needs F64 or F32 storage");
+  return wide_step_impl(A, n, d, mu, ns_steps, method, X_in, X_out, ws, (hipStream_t)stream, 0, 0.0, 0,
+                        false, false);
+}
+
 int sync_step(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
               void *X_out, void *ws, size_t ws_bytes, void *stream) {
-  int st;
-  if ((st = check_step_io(A, n, d, mu, ns_steps, X_in, X_out))) return st;
-  if ((st = check_ws(ws, ws_bytes, n, d, A->fmt))) return st;
-  return step_impl(A, n, d, mu, ns_steps, X_in, X_out, ws, (hipStream_t)stream, 0, 0.0, false);
+  return step_method_entry(A, n, d, mu, ns_steps, WIDE_NS, X_in, X_out, ws, ws_bytes, stream);
+}
+
+int sync_step_polar(const nsrgs_matrix *A, int n, int d, double mu, const void *X_in, void *X_out,
+                    void *ws, size_t ws_bytes, void *stream) {
+  return step_method_entry(A, n, d, mu, 0, WIDE_POLAR, X_in, X_out, ws, ws_bytes, stream);
+}
+
+int sync_step_gpm(const nsrgs_matrix *A, int n, int d, const void *X_in, void *X_out, void *ws,
+                  size_t ws_bytes, void *stream) {
+  return step_method_entry(A, n, d, 0.0, 0, WIDE_GPM, X_in, X_out, ws, ws_bytes, stream);
 }
 
 }  // extern "C"
 
 namespace nsrgs {
+int check_step_inputs(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
+                      const void *X_out) {
+  return check_step_io(A, n, d, mu, ns_steps, X_in, X_out);
+}
+
 // sync_step with caller-placed control block and panel monitors: the
 // no-allocation entry point's path.  The arguments are checked here.
 int step_checked_into(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
@@ -309,6 +416,7 @@ int step_checked_into(const nsrgs_matrix *A, int n, int d, double mu, int ns_ste
 }
 
 size_t step_ws_bytes(int n, int d, int fmt) { return layout(n, d, fmt).total; }
+size_t narrow_ws_bytes(int n, int d, int fmt) { return layout(n, d, fmt).wide; }
 size_t step_ws_stats_offset(int n, int d, int fmt) { return layout(n, d, fmt).stats; }
 
 // sync_step with a given launch shape (the autotuner's timing loop); the
@@ -338,6 +446,8 @@ extern "C" {
 static void fill_info(const DevCtl &c, int d, nsrgs_info *info, int status) {
   if (!info) return;
   memset(info, 0, sizeof(*info));
+  info->objective = NAN;
+  info->objective_ratio = NAN;
   info->iters = c.iters;
   info->nonfinite = c.nonfinite;
   info->converged = c.converged;
@@ -355,17 +465,79 @@ static int read_ctl(const void *ws, DevCtl *host, hipStream_t s) {
   return NSRGS_OK;
 }
 
+// The objective and Ritz values the matrix-core path keeps in its own control block.
+static int read_wide_info(const void *ws, int n, int d, int fmt, nsrgs_info *info, hipStream_t s) {
+  if (!info || !wide_supported_fmt(fmt)) return NSRGS_OK;
+  WideCtl w;
+  NSRGS_HIP(hipMemcpyAsync(&w, wide_ctl(const_cast<void *>(ws), n, d, fmt), sizeof(WideCtl),
+                           hipMemcpyDeviceToHost, s), "wide ctl readback");
+  NSRGS_HIP(hipStreamSynchronize(s), "stream sync");
+  info->objective = w.obj;
+  info->objective_ratio = w.obj_ratio;
+  if (d > kMaxD)
+    for (int i = kMaxD; i < d; ++i) info->ritz_more[i - kMaxD] = w.ritz[i];
+  return NSRGS_OK;
+}
+
 int sync_read_info(const void *ws, size_t ws_bytes, int n, int d, int fmt, nsrgs_info *info,
                    void *stream) {
   int st;
-  if ((st = check_common(n, d))) return st;
   if (!valid_fmt(fmt)) return fail(NSRGS_ERR_INVALID_ARG, "unknown format");
+  if ((st = check_common_wide(n, d, fmt))) return st;
   if ((st = check_ws(ws, ws_bytes, n, d, fmt))) return st;
   if (!info) return fail(NSRGS_ERR_INVALID_ARG, "info is NULL");
   DevCtl c;
   if ((st = read_ctl(ws, &c, (hipStream_t)stream))) return st;
   fill_info(c, d, info, NSRGS_OK);
   info->iters = c.iters ? c.iters : c.init_iters;
+  if (ws_bytes < layout(n, d, fmt).total) return NSRGS_OK;   // no matrix-core region
+  return read_wide_info(ws, n, d, fmt, info, (hipStream_t)stream);
+}
+
+// Spectral initialization for 16 < d <= 32 on the matrix-core product (the
+// same subspace iteration, Cholesky-QR and polar as init_impl).
+static int wide_init_impl(const nsrgs_matrix *A, int n, int d, void *X0, int max_iters, double tol,
+                          void *ws, hipStream_t s, DevCtl *out_ctl) {
+  const int nd = n * d;
+  const WsLayout L = layout(n, d, A->fmt);
+  char *base = static_cast<char *>(ws);
+  DevCtl *ctl = static_cast<DevCtl *>(ws);
+  void *Y[2] = {base + L.y0, base + L.y1};
+  void *W = base + L.w;
+  if (max_iters <= 0) max_iters = 60;
+  if (!(tol > 0.0)) tol = A->fmt == NSRGS_A_F64 ? 1e-13 : 1e-5;
+  NSRGS_HIP(launch_ctl_reset(ctl, 2, s), "ctl reset");
+  NSRGS_HIP(launch_init_random(A->fmt, Y[0], nd, d, 0x5eed5eedULL, s), "init random");
+  WideArgs a = wide_args(A, n, d, ws);
+  a.mode = WIDE_INIT;
+  a.X_out = W;
+  a.stop_flag = &ctl->init_done;
+  const int groups = (nd + 255) / 256;
+  double *apply_part = reinterpret_cast<double *>(base + L.stats);   // 2 doubles per 256 rows
+  DevCtl host{};
+  int k = 0;
+  const int chunk = 4;
+  while (k < max_iters) {
+    const int kend = std::min(max_iters, k + chunk);
+    for (; k < kend; ++k) {
+      a.X_in = Y[k & 1];
+      a.iter = k;
+      NSRGS_HIP(launch_wide_init_product(A->fmt, a, s), "init product");
+      NSRGS_HIP(launch_wide_init_apply(A->fmt, W, Y[k & 1], Y[(k + 1) & 1], nd, d, apply_part, groups, ctl,
+                                       a.wctl, k, tol, s), "init apply");
+    }
+    int st;
+    if ((st = read_ctl(ws, &host, s))) return st;
+    if (host.init_done) break;
+  }
+  const int done_iters = host.init_iters;
+  NSRGS_HIP(launch_wide_init_polar(A->fmt, Y[done_iters & 1], X0, n, d, ctl, s), "init polar");
+  NSRGS_HIP(launch_wide_init_finish(ctl, a.wctl, d, s), "init finish");
+  int st;
+  if ((st = read_ctl(ws, &host, s))) return st;
+  if (out_ctl) *out_ctl = host;
+  if (host.init_bad) return fail(NSRGS_ERR_NONFINITE, "spectral init broke down (Cholesky/polar)");
+  if (!host.init_done) return NSRGS_ERR_NOT_CONVERGED;
   return NSRGS_OK;
 }
 
@@ -434,16 +606,22 @@ static int init_impl(const nsrgs_matrix *A, int n, int d, void *X0, int max_iter
 int sync_init_spectral(const nsrgs_matrix *A, int n, int d, void *X0, int max_iters, double tol,
                        void *ws, size_t ws_bytes, void *stream, nsrgs_info *info) {
   int st;
-  if ((st = check_common(n, d))) return st;
+  if (!A) return fail(NSRGS_ERR_INVALID_ARG, "A is NULL");
+  if ((st = check_common_wide(n, d, A->fmt))) return st;
   if ((st = check_matrix(A, n, d))) return st;
-  if ((st = check_ws(ws, ws_bytes, n, d, A->fmt))) return st;
+  if ((st = check_ws(ws, ws_bytes, n, d, A->fmt, d > kMaxD))) return st;
   if (!X0 || !aligned16(X0)) return fail(NSRGS_ERR_INVALID_ARG, "X0 must be non-NULL and 16-byte aligned");
   DevCtl c{};
-  st = init_impl(A, n, d, X0, max_iters, tol, ws, (hipStream_t)stream, &c);
+  st = d > kMaxD ? wide_init_impl(A, n, d, X0, max_iters, tol, ws, (hipStream_t)stream, &c)
+                 : init_impl(A, n, d, X0, max_iters, tol, ws, (hipStream_t)stream, &c);
   if (info) {
     fill_info(c, d, info, st);
     info->iters = c.init_iters;
     info->converged = c.init_done && !c.init_bad;
+    if (d > kMaxD) {
+      const int st2 = read_wide_info(ws, n, d, A->fmt, info, (hipStream_t)stream);
+      if (st2) return st2;
+    }
   }
   return st;
 }
@@ -452,23 +630,44 @@ int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, int
                double tol, void *X, void *ws, size_t ws_bytes, void *stream,
                const nsrgs_solve_opts *opts, nsrgs_info *info) {
   int st;
-  if ((st = check_common(n, d))) return st;
+  if (!A) return fail(NSRGS_ERR_INVALID_ARG, "A is NULL");
+  if ((st = check_common_wide(n, d, A->fmt))) return st;
   if ((st = check_matrix(A, n, d))) return st;
-  if ((st = check_ws(ws, ws_bytes, n, d, A->fmt))) return st;
   if (!X || !aligned16(X)) return fail(NSRGS_ERR_INVALID_ARG, "X must be non-NULL and 16-byte aligned");
   if (ns_steps < 0 || ns_steps > 64) return fail(NSRGS_ERR_INVALID_ARG, "ns_steps must be in [0, 64]");
   if (max_iters < 0) return fail(NSRGS_ERR_INVALID_ARG, "max_iters must be >= 0");
   if (!std::isfinite(mu)) return fail(NSRGS_ERR_INVALID_ARG, "mu must be finite");
-  nsrgs_solve_opts o{1, 60, 0.0, 0, nullptr, 16, 0};
+  nsrgs_solve_opts o{1, 60, 0.0, 0, nullptr, 16, 0, NSRGS_METHOD_NS_RGS, NSRGS_STOP_REL_CHANGE};
   if (opts) o = *opts;
   if (o.check_every <= 0) o.check_every = 16;
   if (o.symmetric != 0 && o.symmetric != 1) return fail(NSRGS_ERR_INVALID_ARG, "symmetric must be 0 or 1");
+  if (o.method < NSRGS_METHOD_NS_RGS || o.method > NSRGS_METHOD_GPM)
+    return fail(NSRGS_ERR_INVALID_ARG, "unknown method %d", (int)o.method);
+  if (o.stop_rule != NSRGS_STOP_REL_CHANGE && o.stop_rule != NSRGS_STOP_OBJECTIVE)
+    return fail(NSRGS_ERR_INVALID_ARG, "unknown stop rule %d", (int)o.stop_rule);
+  // The matrix-core path runs d > 16, the exact-polar and GPM retractions and
+  // the objective stop rule.
+  const bool wide = d > kMaxD || o.method != NSRGS_METHOD_NS_RGS || o.stop_rule == NSRGS_STOP_OBJECTIVE;
+  if (wide) {
+    if (!wide_supported_fmt(A->fmt))
+      return fail(NSRGS_ERR_UNSUPPORTED, "d > 16, exact polar, GPM and the objective stop need F64 or F32 storage");
+    if (o.symmetric) return fail(NSRGS_ERR_UNSUPPORTED, "the symmetric half-stream runs NS-RGS with d <= 16 only");
+    if (o.refine_iters > 0 && o.A_refine && !wide_supported_fmt(o.A_refine->fmt))
+      return fail(NSRGS_ERR_UNSUPPORTED, "A_refine must be F64 or F32 on this path");
+    if (o.refine_iters > 0 && o.stop_rule == NSRGS_STOP_OBJECTIVE)
+      return fail(NSRGS_ERR_UNSUPPORTED, "the objective stop rule does not combine with refinement");
+  }
+  if ((st = check_ws(ws, ws_bytes, n, d, A->fmt, wide))) return st;
   if (o.symmetric) {
     if ((st = sym_check(A, n, d, ws_bytes))) return st;
     if (o.refine_iters > 0 && o.A_refine && (st = sym_check(o.A_refine, n, d, ws_bytes))) return st;
   }
+  const bool objective = o.stop_rule == NSRGS_STOP_OBJECTIVE;
   // one iteration on matrix M, with the solve's iteration index and stop rule
   auto iterate = [&](const nsrgs_matrix *M, const void *xi, void *xo, int t, double tl) {
+    if (wide)
+      return wide_step_impl(M, n, d, mu, ns_steps, o.method, xi, xo, ws, (hipStream_t)stream, t, tl,
+                            o.stop_rule, objective, true);
     return o.symmetric ? sym_step_launch(M, n, d, mu, ns_steps, xi, xo, ws, (hipStream_t)stream, t, tl, true)
                        : step_impl(M, n, d, mu, ns_steps, xi, xo, ws, (hipStream_t)stream, t, tl, true);
   };
@@ -477,7 +676,7 @@ int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, int
     if ((st = check_matrix(o.A_refine, n, d))) return st;
     if (xbytes(o.A_refine->fmt) != xbytes(A->fmt))
       return fail(NSRGS_ERR_INVALID_ARG, "A_refine must use the same iterate precision as A");
-    if ((st = check_ws(ws, ws_bytes, n, d, o.A_refine->fmt))) return st;
+    if ((st = check_ws(ws, ws_bytes, n, d, o.A_refine->fmt, wide))) return st;
     refine = std::min(o.refine_iters, max_iters);
   } else if (o.refine_iters > 0) {
     return fail(NSRGS_ERR_INVALID_ARG, "refine_iters > 0 needs A_refine");
@@ -488,13 +687,15 @@ int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, int
   DevCtl host{};
   int init_status = NSRGS_OK;
   if (o.init) {
-    init_status = init_impl(A, n, d, X, o.init_iters, o.init_tol, ws, s, &host);
+    init_status = d > kMaxD ? wide_init_impl(A, n, d, X, o.init_iters, o.init_tol, ws, s, &host)
+                            : init_impl(A, n, d, X, o.init_iters, o.init_tol, ws, s, &host);
     if (init_status != NSRGS_OK && init_status != NSRGS_ERR_NOT_CONVERGED) {
       if (info) fill_info(host, d, info, init_status);
       return init_status;
     }
   }
   NSRGS_HIP(launch_ctl_reset(static_cast<DevCtl *>(ws), 1, s), "ctl reset");
+  if (wide) NSRGS_HIP(launch_wide_ctl_reset(wide_ctl(ws, n, d, A->fmt), s), "wide ctl reset");
   // Phase 1 on A (early stop allowed), phase 2 on A_refine (fixed count).
   const int phase1 = max_iters - refine;
   int t = 0;
@@ -530,6 +731,7 @@ int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, int
     fill_info(host, d, info, result);
     info->iters = done_iters;
     info->init_residual = host.init_res;
+    if (wide && (st = read_wide_info(ws, n, d, A->fmt, info, s))) return st;
   }
   (void)init_status;
   return result;
@@ -567,9 +769,9 @@ int nsrgs_generate_measurement(const double *Z, int n, int d, double sigma, uint
                                int zero_diag_blocks, double p, int fmt, void *A, int64_t ld,
                                void *stream) {
   int st;
-  if ((st = check_common(n, d))) return st;
   if (fmt != NSRGS_A_F64 && fmt != NSRGS_A_F32)
     return fail(NSRGS_ERR_INVALID_ARG, "generator writes F64 or F32 only");
+  if ((st = check_common_wide(n, d, fmt))) return st;
   if (!Z || !A) return fail(NSRGS_ERR_INVALID_ARG, "Z / A is NULL");
   if (ld < (int64_t)n * d) return fail(NSRGS_ERR_INVALID_ARG, "ld < n*d");
   if (!std::isfinite(sigma) || !(p > 0.0) || p > 1.0) return fail(NSRGS_ERR_INVALID_ARG, "bad sigma or p");

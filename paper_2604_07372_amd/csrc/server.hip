@@ -181,7 +181,7 @@ static void plan_memory(const Server &S, Request &q) {
   q.z_bytes = (size_t)nd * q.r.d * sizeof(double);
   q.stage_rows = S.o.fmt == NSRGS_A_F32 ? 0 : (int)std::max<int64_t>(1, std::min<int64_t>(nd, kStageBytes / (ld * 4)));
   q.stage_bytes = (size_t)q.stage_rows * ld * 4;
-  q.iws_bytes = sync_workspace_bytes(q.r.n, q.r.d, NSRGS_A_F32);
+  q.iws_bytes = narrow_ws_bytes(q.r.n, q.r.d, NSRGS_A_F32);
   q.A.fmt = S.o.fmt;
   q.A.ld = ld;
 }

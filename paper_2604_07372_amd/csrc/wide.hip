@@ -1,0 +1,836 @@
+// Kernels of the matrix-core path (block sizes up to d = 32; NS-RGS, exact
+// polar and GPM retractions; the objective of eq. def:f).  See wide.h.
+#include "device.h"
+#include "kernels.h"
+#include "wide.h"
+
+namespace nsrgs {
+
+template <typename T> struct WideT;
+template <> struct WideT<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static constexpr int V = 2;     // elements per 16-byte load
+};
+template <> struct WideT<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static constexpr int V = 4;
+};
+
+// D = A B + C on one 16 x 16 x 4 matrix-core tile.  Lane l supplies A(l % 16,
+// l / 16) and B(l / 16, l % 16); it holds D(4 (l / 16) + r, l % 16), r < 4,
+// for FP32 and D(l / 16 + 4 r, l % 16) for FP64 (both measured on gfx950).
+template <typename T>
+__device__ __forceinline__ typename WideT<T>::v4 mfma4(T a, T b, typename WideT<T>::v4 c) {
+  if constexpr (sizeof(T) == 8) return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  else return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+constexpr int kWU = 4;   // 16-byte column vectors per lane per tile row per step
+
+template <typename T>
+constexpr int wide_kstep() { return 4 * kWU * WideT<T>::V; }   // 32 (F64) or 64 (F32) columns
+
+// ---------------------------------------------------------------------------
+// Product kernel: partial[ks][r][c] = sum over the columns k of chunk ks of
+// A[r][k] X[k][c], for the 128 rows of this workgroup and c < 16 NT.
+//
+// A step covers KSTEP columns.  Lane (m = l % 16, q = l / 16) of a wave loads
+// kWU 16-byte vectors of each of its two tile rows, at columns
+// kb + (u 4 + q) V .. + V (u < kWU): the four lanes of a row read 64 bytes
+// contiguously per load, a wave 16 rows x 64 bytes.  Element v of vector u is
+// the lane's A operand of the tile product (u, v); column kb + (u 4 + q) V + v
+// is its k index, so the X tile in LDS is stored in the same order and every
+// B operand read is 64 consecutive values (no bank conflicts).  The X tile is
+// loaded once per workgroup per step (shared by the four waves) into one of
+// two LDS buffers while the other is in use; the next step's A vectors are in
+// flight during the current step's products.
+// ---------------------------------------------------------------------------
+template <typename T, int NT>
+__global__ void __launch_bounds__(256) wide_product_kernel(WideArgs a) {
+  using v4 = typename WideT<T>::v4;
+  constexpr int V = WideT<T>::V;
+  constexpr int KSTEP = wide_kstep<T>();
+  constexpr int XW = 16 * NT;               // X tile width
+  constexpr int XT = KSTEP * XW;            // X tile elements
+  constexpr int XPT = XT / 256;             // per thread
+  __shared__ __attribute__((aligned(16))) T xs[2][XT];
+  __shared__ double s_scr[kMaxWaves];
+  if (a.stop_flag) {
+    if (__atomic_load_n(a.stop_flag, __ATOMIC_RELAXED)) return;   // uniform
+  }
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int m = lane & 15, q = lane >> 4;
+  const int nd = a.nd, d = a.d;
+  const int rt = blockIdx.x, ks = blockIdx.y;
+  const int kbeg = ks * a.g.kchunk;
+  const int kend = min(nd, kbeg + a.g.kchunk);
+  const int nsteps = kend > kbeg ? (kend - kbeg + KSTEP - 1) / KSTEP : 0;
+  const char *__restrict__ Ab = static_cast<const char *>(a.A);
+  const T *__restrict__ X = static_cast<const T *>(a.X_in);
+  const bool want_ssq = a.sumsq != nullptr;
+
+  int64_t roff[2];
+  bool rowok[2];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    const int row = rt * kWideRows + wave * 32 + mt * 16 + m;
+    rowok[mt] = row < nd;
+    roff[mt] = (int64_t)(row < nd ? row : nd - 1) * a.ld * (int64_t)sizeof(T);
+  }
+
+  v4 acc[2][NT];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = v4{0, 0, 0, 0};
+  double ssq = 0.0;
+
+  // X tile element e: row kr = e / XW of the step, column c = e % XW; its LDS
+  // slot follows the lane order of the B operand (see above).
+  auto xload = [&](int kb, T (&xr)[XPT]) {
+#pragma unroll
+    for (int j = 0; j < XPT; ++j) {
+      const int e = tid + 256 * j;
+      const int k = kb + e / XW, c = e % XW;
+      const int kk = k < nd ? k : nd - 1, cc = c < d ? c : d - 1;   // clamped, in bounds
+      const T v = X[(int64_t)kk * d + cc];
+      xr[j] = (k < nd && c < d) ? v : T(0);
+    }
+  };
+  auto xstore = [&](int buf, const T (&xr)[XPT]) {
+#pragma unroll
+    for (int j = 0; j < XPT; ++j) {
+      const int e = tid + 256 * j;
+      const int kr = e / XW, c = e % XW;
+      const int u = kr / (4 * V), qq = (kr / V) & 3, v = kr % V;
+      xs[buf][((u * V + v) * NT + (c >> 4)) * 64 + qq * 16 + (c & 15)] = xr[j];
+    }
+  };
+  auto aload = [&](int kb, uint4 (&ar)[2][kWU]) {
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int u = 0; u < kWU; ++u) {
+        const int kc = kb + (u * 4 + q) * V;
+        const int kcc = kc < nd ? kc : 0;            // a vector starting at or past nd reads column 0
+        ar[mt][u] = ld16_stream(Ab + roff[mt] + (int64_t)kcc * (int64_t)sizeof(T));
+      }
+  };
+  auto compute = [&](int buf, const uint4 (&ar)[2][kWU], int kb) {
+    const bool ragged = kb + KSTEP > nd;             // uniform: only the matrix's last step
+#pragma unroll
+    for (int u = 0; u < kWU; ++u) {
+      T av[2][V];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        if constexpr (sizeof(T) == 8) {
+          av[mt][0] = __hiloint2double((int)ar[mt][u].y, (int)ar[mt][u].x);
+          av[mt][1] = __hiloint2double((int)ar[mt][u].w, (int)ar[mt][u].z);
+        } else {
+          av[mt][0] = __uint_as_float(ar[mt][u].x);
+          av[mt][1] = __uint_as_float(ar[mt][u].y);
+          av[mt][2] = __uint_as_float(ar[mt][u].z);
+          av[mt][3] = __uint_as_float(ar[mt][u].w);
+        }
+      }
+      if (ragged) {
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+          for (int v = 0; v < V; ++v) av[mt][v] = (kb + (u * 4 + q) * V + v < nd) ? av[mt][v] : T(0);
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const T b = xs[buf][((u * V + v) * NT + nt) * 64 + lane];
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt) acc[mt][nt] = mfma4<T>(av[mt][v], b, acc[mt][nt]);
+        }
+      }
+      if (want_ssq) {
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            const double x = rowok[mt] ? (double)av[mt][v] : 0.0;
+            ssq += x * x;
+          }
+      }
+    }
+  };
+
+  uint4 ar0[2][kWU], ar1[2][kWU];
+  T xr[XPT];
+  if (nsteps > 0) {
+    xload(kbeg, xr);
+    xstore(0, xr);
+    aload(kbeg, ar0);
+  }
+  __syncthreads();
+  // Unrolled by two so the two A register sets take turns without copies.
+  for (int s = 0; s < nsteps; s += 2) {
+    const int kb = kbeg + s * KSTEP;
+    const bool more1 = s + 1 < nsteps;
+    if (more1) {
+      aload(kb + KSTEP, ar1);
+      xload(kb + KSTEP, xr);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    compute(0, ar0, kb);
+    if (more1) xstore(1, xr);
+    __syncthreads();
+    if (more1) {
+      const int kb1 = kb + KSTEP;
+      const bool more2 = s + 2 < nsteps;
+      if (more2) {
+        aload(kb1 + KSTEP, ar0);
+        xload(kb1 + KSTEP, xr);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      compute(1, ar1, kb1);
+      if (more2) xstore(0, xr);
+      __syncthreads();
+    }
+  }
+
+  T *__restrict__ P = static_cast<T *>(a.part) + (size_t)ks * a.g.rows_pad * 32;
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rt * kWideRows + wave * 32 + mt * 16 + (sizeof(T) == 8 ? q + 4 * r : 4 * q + r);
+        P[(size_t)row * 32 + nt * 16 + m] = acc[mt][nt][r];
+      }
+  if (want_ssq) {
+    ssq = block_sum(ssq, s_scr);
+    if (tid == 0) a.sumsq[(size_t)ks * gridDim.x + rt] = ssq;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// d x d helpers in FP64 on LDS, for every thread of a workgroup.
+// ---------------------------------------------------------------------------
+// out = op(A) op(B), op = transpose when tA / tB; ends with a barrier.
+__device__ inline void wmm(double *out, const double *A, bool tA, const double *B, bool tB, int d) {
+  const int dd = d * d;
+  for (int e = threadIdx.x; e < dd; e += blockDim.x) {
+    const int r = e / d, k = e % d;
+    double s = 0.0;
+    for (int m = 0; m < d; ++m) s += (tA ? A[m * d + r] : A[r * d + m]) * (tB ? B[k * d + m] : B[m * d + k]);
+    out[e] = s;
+  }
+  __syncthreads();
+}
+
+// ||I - M||_F of a d x d matrix in LDS (a block reduction).
+__device__ inline double wdefect(const double *M, int d, double *scr) {
+  double s = 0.0;
+  for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+    const double v = ((e / d) == (e % d) ? 1.0 : 0.0) - M[e];
+    s += v * v;
+  }
+  return sqrt(block_sum(s, scr));
+}
+
+// The polar factor sgn(S) = U V^T of a nonsingular d x d matrix S = U Sigma V^T
+// (Sec. 2.1), in place, to FP64 accuracy: Newton-Schulz from S scaled by
+// 1 / sqrt(g), g the largest Gershgorin row sum of S^T S (an upper bound of
+// sigma_max^2, so every scaled singular value lies in (0, 1], inside the
+// region (0, sqrt 3) where the iteration converges to sgn), until
+// ||I - S^T S||_F <= 64 d eps, then two more (quadratic) steps.  M, N are LDS
+// scratch.  Returns the number of steps, or -1 if the matrix is singular or
+// not finite (no convergence within 200 steps).
+__device__ inline int wide_polar(double *S, double *M, double *N, int d, double *scr) {
+  const int dd = d * d;
+  wmm(M, S, true, S, false, d);
+  double g = 0.0;
+  for (int r = threadIdx.x; r < d; r += blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) s += fabs(M[r * d + k]);
+    g = s > g ? s : g;
+  }
+  g = block_max(g, scr);
+  if (!(g > 0.0) || !isfinite(g)) return -1;
+  const double sc = 1.0 / sqrt(g);
+  for (int e = threadIdx.x; e < dd; e += blockDim.x) S[e] *= sc;
+  __syncthreads();
+  const double stop = 64.0 * d * 2.220446049250313e-16;
+  int extra = -1;
+  for (int it = 0; it < 200; ++it) {
+    wmm(M, S, true, S, false, d);
+    const double def = wdefect(M, d, scr);
+    if (!isfinite(def)) return -1;
+    if (extra < 0 && def <= stop) extra = 2;
+    if (extra == 0) return it;
+    wmm(N, S, false, M, false, d);
+    for (int e = threadIdx.x; e < dd; e += blockDim.x) S[e] = 1.5 * S[e] - 0.5 * N[e];
+    __syncthreads();
+    if (extra > 0) --extra;
+  }
+  return -1;
+}
+
+// ---------------------------------------------------------------------------
+// Epilogue: one workgroup per block i.  Step mode: C_i from the partials, the
+// diagonal-block term, the retraction, X_i^{t+1} and the block's record.
+// Init mode: W_i = (A Y)_i and the block's Grams Y_i^T W_i, W_i^T W_i.
+// The d x d arithmetic is FP64 for every storage format.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) wide_epilogue_kernel(WideArgs a) {
+  constexpr int NE = kWideMaxD * kWideMaxD;
+  __shared__ double sm[7][NE];
+  __shared__ double s_scr[kMaxWaves];
+  if (a.stop_flag) {
+    if (__atomic_load_n(a.stop_flag, __ATOMIC_RELAXED)) return;   // uniform
+  }
+  const int i = blockIdx.x, d = a.d, dd = d * d, tid = threadIdx.x;
+  double *X = sm[0], *C = sm[1], *Ad = sm[2], *G = sm[3], *Tm = sm[4], *F = sm[5], *M = sm[6];
+  const T *__restrict__ Xin = static_cast<const T *>(a.X_in);
+  const T *__restrict__ P = static_cast<const T *>(a.part);
+  const T *__restrict__ A = static_cast<const T *>(a.A);
+  for (int e = tid; e < dd; e += blockDim.x) {
+    const int r = e / d, k = e % d;
+    const int64_t row = (int64_t)i * d + r;
+    X[e] = (double)Xin[row * d + k];
+    double c = 0.0;
+    for (int s = 0; s < a.g.ks; ++s) c += (double)P[((size_t)s * a.g.rows_pad + row) * 32 + k];
+    C[e] = c;
+    Ad[e] = (double)A[row * a.ld + (int64_t)i * d + k];
+  }
+  __syncthreads();
+
+  if (a.mode == WIDE_INIT) {
+    T *__restrict__ W = static_cast<T *>(a.X_out);
+    for (int e = tid; e < dd; e += blockDim.x) W[((int64_t)i * d + e / d) * d + e % d] = (T)C[e];
+    wmm(G, X, true, C, false, d);       // Y_i^T W_i
+    wmm(Tm, C, true, C, false, d);      // W_i^T W_i
+    double *out = a.igram + (size_t)i * 2 * dd;
+    for (int e = tid; e < dd; e += blockDim.x) {
+      out[e] = G[e];
+      out[dd + e] = Tm[e];
+    }
+    return;
+  }
+
+  wmm(G, Ad, false, X, false, d);       // A_ii X_i
+  wmm(Tm, X, true, X, false, d);        // H_i = X_i^T X_i
+  double xc = 0.0, hh = 0.0, aii2 = 0.0, x2 = 0.0;
+  for (int e = tid; e < dd; e += blockDim.x) {
+    xc += X[e] * (C[e] - G[e]);         // tr(X_i^T C_i), C_i without the diagonal block
+    hh += Tm[e] * Tm[e];
+    aii2 += Ad[e] * Ad[e];
+    x2 += X[e] * X[e];
+  }
+  xc = block_sum(xc, s_scr);
+  hh = block_sum(hh, s_scr);
+  aii2 = block_sum(aii2, s_scr);
+  x2 = block_sum(x2, s_scr);
+
+  double *S = F;         // the iterate being retracted
+  double dmax = 0.0;
+  int polar_steps = 0;
+  if (a.method == WIDE_GPM) {
+    for (int e = tid; e < dd; e += blockDim.x) S[e] = C[e];        // (A X)_i, diagonal block included
+    __syncthreads();
+    polar_steps = wide_polar(S, M, Tm, d, s_scr);
+    wmm(M, S, true, S, false, d);
+    dmax = wdefect(M, d, s_scr);
+  } else {
+    const double nm1 = (double)(a.n - 1), mu = a.mu;
+    for (int e = tid; e < dd; e += blockDim.x) G[e] = nm1 * X[e] - (C[e] - G[e]);   // G_i
+    __syncthreads();
+    wmm(Tm, G, true, X, false, d);       // G_i^T X_i
+    wmm(M, X, false, Tm, false, d);      // X_i G_i^T X_i
+    for (int e = tid; e < dd; e += blockDim.x) F[e] = X[e] - mu * 0.5 * (G[e] - M[e]);
+    __syncthreads();
+    wmm(M, F, true, F, false, d);
+    dmax = wdefect(M, d, s_scr);         // ||I - F_i^T F_i||_F
+    if (a.method == WIDE_POLAR) {
+      polar_steps = wide_polar(S, M, Tm, d, s_scr);
+    } else {
+      double *cur = F, *nxt = G;
+      for (int st = 0; st < a.ns_steps; ++st) {
+        wmm(M, cur, true, cur, false, d);
+        wmm(Tm, cur, false, M, false, d);
+        for (int e = tid; e < dd; e += blockDim.x) nxt[e] = 1.5 * cur[e] - 0.5 * Tm[e];
+        __syncthreads();
+        double *t = cur;
+        cur = nxt;
+        nxt = t;
+      }
+      S = cur;
+    }
+  }
+  T *__restrict__ Xo = static_cast<T *>(a.X_out);
+  double dx2 = 0.0;
+  int nonfin = 0;
+  for (int e = tid; e < dd; e += blockDim.x) {
+    const T v = (T)S[e];
+    Xo[((int64_t)i * d + e / d) * d + e % d] = v;
+    const double dv = (double)v - X[e];
+    dx2 += dv * dv;
+    nonfin |= !isfinite(v);
+  }
+  dx2 = block_sum(dx2, s_scr);
+  const double nf = block_max((double)nonfin, s_scr);
+  if (tid == 0)
+    a.stats[i] = WideStat{dx2, x2, dmax, (nf != 0.0 || !isfinite(dmax)) ? 1.0 : 0.0, xc, hh, aii2,
+                          polar_steps < 0 ? 1.0 : 0.0};
+}
+
+// Partial X^T X over a slice of rows: workgroup g sums rows
+// [g rpg, (g + 1) rpg) into gram[g] (FP64), d^2 entries.
+template <typename T>
+__global__ void __launch_bounds__(256) wide_gram_kernel(const T *__restrict__ X, int nd, int d,
+                                                        double *gram, const int *stop_flag) {
+  __shared__ double xs[32][kWideMaxD + 1];
+  if (stop_flag) {
+    if (__atomic_load_n(stop_flag, __ATOMIC_RELAXED)) return;   // uniform
+  }
+  const int g = blockIdx.x, tid = threadIdx.x, dd = d * d;
+  const int rpg = (nd + gridDim.x - 1) / gridDim.x;
+  const int r0 = g * rpg, r1 = min(nd, r0 + rpg);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int ea[4], eb[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int e = tid + 256 * j;
+    const int ee = e < dd ? e : 0;
+    ea[j] = ee / d;
+    eb[j] = ee % d;
+  }
+  for (int rb = r0; rb < r1; rb += 32) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int e = tid + 256 * j;
+      const int rr = e / kWideMaxD, c = e % kWideMaxD;
+      const int row = rb + rr;
+      const int rowc = row < nd ? row : nd - 1, cc = c < d ? c : d - 1;
+      const double v = (double)X[(int64_t)rowc * d + cc];
+      xs[rr][c] = (row < r1 && c < d) ? v : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      for (int rr = 0; rr < 32; ++rr) acc[j] += xs[rr][ea[j]] * xs[rr][eb[j]];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int e = tid + 256 * j;
+    if (e < dd) gram[(size_t)g * dd + e] = acc[j];
+  }
+}
+
+// One workgroup after each step: FP64 reduction of the block records in a
+// fixed order, the objective F(X^t) (eq. def:f) from its per-block pieces
+//   F = (1/2)(||sum_i X_i^T X_i||^2 - sum_i ||X_i^T X_i||^2)
+//       - sum_i tr(X_i^T C_i) + (1/2) sum_{i != j} ||A_ij||^2,
+// and the stop rules: relative change ||X^{t+1} - X^t|| / ||X^t|| <= tol, or
+// the paper's ratio R^{t-1} = (F(X^{t-1}) - F(X^t)) / F(X^t) < tol, which
+// stops with X^t (this step's input) as the result.
+__global__ void __launch_bounds__(256) wide_finish_kernel(WideArgs a) {
+  __shared__ double s_scr[kMaxWaves];
+  if (a.stop_flag) {
+    if (__atomic_load_n(a.stop_flag, __ATOMIC_RELAXED)) return;   // uniform
+  }
+  const int tid = threadIdx.x, d = a.d, dd = d * d;
+  double dx2 = 0, x2 = 0, dmax = 0, nf = 0, xc = 0, hh = 0, aii2 = 0, pb = 0;
+  for (int p = tid; p < a.n; p += blockDim.x) {
+    const WideStat s = a.stats[p];
+    dx2 += s.dx2;
+    x2 += s.x2;
+    dmax = s.dmax > dmax ? s.dmax : dmax;
+    nf = s.nonfinite > nf ? s.nonfinite : nf;
+    xc += s.xc;
+    hh += s.hh;
+    aii2 += s.aii2;
+    pb = s.polar_bad > pb ? s.polar_bad : pb;
+  }
+  dx2 = block_sum(dx2, s_scr);
+  x2 = block_sum(x2, s_scr);
+  dmax = block_max(dmax, s_scr);
+  nf = block_max(nf, s_scr);
+  xc = block_sum(xc, s_scr);
+  hh = block_sum(hh, s_scr);
+  aii2 = block_sum(aii2, s_scr);
+  pb = block_max(pb, s_scr);
+  double Fx = 0.0;
+  if (a.objective) {
+    double ss = 0.0;
+    for (int e = tid; e < dd; e += blockDim.x) {
+      double s = 0.0;
+      for (int g = 0; g < kWideGramGroups; ++g) s += a.gram[(size_t)g * dd + e];
+      ss += s * s;
+    }
+    ss = block_sum(ss, s_scr);
+    double tot = 0.0;
+    if (a.sumsq) {
+      const int np = a.g.row_tiles * a.g.ks;
+      for (int p = tid; p < np; p += blockDim.x) tot += a.sumsq[p];
+      tot = block_sum(tot, s_scr);
+    }
+    if (tid == 0) {
+      WideCtl *w = a.wctl;
+      if (a.sumsq) {
+        w->obj_const = 0.5 * (tot - aii2);
+        w->have_const = 1;
+      }
+      Fx = 0.5 * (ss - hh) - xc + w->obj_const;
+    }
+  }
+  if (tid == 0) {
+    DevCtl *ctl = a.ctl;
+    const double rel = x2 > 0.0 ? sqrt(dx2 / x2) : 0.0;
+    ctl->sum_dx2 = dx2;
+    ctl->sum_x2 = x2;
+    ctl->rel_change = rel;
+    ctl->max_defect = dmax;
+    ctl->nonfinite = (nf != 0.0 || pb != 0.0) ? 1 : 0;
+    ctl->iters = a.iter + 1;
+    if (ctl->nonfinite || !isfinite(rel)) {
+      ctl->nonfinite = 1;
+      ctl->done = 1;
+    } else if (a.stop_rule == 0 && a.tol > 0.0 && rel <= a.tol) {
+      ctl->converged = 1;
+      ctl->done = 1;
+    }
+    if (a.objective) {
+      WideCtl *w = a.wctl;
+      double R = NAN;
+      if (a.iter >= 1) R = (w->obj - Fx) / Fx;
+      w->obj_prev = w->obj;
+      w->obj = Fx;
+      w->obj_ratio = R;
+      if (!ctl->done && a.stop_rule == 1 && a.tol > 0.0 && a.iter >= 1 && R < a.tol) {
+        ctl->converged = 1;
+        ctl->done = 1;
+        ctl->iters = a.iter;         // X^t, this step's input, is the result
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Spectral initialization for d up to 32 (the same subspace iteration as the
+// narrow path: W = A Y, Cholesky-QR of W in FP64, Rayleigh-Ritz values).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) wide_gram_finish_kernel(const double *igram, int n, int d,
+                                                                DevCtl *ctl, WideCtl *w) {
+  constexpr int NE = kWideMaxD * kWideMaxD;
+  __shared__ double G1[NE], G2[NE], Rm[NE];
+  if (__atomic_load_n(&ctl->init_done, __ATOMIC_RELAXED)) return;   // uniform
+  const int dd = d * d, tid = threadIdx.x;
+  for (int e = tid; e < 2 * dd; e += blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += igram[(size_t)i * 2 * dd + e];
+    if (e < dd) G1[e] = s; else G2[e - dd] = s;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int bad = 0;
+    for (int r = 0; r < d; ++r)
+      for (int k = 0; k < d; ++k) w->T[r * d + k] = 0.5 * (G1[r * d + k] + G1[k * d + r]);
+    for (int j = 0; j < dd; ++j) Rm[j] = 0.0;
+    for (int j = 0; j < d; ++j) {
+      double s = G2[j * d + j];
+      for (int q = 0; q < j; ++q) s -= Rm[q * d + j] * Rm[q * d + j];
+      if (!(s > 0.0) || !isfinite(s)) { bad = 1; s = 1.0; }
+      const double rjj = sqrt(s);
+      Rm[j * d + j] = rjj;
+      for (int k = j + 1; k < d; ++k) {
+        double t = G2[j * d + k];
+        for (int q = 0; q < j; ++q) t -= Rm[q * d + j] * Rm[q * d + k];
+        Rm[j * d + k] = t / rjj;
+      }
+    }
+    for (int j = 0; j < dd; ++j) w->Rinv[j] = 0.0;
+    for (int k = 0; k < d; ++k) {
+      w->Rinv[k * d + k] = 1.0 / Rm[k * d + k];
+      for (int r = k - 1; r >= 0; --r) {
+        double s = 0.0;
+        for (int q = r + 1; q <= k; ++q) s += Rm[r * d + q] * w->Rinv[q * d + k];
+        w->Rinv[r * d + k] = -s / Rm[r * d + r];
+      }
+    }
+    if (bad) ctl->init_bad = 1;
+  }
+}
+
+// One thread per row: Y_next = W R^{-1}, residual rows W - Y T.
+template <typename T>
+__global__ void __launch_bounds__(256) wide_init_apply_kernel(const T *W, const T *Y, T *Yn, int nd, int d,
+                                                              double *part, int num_groups, DevCtl *ctl,
+                                                              WideCtl *w, int iter, double tol) {
+  constexpr int NE = kWideMaxD * kWideMaxD;
+  __shared__ double sR[NE], sT[NE];
+  __shared__ double s_scr[kMaxWaves];
+  __shared__ int s_last;
+  if (__atomic_load_n(&ctl->init_done, __ATOMIC_RELAXED)) return;   // uniform
+  const int tid = threadIdx.x, dd = d * d;
+  for (int e = tid; e < dd; e += blockDim.x) {
+    sR[e] = w->Rinv[e];
+    sT[e] = w->T[e];
+  }
+  __syncthreads();
+  const int row = blockIdx.x * blockDim.x + tid;
+  const int rowc = row < nd ? row : nd - 1;
+  double wr[kWideMaxD], yr[kWideMaxD];
+#pragma unroll
+  for (int m = 0; m < kWideMaxD; ++m) {
+    const int mc = m < d ? m : d - 1;
+    const double wv = (double)W[(int64_t)rowc * d + mc], yv = (double)Y[(int64_t)rowc * d + mc];
+    wr[m] = m < d ? wv : 0.0;
+    yr[m] = m < d ? yv : 0.0;
+  }
+  double res2 = 0.0;
+  int bad = 0;
+  for (int k = 0; k < d; ++k) {
+    double s = 0.0, t = 0.0;
+#pragma unroll
+    for (int m = 0; m < kWideMaxD; ++m) {
+      const int mm = m < d ? m : 0;
+      s += wr[m] * sR[mm * d + k];
+      t += yr[m] * sT[mm * d + k];
+    }
+    double out = 0.0, r = 0.0;
+#pragma unroll
+    for (int m = 0; m < kWideMaxD; ++m) r = (m == k) ? wr[m] : r;
+    r -= t;
+    out = s;
+    if (row < nd) Yn[(int64_t)row * d + k] = (T)out;
+    res2 += row < nd ? r * r : 0.0;
+    bad |= (row < nd) && !isfinite(s);
+  }
+  res2 = block_sum(res2, s_scr);
+  const double fbad = block_max((double)bad, s_scr);
+  if (tid == 0) {
+    part[2 * blockIdx.x] = res2;
+    part[2 * blockIdx.x + 1] = fbad;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (tid == 0) s_last = (atomicAdd(&ctl->arrive2, 1u) == (unsigned)num_groups - 1u);
+  __syncthreads();
+  if (s_last) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    double s = 0.0, b = 0.0;
+    for (int g = tid; g < num_groups; g += blockDim.x) {
+      s += part[2 * g];
+      b = part[2 * g + 1] > b ? part[2 * g + 1] : b;
+    }
+    s = block_sum(s, s_scr);
+    b = block_max(b, s_scr);
+    if (tid == 0) {
+      double tn = 0.0;
+      for (int e = 0; e < dd; ++e) tn += w->T[e] * w->T[e];
+      const double rel = tn > 0.0 ? sqrt(s / tn) : 0.0;
+      ctl->init_res = rel;
+      ctl->init_iters = iter + 1;
+      if (b != 0.0 || !isfinite(rel)) ctl->init_bad = 1;
+      if (iter >= 1 && rel <= tol) ctl->init_done = 1;   // the first basis is random
+      if (ctl->init_bad) ctl->init_done = 1;
+      ctl->arrive2 = 0u;
+    }
+  }
+}
+
+// One workgroup per block: X0_i = sgn(Y_i) in FP64.
+template <typename T>
+__global__ void __launch_bounds__(256) wide_init_polar_kernel(const T *Y, T *X0, int n, int d, DevCtl *ctl) {
+  constexpr int NE = kWideMaxD * kWideMaxD;
+  __shared__ double sS[NE], sM[NE], sN[NE];
+  __shared__ double s_scr[kMaxWaves];
+  const int b = blockIdx.x, dd = d * d;
+  for (int e = threadIdx.x; e < dd; e += blockDim.x) sS[e] = (double)Y[(int64_t)b * dd + e];
+  __syncthreads();
+  const int steps = wide_polar(sS, sM, sN, d, s_scr);
+  for (int e = threadIdx.x; e < dd; e += blockDim.x) X0[(int64_t)b * dd + e] = (T)sS[e];
+  if (threadIdx.x == 0) {
+    atomicMax(&ctl->polar_steps, steps);
+    if (steps < 0) atomicOr(&ctl->init_bad, 1);
+  }
+}
+
+// Ritz values: eigenvalues of T (FP64 cyclic Jacobi), descending.
+__global__ void wide_init_finish_kernel(DevCtl *ctl, WideCtl *w, int d) {
+  constexpr int NE = kWideMaxD * kWideMaxD;
+  __shared__ double M[NE];
+  if (threadIdx.x != 0) return;
+  for (int e = 0; e < d * d; ++e) M[e] = w->T[e];
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int p = 0; p < d; ++p)
+      for (int q = 0; q < d; ++q) {
+        tot += M[p * d + q] * M[p * d + q];
+        if (p != q) off += M[p * d + q] * M[p * d + q];
+      }
+    if (off <= 1e-30 * tot) break;
+    for (int p = 0; p < d - 1; ++p)
+      for (int q = p + 1; q < d; ++q) {
+        const double apq = M[p * d + q];
+        if (apq == 0.0) continue;
+        const double theta = (M[q * d + q] - M[p * d + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < d; ++k) {
+          const double mp = M[p * d + k], mq = M[q * d + k];
+          M[p * d + k] = c * mp - s * mq;
+          M[q * d + k] = s * mp + c * mq;
+        }
+        for (int k = 0; k < d; ++k) {
+          const double mp = M[k * d + p], mq = M[k * d + q];
+          M[k * d + p] = c * mp - s * mq;
+          M[k * d + q] = s * mp + c * mq;
+        }
+      }
+  }
+  double wv[kWideMaxD];
+  for (int i = 0; i < d; ++i) wv[i] = M[i * d + i];
+  for (int i = 0; i < d; ++i)
+    for (int j = i + 1; j < d; ++j)
+      if (wv[j] > wv[i]) {
+        const double t = wv[i];
+        wv[i] = wv[j];
+        wv[j] = t;
+      }
+  for (int i = 0; i < d; ++i) w->ritz[i] = wv[i];
+  for (int i = 0; i < d && i < kMaxD; ++i) ctl->ritz[i] = wv[i];
+}
+
+__global__ void wide_ctl_reset_kernel(WideCtl *w) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  w->obj_const = 0.0;
+  w->obj_prev = NAN;
+  w->obj = NAN;
+  w->obj_ratio = NAN;
+  w->have_const = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Geometry, workspace and launches.
+// ---------------------------------------------------------------------------
+int wide_supported_fmt(int fmt) { return fmt == NSRGS_A_F64 || fmt == NSRGS_A_F32; }
+
+// The geometry and workspace depend on the iterate precision only: F64
+// storage has FP64 partial products, every other format FP32 ones.
+WideGeom wide_geom(int n, int d, int fmt) {
+  WideGeom g{};
+  const int nd = n * d;
+  g.nt = d <= 16 ? 1 : 2;
+  g.kstep = fmt == NSRGS_A_F64 ? wide_kstep<double>() : wide_kstep<float>();
+  g.row_tiles = (nd + kWideRows - 1) / kWideRows;
+  g.rows_pad = g.row_tiles * kWideRows;
+  // About 1024 workgroups (four per CU), at most 32 column chunks.
+  int ks = (1024 + g.row_tiles - 1) / g.row_tiles;
+  ks = ks < 1 ? 1 : ks > 32 ? 32 : ks;
+  const int steps = (nd + g.kstep - 1) / g.kstep;
+  const int steps_per = (steps + ks - 1) / ks;
+  g.kchunk = steps_per * g.kstep;
+  g.ks = (nd + g.kchunk - 1) / g.kchunk;
+  return g;
+}
+
+static size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+WideLayout wide_layout(int n, int d, int fmt) {
+  const WideGeom g = wide_geom(n, d, fmt);
+  const size_t tb = fmt == NSRGS_A_F64 ? 8 : 4;
+  WideLayout L{};
+  size_t off = 0;
+  L.ctl = off;   off += a256(sizeof(WideCtl));
+  L.stats = off; off += a256((size_t)n * sizeof(WideStat));
+  L.part = off;  off += a256((size_t)g.ks * g.rows_pad * 32 * tb);
+  L.gram = off;  off += a256((size_t)kWideGramGroups * d * d * sizeof(double));
+  L.sumsq = off; off += a256((size_t)g.row_tiles * g.ks * sizeof(double));
+  L.igram = off; off += a256((size_t)n * 2 * d * d * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+template <typename T>
+static hipError_t wide_launch_product(const WideArgs &a, hipStream_t s) {
+  const dim3 grid(a.g.row_tiles, a.g.ks), block(256);
+  if (a.g.nt == 1) hipLaunchKernelGGL((wide_product_kernel<T, 1>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((wide_product_kernel<T, 2>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t wide_step_t(const WideArgs &a, hipStream_t s) {
+  hipError_t e;
+  if (a.objective) {
+    hipLaunchKernelGGL(wide_gram_kernel<T>, dim3(kWideGramGroups), dim3(256), 0, s,
+                       static_cast<const T *>(a.X_in), a.nd, a.d, a.gram, a.stop_flag);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if ((e = wide_launch_product<T>(a, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(wide_epilogue_kernel<T>, dim3(a.n), dim3(256), 0, s, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(wide_finish_kernel, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_wide_step(int fmt, const WideArgs &a, hipStream_t s) {
+  if (fmt == NSRGS_A_F64) return wide_step_t<double>(a, s);
+  if (fmt == NSRGS_A_F32) return wide_step_t<float>(a, s);
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t wide_init_product_t(const WideArgs &a, hipStream_t s) {
+  hipError_t e;
+  if ((e = wide_launch_product<T>(a, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(wide_epilogue_kernel<T>, dim3(a.n), dim3(256), 0, s, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(wide_gram_finish_kernel, dim3(1), dim3(1024), 0, s, a.igram, a.n, a.d, a.ctl, a.wctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_wide_init_product(int fmt, const WideArgs &a, hipStream_t s) {
+  if (fmt == NSRGS_A_F64) return wide_init_product_t<double>(a, s);
+  if (fmt == NSRGS_A_F32) return wide_init_product_t<float>(a, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_wide_init_apply(int fmt, const void *W, const void *Y, void *Y_next, int nd, int d,
+                                  double *partials, int num_groups, DevCtl *ctl, WideCtl *wctl,
+                                  int iter, double tol, hipStream_t s) {
+  const dim3 grid(num_groups), block(256);
+  if (fmt == NSRGS_A_F64)
+    hipLaunchKernelGGL(wide_init_apply_kernel<double>, grid, block, 0, s, (const double *)W, (const double *)Y,
+                       (double *)Y_next, nd, d, partials, num_groups, ctl, wctl, iter, tol);
+  else
+    hipLaunchKernelGGL(wide_init_apply_kernel<float>, grid, block, 0, s, (const float *)W, (const float *)Y,
+                       (float *)Y_next, nd, d, partials, num_groups, ctl, wctl, iter, tol);
+  return hipGetLastError();
+}
+
+hipError_t launch_wide_init_polar(int fmt, const void *Y, void *X0, int n, int d, DevCtl *ctl,
+                                  hipStream_t s) {
+  if (fmt == NSRGS_A_F64)
+    hipLaunchKernelGGL(wide_init_polar_kernel<double>, dim3(n), dim3(256), 0, s, (const double *)Y,
+                       (double *)X0, n, d, ctl);
+  else
+    hipLaunchKernelGGL(wide_init_polar_kernel<float>, dim3(n), dim3(256), 0, s, (const float *)Y,
+                       (float *)X0, n, d, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_wide_init_finish(DevCtl *ctl, WideCtl *wctl, int d, hipStream_t s) {
+  hipLaunchKernelGGL(wide_init_finish_kernel, dim3(1), dim3(64), 0, s, ctl, wctl, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_wide_ctl_reset(WideCtl *wctl, hipStream_t s) {
+  hipLaunchKernelGGL(wide_ctl_reset_kernel, dim3(1), dim3(64), 0, s, wctl);
+  return hipGetLastError();
+}
+
+}  // namespace nsrgs

@@ -46,7 +46,7 @@ def _mat(fmt=P.F32, ld=304, data=16):
 
 
 @pytest.mark.parametrize("n,d,msg", [(1, 3, "n must be"), (0, 3, "n must be"), (10, 0, "d must be"),
-                                     (10, 17, "d must be")])
+                                     (10, 33, "d must be")])
 def test_step_rejects_bad_sizes(n, d, msg):
     L = P.lib()
     m = _mat()
@@ -75,8 +75,11 @@ def test_step_rejects_bad_matrix_and_buffers():
     # aliasing input/output
     st = L.sync_step(ctypes.byref(m), n, d, 0.0, 3, 4096, 4096 + 64, 256, ws_bytes, None)
     assert st == 1 and "overlap" in L.nsrgs_last_error().decode()
-    # workspace too small
-    st = L.sync_step(ctypes.byref(m), n, d, 0.0, 3, 4096, 1 << 20, 256, ws_bytes - 1, None)
+    # workspace too small (the streaming-kernel calls need only the part before
+    # the matrix-core region; the exact-polar step needs all of it)
+    st = L.sync_step(ctypes.byref(m), n, d, 0.0, 3, 4096, 1 << 20, 256, 4096, None)
+    assert st == 3
+    st = L.sync_step_polar(ctypes.byref(m), n, d, 0.0, 4096, 1 << 20, 256, ws_bytes - 1, None)
     assert st == 3
     # ns_steps out of range, non-finite mu
     assert L.sync_step(ctypes.byref(m), n, d, 0.0, 65, 4096, 1 << 20, 256, ws_bytes, None) == 1
@@ -86,14 +89,19 @@ def test_step_rejects_bad_matrix_and_buffers():
 def test_workspace_size_scales_and_rejects():
     L = P.lib()
     assert L.sync_workspace_bytes(1, 3, P.F32) == 0
-    assert L.sync_workspace_bytes(10, 17, P.F32) == 0
+    assert L.sync_workspace_bytes(10, 33, P.F32) == 0
+    assert L.sync_workspace_bytes(10, 17, P.BF16) == 0
     assert L.sync_workspace_bytes(10, 3, 9) == 0
     small = L.sync_workspace_bytes(100, 3, P.F32)
     big = L.sync_workspace_bytes(20000, 3, P.F32)
+    bigger = L.sync_workspace_bytes(40000, 3, P.F32)
     f64 = L.sync_workspace_bytes(100, 3, P.F64)
-    assert 0 < small < big and f64 > small
-    # the workspace is O(n d^2): no nd x nd scratch
-    assert big < 64 * 20000 * 9 * 4
+    assert 0 < small < big < bigger and f64 > small
+    # the workspace grows linearly in n d (iterates, per-block records, partial
+    # products of at most a few column chunks): no nd x nd scratch
+    nd = 60000
+    assert big < 0.01 * nd * nd * 4
+    assert bigger < 2.2 * big
 
 
 def test_solve_and_init_reject_before_device_use():
@@ -170,10 +178,41 @@ def test_block_sparse_entry_points_reject_on_the_host():
     null = P._Bsr(P.F32, 0, 256, None, 1024)
     assert L.sync_step_bsr(ctypes.byref(null), 100, 3, 0.0, 3, 4096, 1 << 20, 256, ws, None) == 1
     assert L.sync_step_bsr(ctypes.byref(b), 100, 3, 0.0, 3, 4096, 4096 + 64, 256, ws, None) == 1
-    assert L.sync_step_bsr(ctypes.byref(b), 100, 3, 0.0, 3, 4096, 1 << 20, 256, ws - 1, None) == 3
+    assert L.sync_step_bsr(ctypes.byref(b), 100, 3, 0.0, 3, 4096, 1 << 20, 256, 4096, None) == 3
     assert L.sync_step_bsr(ctypes.byref(b), 100, 3, float("nan"), 3, 4096, 1 << 20, 256, ws, None) == 1
     nnzb = ctypes.c_int64(0)
     assert L.nsrgs_bsr_count(16, 100, 3, 1.5, 0, 256, 512, ctypes.byref(nnzb), None) == 1      # p > 1
     assert L.nsrgs_bsr_count(None, 100, 3, 0.5, 0, 256, 512, ctypes.byref(nnzb), None) == 1
     assert L.nsrgs_bsr_fill(16, 100, 3, 1.0, 0.5, 0, ctypes.byref(f64), None) == 2
     assert L.nsrgs_bsr_fill(16, 100, 3, float("inf"), 0.5, 0, ctypes.byref(b), None) == 1
+
+
+def test_wide_block_sizes_need_f64_or_f32():
+    """16 < d <= 32 runs on the matrix-core path, F64 and F32 storage only; the
+    exact-polar and GPM steps likewise (checked before any device work)."""
+    L = P.lib()
+    m = _mat(P.BF16, ld=352)
+    st = L.sync_step(ctypes.byref(m), 20, 17, 0.0, 3, 16, 4096, 256, 1 << 30, None)
+    assert st == 2 and "F64 or F32" in L.nsrgs_last_error().decode()
+    st = L.sync_step_gpm(ctypes.byref(m), 20, 3, 16, 4096, 256, 1 << 30, None)
+    assert st == 2
+    assert L.sync_workspace_bytes(20, 17, P.BF16) == 0
+    assert L.sync_workspace_bytes(20, 25, P.F64) > L.sync_workspace_bytes(20, 16, P.F64) > 0
+    assert L.sync_workspace_bytes(20, 33, P.F64) == 0
+    # the no-allocation step keeps the narrow path's limit
+    m32 = _mat(P.F32, ld=352)
+    st = L.sync_step_noalloc(ctypes.byref(m32), 20, 17, 0.0, 3, 16, 4096, None)
+    assert st == 1 and "d must be" in L.nsrgs_last_error().decode()
+
+
+def test_solve_rejects_unknown_method_and_stop_rule():
+    L = P.lib()
+    m = _mat(P.F64, ld=304)
+    for method, stop, msg in ((3, 0, "method"), (0, 2, "stop rule")):
+        o = P._SolveOpts(0, 60, 0.0, 0, None, 16, 0, method, stop)
+        st = L.sync_solve(ctypes.byref(m), 100, 3, 0.0, 3, 10, 0.0, 4096, 256, 1 << 30, None,
+                          ctypes.byref(o), None)
+        assert st == 1 and msg in L.nsrgs_last_error().decode()
+    o = P._SolveOpts(0, 60, 0.0, 0, None, 16, 1, 1, 0)             # symmetric + exact polar
+    st = L.sync_solve(ctypes.byref(m), 100, 3, 0.0, 3, 10, 0.0, 4096, 256, 1 << 30, None, ctypes.byref(o), None)
+    assert st == 2
