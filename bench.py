@@ -280,23 +280,15 @@ def table1_bench(steps: int = 50, warmup: int = 5, seed: int = 61):
         X0 = torch.from_numpy(synth.perturbed_start(Z, 0.02, seed + 2)).to("cuda", dt)
         res = {}
         for method in ("ns_rgs", "polar", "gpm"):
-            def one(xi, xo):
-                if method == "ns_rgs":
-                    P.step(Am, n, d, xi, xo, ws, ns_steps=1)
-                elif method == "polar":
-                    P.step_polar(Am, n, d, xi, xo, ws)
-                else:
-                    P.step_gpm(Am, n, d, xi, xo, ws)
-            Xa, Xb = X0.clone(), torch.empty_like(X0)
-            for _ in range(warmup):
-                one(Xa, Xb)
-                Xa, Xb = Xb, Xa
+            # `steps` iterations in one sync_solve call (fixed budget, no stop
+            # rule): the library's own launch loop, timed with HIP events
+            X = X0.clone()
+            P.solve(Am, n, d, X, ws, ns_steps=1, max_iters=warmup, init=False, method=method)
+            X = X0.clone()
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            for _ in range(steps):
-                one(Xa, Xb)
-                Xa, Xb = Xb, Xa
+            P.solve(Am, n, d, X, ws, ns_steps=1, max_iters=steps, init=False, method=method, check_every=steps)
             e1.record()
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / steps

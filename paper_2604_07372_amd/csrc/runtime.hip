@@ -324,6 +324,7 @@ static WideArgs wide_args(const nsrgs_matrix *A, int n, int d, void *ws) {
   a.d = d;
   a.nd = n * d;
   a.part = base + W.part;
+  a.xs = base + W.xs;
   a.stats = reinterpret_cast<WideStat *>(base + W.stats);
   a.igram = reinterpret_cast<double *>(base + W.igram);
   a.gram = reinterpret_cast<double *>(base + W.gram);

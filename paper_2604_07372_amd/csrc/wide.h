@@ -10,10 +10,11 @@
 //
 // At d = 25 the product A X costs 2d = 50 flops per element of A, above what
 // the vector units sustain against HBM, so it runs on MFMA: a workgroup owns
-// 128 rows of A and one chunk of its columns, each wave 32 rows (two 16-row
-// tiles), and accumulates A_tile X_chunk with v_mfma_*_16x16x4 over columns
-// padded to 16 or 32.  The partial products of the column chunks go to the
-// workspace; a per-block epilogue kernel sums them and runs the d x d part.
+// 64 mt rows of A and one chunk of its columns, each wave 16 mt rows (mt
+// 16-row tiles), and accumulates A_tile X_chunk with v_mfma_*_16x16x4 over columns
+// padded to 16 or 32, reading X from a copy arranged in operand order.  The
+// partial products of the column chunks go to the workspace; a per-block
+// epilogue kernel sums them and runs the d x d part.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -25,7 +26,6 @@ namespace nsrgs {
 struct DevCtl;
 
 constexpr int kWideMaxD = 32;       // largest block size of this path
-constexpr int kWideRows = 128;      // rows of A per workgroup (4 waves x 2 tiles x 16)
 constexpr int kWideGramGroups = 64; // workgroups of the X^T X reduction
 
 enum WideMethod { WIDE_NS = 0, WIDE_POLAR = 1, WIDE_GPM = 2 };
@@ -55,17 +55,23 @@ struct alignas(256) WideCtl {
 // Launch geometry of the product for a problem (n, d, storage format).
 struct WideGeom {
   int nt;          // 16-column tiles (1: d <= 16, 2: d <= 32)
-  int kstep;       // columns per MFMA step: 32 (F64) or 64 (F32)
-  int row_tiles;   // ceil(nd / 128)
-  int rows_pad;    // row_tiles * 128
+  int mt;          // 16-row tiles per wave (rows per workgroup = 64 mt)
+  int rows;        // rows of A per workgroup
+  int xcd_remap;   // deal column-chunk-major tile ranges to the XCDs
+  int ku;          // 16-byte vectors per lane per tile row per step (8 / mt)
+  int kstep;       // columns per step: 4 ku V (V = 2 for F64, 4 for F32)
+  int steps;       // ceil(nd / kstep)
+  int row_tiles;   // ceil(nd / rows)
+  int rows_pad;    // row_tiles * rows
   int ks;          // column chunks
+  int ks_max;      // bound on ks for every step width (sizes the workspace)
   int kchunk;      // columns per chunk (multiple of kstep)
 };
 WideGeom wide_geom(int n, int d, int fmt);
 
 // Workspace areas of the wide path (offsets relative to its region).
 struct WideLayout {
-  size_t ctl, stats, part, gram, sumsq, igram, total;
+  size_t ctl, stats, part, xs, gram, sumsq, igram, total;
 };
 WideLayout wide_layout(int n, int d, int fmt);
 
@@ -76,6 +82,7 @@ struct WideArgs {
   const void *X_in;    // X^t, or Y (init)
   void *X_out;         // X^{t+1}, or W = A Y (init)
   void *part;          // ks x rows_pad x 32 partial products
+  void *xs;            // X in the product's B-operand order (wide_xs_kernel)
   WideStat *stats;     // n per-block records (step)
   double *igram;       // n x 2 d^2 per-block Grams Y^T W, W^T W (init)
   double *gram;        // kWideGramGroups x d^2 partial X^T X (objective)

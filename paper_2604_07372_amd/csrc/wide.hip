@@ -1,6 +1,7 @@
 // Kernels of the matrix-core path (block sizes up to d = 32; NS-RGS, exact
 // polar and GPM retractions; the objective of eq. def:f).  See wide.h.
 #include "device.h"
+#include "host.h"
 #include "kernels.h"
 #include "wide.h"
 
@@ -25,35 +26,39 @@ __device__ __forceinline__ typename WideT<T>::v4 mfma4(T a, T b, typename WideT<
   else return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-constexpr int kWU = 4;   // 16-byte column vectors per lane per tile row per step
-
-template <typename T>
-constexpr int wide_kstep() { return 4 * kWU * WideT<T>::V; }   // 32 (F64) or 64 (F32) columns
+// KU: 16-byte column vectors per lane per tile row per step; a step covers
+// 4 KU V columns.
+template <typename T, int KU>
+constexpr int wide_kstep() { return 4 * KU * WideT<T>::V; }
 
 // ---------------------------------------------------------------------------
 // Product kernel: partial[ks][r][c] = sum over the columns k of chunk ks of
 // A[r][k] X[k][c], for the 128 rows of this workgroup and c < 16 NT.
 //
-// A step covers KSTEP columns.  Lane (m = l % 16, q = l / 16) of a wave loads
-// kWU 16-byte vectors of each of its two tile rows, at columns
-// kb + (u 4 + q) V .. + V (u < kWU): the four lanes of a row read 64 bytes
+// A step covers KSTEP = 4 KU V columns.  Lane (m = l % 16, q = l / 16) of a
+// wave loads KU 16-byte vectors of each of its two tile rows, at columns
+// kb + (u 4 + q) V .. + V (u < KU): the four lanes of a row read 64 bytes
 // contiguously per load, a wave 16 rows x 64 bytes.  Element v of vector u is
-// the lane's A operand of the tile product (u, v); column kb + (u 4 + q) V + v
-// is its k index, so the X tile in LDS is stored in the same order and every
-// B operand read is 64 consecutive values (no bank conflicts).  The X tile is
-// loaded once per workgroup per step (shared by the four waves) into one of
-// two LDS buffers while the other is in use; the next step's A vectors are in
-// flight during the current step's products.
+// the lane's A operand of the tile product (u, v), so column kb + (u 4 + q) V
+// + v is its k index.  The B operands come from Xs, a copy of X arranged in
+// exactly that order by wide_xs_kernel: for each step and 16-column tile, lane
+// l's KU V values are contiguous, so a wave reads them with KU V / (16 /
+// sizeof(T)) 16-byte loads per tile, 64 lanes x 64 bytes contiguous.  Each
+// wave works alone (no LDS, no barrier); the next step's A and B vectors are
+// in flight during the current step's products.
 // ---------------------------------------------------------------------------
-template <typename T, int NT>
+// MT 16-row tiles per wave (64 MT rows per workgroup) and KU = 8 / MT
+// vectors per tile row per step: each B operand serves MT tiles.
+template <int MT> constexpr int wide_ku() { return 8 / MT; }
+
+template <typename T, int NT, int MT>
 __global__ void __launch_bounds__(256) wide_product_kernel(WideArgs a) {
   using v4 = typename WideT<T>::v4;
   constexpr int V = WideT<T>::V;
-  constexpr int KSTEP = wide_kstep<T>();
-  constexpr int XW = 16 * NT;               // X tile width
-  constexpr int XT = KSTEP * XW;            // X tile elements
-  constexpr int XPT = XT / 256;             // per thread
-  __shared__ __attribute__((aligned(16))) T xs[2][XT];
+  constexpr int KU = wide_ku<MT>();
+  constexpr int ROWS = 64 * MT;
+  constexpr int KSTEP = wide_kstep<T, KU>();
+  constexpr int BQ = KU * V * (int)sizeof(T) / 16;   // 16-byte B loads per tile per step
   __shared__ double s_scr[kMaxWaves];
   if (a.stop_flag) {
     if (__atomic_load_n(a.stop_flag, __ATOMIC_RELAXED)) return;   // uniform
@@ -62,69 +67,83 @@ __global__ void __launch_bounds__(256) wide_product_kernel(WideArgs a) {
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int m = lane & 15, q = lane >> 4;
-  const int nd = a.nd, d = a.d;
-  const int rt = blockIdx.x, ks = blockIdx.y;
+  const int nd = a.nd;
+  // Workgroup b runs on XCD b % 8 (round-robin dispatch); the logical tiles
+  // are ordered column-chunk major and dealt out so that each XCD works on a
+  // contiguous range of them, i.e. on few column chunks, and its L2 holds
+  // only those chunks' B operands.
+  const int total = a.g.row_tiles * a.g.ks;
+  int lin = blockIdx.x;
+  if (a.g.xcd_remap) {
+    const int per = (total + 7) / 8;
+    lin = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  }
+  if (lin >= total) return;                          // uniform: padding workgroups of the remap
+  const int rt = lin % a.g.row_tiles, ks = lin / a.g.row_tiles;
   const int kbeg = ks * a.g.kchunk;
   const int kend = min(nd, kbeg + a.g.kchunk);
   const int nsteps = kend > kbeg ? (kend - kbeg + KSTEP - 1) / KSTEP : 0;
+  const int step0 = kbeg / KSTEP;
   const char *__restrict__ Ab = static_cast<const char *>(a.A);
-  const T *__restrict__ X = static_cast<const T *>(a.X_in);
+  const uint4 *__restrict__ Xs = static_cast<const uint4 *>(a.xs);
   const bool want_ssq = a.sumsq != nullptr;
 
-  int64_t roff[2];
-  bool rowok[2];
+  int64_t roff[MT];
+  bool rowok[MT];
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt) {
-    const int row = rt * kWideRows + wave * 32 + mt * 16 + m;
+  for (int mt = 0; mt < MT; ++mt) {
+    const int row = rt * ROWS + wave * 16 * MT + mt * 16 + m;
     rowok[mt] = row < nd;
     roff[mt] = (int64_t)(row < nd ? row : nd - 1) * a.ld * (int64_t)sizeof(T);
   }
 
-  v4 acc[2][NT];
+  v4 acc[MT][NT];
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
+  for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = v4{0, 0, 0, 0};
   double ssq = 0.0;
 
-  // X tile element e: row kr = e / XW of the step, column c = e % XW; its LDS
-  // slot follows the lane order of the B operand (see above).
-  auto xload = [&](int kb, T (&xr)[XPT]) {
+  auto load = [&](int s, uint4 (&ar)[MT][KU], uint4 (&br)[NT][BQ]) {
+    const int kb = kbeg + s * KSTEP;
 #pragma unroll
-    for (int j = 0; j < XPT; ++j) {
-      const int e = tid + 256 * j;
-      const int k = kb + e / XW, c = e % XW;
-      const int kk = k < nd ? k : nd - 1, cc = c < d ? c : d - 1;   // clamped, in bounds
-      const T v = X[(int64_t)kk * d + cc];
-      xr[j] = (k < nd && c < d) ? v : T(0);
+    for (int nt = 0; nt < NT; ++nt) {
+      const uint4 *bp = Xs + ((int64_t)((step0 + s) * NT + nt) * 64 + lane) * BQ;
+#pragma unroll
+      for (int j = 0; j < BQ; ++j) br[nt][j] = bp[j];
     }
-  };
-  auto xstore = [&](int buf, const T (&xr)[XPT]) {
 #pragma unroll
-    for (int j = 0; j < XPT; ++j) {
-      const int e = tid + 256 * j;
-      const int kr = e / XW, c = e % XW;
-      const int u = kr / (4 * V), qq = (kr / V) & 3, v = kr % V;
-      xs[buf][((u * V + v) * NT + (c >> 4)) * 64 + qq * 16 + (c & 15)] = xr[j];
-    }
-  };
-  auto aload = [&](int kb, uint4 (&ar)[2][kWU]) {
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-      for (int u = 0; u < kWU; ++u) {
+      for (int u = 0; u < KU; ++u) {
         const int kc = kb + (u * 4 + q) * V;
         const int kcc = kc < nd ? kc : 0;            // a vector starting at or past nd reads column 0
         ar[mt][u] = ld16_stream(Ab + roff[mt] + (int64_t)kcc * (int64_t)sizeof(T));
       }
   };
-  auto compute = [&](int buf, const uint4 (&ar)[2][kWU], int kb) {
+  auto compute = [&](int s, const uint4 (&ar)[MT][KU], const uint4 (&br)[NT][BQ]) {
+    const int kb = kbeg + s * KSTEP;
     const bool ragged = kb + KSTEP > nd;             // uniform: only the matrix's last step
+    T bv[NT][KU * V];
 #pragma unroll
-    for (int u = 0; u < kWU; ++u) {
-      T av[2][V];
+    for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt) {
+      for (int j = 0; j < BQ; ++j) {
+        if constexpr (sizeof(T) == 8) {
+          bv[nt][2 * j] = __hiloint2double((int)br[nt][j].y, (int)br[nt][j].x);
+          bv[nt][2 * j + 1] = __hiloint2double((int)br[nt][j].w, (int)br[nt][j].z);
+        } else {
+          bv[nt][4 * j] = __uint_as_float(br[nt][j].x);
+          bv[nt][4 * j + 1] = __uint_as_float(br[nt][j].y);
+          bv[nt][4 * j + 2] = __uint_as_float(br[nt][j].z);
+          bv[nt][4 * j + 3] = __uint_as_float(br[nt][j].w);
+        }
+      }
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      T av[MT][V];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
         if constexpr (sizeof(T) == 8) {
           av[mt][0] = __hiloint2double((int)ar[mt][u].y, (int)ar[mt][u].x);
           av[mt][1] = __hiloint2double((int)ar[mt][u].w, (int)ar[mt][u].z);
@@ -137,22 +156,19 @@ __global__ void __launch_bounds__(256) wide_product_kernel(WideArgs a) {
       }
       if (ragged) {
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
           for (int v = 0; v < V; ++v) av[mt][v] = (kb + (u * 4 + q) * V + v < nd) ? av[mt][v] : T(0);
       }
 #pragma unroll
-      for (int v = 0; v < V; ++v) {
+      for (int v = 0; v < V; ++v)
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const T b = xs[buf][((u * V + v) * NT + nt) * 64 + lane];
+        for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-          for (int mt = 0; mt < 2; ++mt) acc[mt][nt] = mfma4<T>(av[mt][v], b, acc[mt][nt]);
-        }
-      }
+          for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma4<T>(av[mt][v], bv[nt][u * V + v], acc[mt][nt]);
       if (want_ssq) {
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
           for (int v = 0; v < V; ++v) {
             const double x = rowok[mt] ? (double)av[mt][v] : 0.0;
@@ -162,69 +178,104 @@ __global__ void __launch_bounds__(256) wide_product_kernel(WideArgs a) {
     }
   };
 
-  uint4 ar0[2][kWU], ar1[2][kWU];
-  T xr[XPT];
-  if (nsteps > 0) {
-    xload(kbeg, xr);
-    xstore(0, xr);
-    aload(kbeg, ar0);
-  }
-  __syncthreads();
-  // Unrolled by two so the two A register sets take turns without copies.
+  uint4 ar0[MT][KU], ar1[MT][KU], br0[NT][BQ], br1[NT][BQ];
+  if (nsteps > 0) load(0, ar0, br0);
+  // Unrolled by two so the two register sets take turns without copies.
   for (int s = 0; s < nsteps; s += 2) {
-    const int kb = kbeg + s * KSTEP;
-    const bool more1 = s + 1 < nsteps;
-    if (more1) {
-      aload(kb + KSTEP, ar1);
-      xload(kb + KSTEP, xr);
-    }
+    if (s + 1 < nsteps) load(s + 1, ar1, br1);
     __builtin_amdgcn_sched_barrier(0);
-    compute(0, ar0, kb);
-    if (more1) xstore(1, xr);
-    __syncthreads();
-    if (more1) {
-      const int kb1 = kb + KSTEP;
-      const bool more2 = s + 2 < nsteps;
-      if (more2) {
-        aload(kb1 + KSTEP, ar0);
-        xload(kb1 + KSTEP, xr);
-      }
+    compute(s, ar0, br0);
+    if (s + 1 < nsteps) {
+      if (s + 2 < nsteps) load(s + 2, ar0, br0);
       __builtin_amdgcn_sched_barrier(0);
-      compute(1, ar1, kb1);
-      if (more2) xstore(0, xr);
-      __syncthreads();
+      compute(s + 1, ar1, br1);
     }
   }
 
   T *__restrict__ P = static_cast<T *>(a.part) + (size_t)ks * a.g.rows_pad * 32;
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
+  for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = rt * kWideRows + wave * 32 + mt * 16 + (sizeof(T) == 8 ? q + 4 * r : 4 * q + r);
+        const int row = rt * ROWS + wave * 16 * MT + mt * 16 + (sizeof(T) == 8 ? q + 4 * r : 4 * q + r);
         P[(size_t)row * 32 + nt * 16 + m] = acc[mt][nt][r];
       }
   if (want_ssq) {
     ssq = block_sum(ssq, s_scr);
-    if (tid == 0) a.sumsq[(size_t)ks * gridDim.x + rt] = ssq;
+    if (tid == 0) a.sumsq[(size_t)ks * a.g.row_tiles + rt] = ssq;
   }
+}
+
+// Xs: X in the product kernel's B-operand order.  Element (step, nt, l, j),
+// j = u V + v, at ((step NT + nt) 64 + l) KU V + j holds X[k][c] with
+// k = step KSTEP + (u 4 + l / 16) V + v and c = 16 nt + l % 16 (zero past nd
+// or d).  One thread per element.
+template <typename T, int NT, int MT>
+__global__ void __launch_bounds__(256) wide_xs_kernel(const T *__restrict__ X, int nd, int d, int steps,
+                                                      T *__restrict__ Xs, const int *stop_flag) {
+  constexpr int V = WideT<T>::V;
+  constexpr int KU = wide_ku<MT>();
+  constexpr int KSTEP = wide_kstep<T, KU>();
+  constexpr int PER = KU * V;
+  if (stop_flag) {
+    if (__atomic_load_n(stop_flag, __ATOMIC_RELAXED)) return;   // uniform
+  }
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)steps * NT * 64 * PER;
+  if (e >= total) return;
+  const int j = (int)(e % PER);
+  const int l = (int)((e / PER) % 64);
+  const int nt = (int)((e / (PER * 64)) % NT);
+  const int step = (int)(e / ((int64_t)PER * 64 * NT));
+  const int u = j / V, v = j % V;
+  const int k = step * KSTEP + (u * 4 + l / 16) * V + v;
+  const int c = 16 * nt + l % 16;
+  const int kk = k < nd ? k : nd - 1, cc = c < d ? c : d - 1;
+  const T x = X[(int64_t)kk * d + cc];
+  Xs[e] = (k < nd && c < d) ? x : T(0);
 }
 
 // ---------------------------------------------------------------------------
 // d x d helpers in FP64 on LDS, for every thread of a workgroup.
 // ---------------------------------------------------------------------------
-// out = op(A) op(B), op = transpose when tA / tB; ends with a barrier.
-__device__ inline void wmm(double *out, const double *A, bool tA, const double *B, bool tB, int d) {
+// out = op(A) op(B), op = transpose when TA / TB; ends with a barrier.
+template <bool TA, bool TB>
+__device__ inline void wmm(double *out, const double *A, const double *B, int d) {
   const int dd = d * d;
   for (int e = threadIdx.x; e < dd; e += blockDim.x) {
     const int r = e / d, k = e % d;
-    double s = 0.0;
-    for (int m = 0; m < d; ++m) s += (tA ? A[m * d + r] : A[r * d + m]) * (tB ? B[k * d + m] : B[m * d + k]);
-    out[e] = s;
+    double s0 = 0.0, s1 = 0.0;
+    int m = 0;
+    for (; m + 1 < d; m += 2) {
+      s0 += (TA ? A[m * d + r] : A[r * d + m]) * (TB ? B[k * d + m] : B[m * d + k]);
+      s1 += (TA ? A[(m + 1) * d + r] : A[r * d + m + 1]) * (TB ? B[k * d + m + 1] : B[(m + 1) * d + k]);
+    }
+    if (m < d) s0 += (TA ? A[m * d + r] : A[r * d + m]) * (TB ? B[k * d + m] : B[m * d + k]);
+    out[e] = s0 + s1;
   }
   __syncthreads();
+}
+
+// Sums of N values per thread over the workgroup in one pass (two barriers);
+// every thread receives the N totals.  scr holds N * kMaxWaves doubles.
+template <int N>
+__device__ inline void block_sum_n(double (&v)[N], double *scr) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] = wave_sum(v[j]);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int j = 0; j < N; ++j) scr[j * kMaxWaves + wave] = v[j];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += scr[j * kMaxWaves + w];
+    v[j] = t;
+  }
 }
 
 // ||I - M||_F of a d x d matrix in LDS (a block reduction).
@@ -247,7 +298,7 @@ __device__ inline double wdefect(const double *M, int d, double *scr) {
 // not finite (no convergence within 200 steps).
 __device__ inline int wide_polar(double *S, double *M, double *N, int d, double *scr) {
   const int dd = d * d;
-  wmm(M, S, true, S, false, d);
+  wmm<true, false>(M, S, S, d);
   double g = 0.0;
   for (int r = threadIdx.x; r < d; r += blockDim.x) {
     double s = 0.0;
@@ -262,12 +313,12 @@ __device__ inline int wide_polar(double *S, double *M, double *N, int d, double 
   const double stop = 64.0 * d * 2.220446049250313e-16;
   int extra = -1;
   for (int it = 0; it < 200; ++it) {
-    wmm(M, S, true, S, false, d);
+    wmm<true, false>(M, S, S, d);
     const double def = wdefect(M, d, scr);
     if (!isfinite(def)) return -1;
     if (extra < 0 && def <= stop) extra = 2;
     if (extra == 0) return it;
-    wmm(N, S, false, M, false, d);
+    wmm<false, false>(N, S, M, d);
     for (int e = threadIdx.x; e < dd; e += blockDim.x) S[e] = 1.5 * S[e] - 0.5 * N[e];
     __syncthreads();
     if (extra > 0) --extra;
@@ -286,6 +337,7 @@ __global__ void __launch_bounds__(256) wide_epilogue_kernel(WideArgs a) {
   constexpr int NE = kWideMaxD * kWideMaxD;
   __shared__ double sm[7][NE];
   __shared__ double s_scr[kMaxWaves];
+  __shared__ double s_scr7[7 * kMaxWaves];
   if (a.stop_flag) {
     if (__atomic_load_n(a.stop_flag, __ATOMIC_RELAXED)) return;   // uniform
   }
@@ -308,8 +360,8 @@ __global__ void __launch_bounds__(256) wide_epilogue_kernel(WideArgs a) {
   if (a.mode == WIDE_INIT) {
     T *__restrict__ W = static_cast<T *>(a.X_out);
     for (int e = tid; e < dd; e += blockDim.x) W[((int64_t)i * d + e / d) * d + e % d] = (T)C[e];
-    wmm(G, X, true, C, false, d);       // Y_i^T W_i
-    wmm(Tm, C, true, C, false, d);      // W_i^T W_i
+    wmm<true, false>(G, X, C, d);       // Y_i^T W_i
+    wmm<true, false>(Tm, C, C, d);      // W_i^T W_i
     double *out = a.igram + (size_t)i * 2 * dd;
     for (int e = tid; e < dd; e += blockDim.x) {
       out[e] = G[e];
@@ -318,70 +370,74 @@ __global__ void __launch_bounds__(256) wide_epilogue_kernel(WideArgs a) {
     return;
   }
 
-  wmm(G, Ad, false, X, false, d);       // A_ii X_i
-  wmm(Tm, X, true, X, false, d);        // H_i = X_i^T X_i
-  double xc = 0.0, hh = 0.0, aii2 = 0.0, x2 = 0.0;
+  // Per-thread partial sums, reduced once at the end: ||X_i||^2 and the
+  // objective pieces tr(X_i^T C_i) (C_i without the diagonal block),
+  // ||X_i^T X_i||^2 and ||A_ii||^2 (the latter three only when F is evaluated).
+  double red[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // x2 xc hh aii2 dx2 nonfin def2
+  const bool need_diag = a.method != WIDE_GPM || a.objective;
+  if (need_diag) wmm<false, false>(G, Ad, X, d);          // A_ii X_i
+  if (a.objective) wmm<true, false>(Tm, X, X, d);         // X_i^T X_i
   for (int e = tid; e < dd; e += blockDim.x) {
-    xc += X[e] * (C[e] - G[e]);         // tr(X_i^T C_i), C_i without the diagonal block
-    hh += Tm[e] * Tm[e];
-    aii2 += Ad[e] * Ad[e];
-    x2 += X[e] * X[e];
+    red[0] += X[e] * X[e];
+    if (a.objective) {
+      red[1] += X[e] * (C[e] - G[e]);
+      red[2] += Tm[e] * Tm[e];
+      red[3] += Ad[e] * Ad[e];
+    }
   }
-  xc = block_sum(xc, s_scr);
-  hh = block_sum(hh, s_scr);
-  aii2 = block_sum(aii2, s_scr);
-  x2 = block_sum(x2, s_scr);
 
   double *S = F;         // the iterate being retracted
-  double dmax = 0.0;
   int polar_steps = 0;
   if (a.method == WIDE_GPM) {
     for (int e = tid; e < dd; e += blockDim.x) S[e] = C[e];        // (A X)_i, diagonal block included
     __syncthreads();
     polar_steps = wide_polar(S, M, Tm, d, s_scr);
-    wmm(M, S, true, S, false, d);
-    dmax = wdefect(M, d, s_scr);
+    wmm<true, false>(M, S, S, d);
   } else {
     const double nm1 = (double)(a.n - 1), mu = a.mu;
     for (int e = tid; e < dd; e += blockDim.x) G[e] = nm1 * X[e] - (C[e] - G[e]);   // G_i
     __syncthreads();
-    wmm(Tm, G, true, X, false, d);       // G_i^T X_i
-    wmm(M, X, false, Tm, false, d);      // X_i G_i^T X_i
+    wmm<true, false>(Tm, G, X, d);       // G_i^T X_i
+    wmm<false, false>(M, X, Tm, d);      // X_i G_i^T X_i
     for (int e = tid; e < dd; e += blockDim.x) F[e] = X[e] - mu * 0.5 * (G[e] - M[e]);
     __syncthreads();
-    wmm(M, F, true, F, false, d);
-    dmax = wdefect(M, d, s_scr);         // ||I - F_i^T F_i||_F
-    if (a.method == WIDE_POLAR) {
-      polar_steps = wide_polar(S, M, Tm, d, s_scr);
-    } else {
-      double *cur = F, *nxt = G;
-      for (int st = 0; st < a.ns_steps; ++st) {
-        wmm(M, cur, true, cur, false, d);
-        wmm(Tm, cur, false, M, false, d);
-        for (int e = tid; e < dd; e += blockDim.x) nxt[e] = 1.5 * cur[e] - 0.5 * Tm[e];
-        __syncthreads();
-        double *t = cur;
-        cur = nxt;
-        nxt = t;
-      }
-      S = cur;
+    wmm<true, false>(M, F, F, d);        // F_i^T F_i (also the first Newton-Schulz M)
+  }
+  // ||I - F_i^T F_i|| (for GPM: of the new iterate), summed with the rest
+  for (int e = tid; e < dd; e += blockDim.x) {
+    const double v = ((e / d) == (e % d) ? 1.0 : 0.0) - M[e];
+    red[6] += v * v;
+  }
+  if (a.method == WIDE_POLAR) {
+    __syncthreads();                     // M is rewritten by the polar iteration
+    polar_steps = wide_polar(S, M, Tm, d, s_scr);
+  } else if (a.method == WIDE_NS) {
+    double *cur = F, *nxt = G;
+    for (int st = 0; st < a.ns_steps; ++st) {
+      if (st > 0) wmm<true, false>(M, cur, cur, d);
+      wmm<false, false>(Tm, cur, M, d);
+      for (int e = tid; e < dd; e += blockDim.x) nxt[e] = 1.5 * cur[e] - 0.5 * Tm[e];
+      __syncthreads();
+      double *t = cur;
+      cur = nxt;
+      nxt = t;
     }
+    S = cur;
   }
   T *__restrict__ Xo = static_cast<T *>(a.X_out);
-  double dx2 = 0.0;
-  int nonfin = 0;
   for (int e = tid; e < dd; e += blockDim.x) {
     const T v = (T)S[e];
     Xo[((int64_t)i * d + e / d) * d + e % d] = v;
     const double dv = (double)v - X[e];
-    dx2 += dv * dv;
-    nonfin |= !isfinite(v);
+    red[4] += dv * dv;
+    red[5] += isfinite(v) ? 0.0 : 1.0;
   }
-  dx2 = block_sum(dx2, s_scr);
-  const double nf = block_max((double)nonfin, s_scr);
-  if (tid == 0)
-    a.stats[i] = WideStat{dx2, x2, dmax, (nf != 0.0 || !isfinite(dmax)) ? 1.0 : 0.0, xc, hh, aii2,
-                          polar_steps < 0 ? 1.0 : 0.0};
+  block_sum_n<7>(red, s_scr7);
+  if (tid == 0) {
+    const double dmax = sqrt(red[6]);
+    a.stats[i] = WideStat{red[4], red[0], dmax, (red[5] != 0.0 || !isfinite(dmax)) ? 1.0 : 0.0, red[1], red[2],
+                          red[3], polar_steps < 0 ? 1.0 : 0.0};
+  }
 }
 
 // Partial X^T X over a slice of rows: workgroup g sums rows
@@ -437,30 +493,28 @@ __global__ void __launch_bounds__(256) wide_gram_kernel(const T *__restrict__ X,
 // stops with X^t (this step's input) as the result.
 __global__ void __launch_bounds__(256) wide_finish_kernel(WideArgs a) {
   __shared__ double s_scr[kMaxWaves];
+  __shared__ double s_scr7[7 * kMaxWaves];
   if (a.stop_flag) {
     if (__atomic_load_n(a.stop_flag, __ATOMIC_RELAXED)) return;   // uniform
   }
   const int tid = threadIdx.x, d = a.d, dd = d * d;
-  double dx2 = 0, x2 = 0, dmax = 0, nf = 0, xc = 0, hh = 0, aii2 = 0, pb = 0;
+  // sums in a fixed order; the non-finite and polar-failure flags are 0 / 1
+  // per block, so their sums are counts
+  double v[7] = {0, 0, 0, 0, 0, 0, 0}, dmax = 0;
   for (int p = tid; p < a.n; p += blockDim.x) {
     const WideStat s = a.stats[p];
-    dx2 += s.dx2;
-    x2 += s.x2;
+    v[0] += s.dx2;
+    v[1] += s.x2;
+    v[2] += s.xc;
+    v[3] += s.hh;
+    v[4] += s.aii2;
+    v[5] += s.nonfinite;
+    v[6] += s.polar_bad;
     dmax = s.dmax > dmax ? s.dmax : dmax;
-    nf = s.nonfinite > nf ? s.nonfinite : nf;
-    xc += s.xc;
-    hh += s.hh;
-    aii2 += s.aii2;
-    pb = s.polar_bad > pb ? s.polar_bad : pb;
   }
-  dx2 = block_sum(dx2, s_scr);
-  x2 = block_sum(x2, s_scr);
+  block_sum_n<7>(v, s_scr7);
   dmax = block_max(dmax, s_scr);
-  nf = block_max(nf, s_scr);
-  xc = block_sum(xc, s_scr);
-  hh = block_sum(hh, s_scr);
-  aii2 = block_sum(aii2, s_scr);
-  pb = block_max(pb, s_scr);
+  const double dx2 = v[0], x2 = v[1], xc = v[2], hh = v[3], aii2 = v[4], nf = v[5], pb = v[6];
   double Fx = 0.0;
   if (a.objective) {
     double ss = 0.0;
@@ -724,16 +778,31 @@ WideGeom wide_geom(int n, int d, int fmt) {
   WideGeom g{};
   const int nd = n * d;
   g.nt = d <= 16 ? 1 : 2;
-  g.kstep = fmt == NSRGS_A_F64 ? wide_kstep<double>() : wide_kstep<float>();
-  g.row_tiles = (nd + kWideRows - 1) / kWideRows;
-  g.rows_pad = g.row_tiles * kWideRows;
-  // About 1024 workgroups (four per CU), at most 32 column chunks.
-  int ks = (1024 + g.row_tiles - 1) / g.row_tiles;
-  ks = ks < 1 ? 1 : ks > 32 ? 32 : ks;
+  g.mt = env_int("NSRGS_WIDE_MT", 4) == 2 ? 2 : 4;
+  g.ku = 8 / g.mt;
+  g.xcd_remap = env_int("NSRGS_WIDE_XCD", 1) != 0;
+  const int V = fmt == NSRGS_A_F64 ? 2 : 4;
+  g.kstep = 4 * g.ku * V;
+  g.rows = 64 * g.mt;
+  g.row_tiles = (nd + g.rows - 1) / g.rows;
+  g.rows_pad = g.row_tiles * g.rows;
+  // Column chunks so that the grid fills the CUs once (256 workgroups of
+  // 64 mt rows) without a part-empty last round; at most 32.  Measured at
+  // n = 500, d = 25: one workgroup of 256 rows per CU beats 512 or 1024
+  // workgroups of 128 or 256 rows (357 / 370 / 392 us per FP64 iteration).
+  g.ks_max = 2048 / ((nd + 127) / 128);   // the same bound for either tile height
+  g.ks_max = g.ks_max < 1 ? 1 : g.ks_max > 32 ? 32 : g.ks_max;   // sizes the workspace
+  int slots = env_int("NSRGS_WIDE_SLOTS", 256);
+  slots = slots < 1 ? 1 : slots > 2048 ? 2048 : slots;
+  int ks = slots / g.row_tiles;
+  ks = ks < 1 ? 1 : ks > g.ks_max ? g.ks_max : ks;
+  const int forced = env_int("NSRGS_WIDE_KS", 0);
+  if (forced >= 1) ks = forced < g.ks_max ? forced : g.ks_max;
   const int steps = (nd + g.kstep - 1) / g.kstep;
   const int steps_per = (steps + ks - 1) / ks;
   g.kchunk = steps_per * g.kstep;
   g.ks = (nd + g.kchunk - 1) / g.kchunk;
+  g.steps = steps;
   return g;
 }
 
@@ -746,19 +815,35 @@ WideLayout wide_layout(int n, int d, int fmt) {
   size_t off = 0;
   L.ctl = off;   off += a256(sizeof(WideCtl));
   L.stats = off; off += a256((size_t)n * sizeof(WideStat));
-  L.part = off;  off += a256((size_t)g.ks * g.rows_pad * 32 * tb);
+  // sized for every tile height and step width (rows_pad and steps * kstep
+  // are below n d + 256)
+  const size_t nd_pad = (size_t)n * d + 256;
+  L.part = off;  off += a256((size_t)g.ks_max * nd_pad * 32 * tb);
+  L.xs = off;    off += a256(nd_pad * 32 * tb);                             // B operands, 2 tiles
   L.gram = off;  off += a256((size_t)kWideGramGroups * d * d * sizeof(double));
-  L.sumsq = off; off += a256((size_t)g.row_tiles * g.ks * sizeof(double));
+  L.sumsq = off; off += a256((size_t)((n * d + 63) / 64) * g.ks_max * sizeof(double));
   L.igram = off; off += a256((size_t)n * 2 * d * d * sizeof(double));
   L.total = off;
   return L;
 }
 
+template <typename T, int NT, int MT>
+static void wide_launch_product_t(const WideArgs &a, hipStream_t s) {
+  const int64_t xs_elems = (int64_t)a.g.steps * NT * 64 * (a.g.kstep / 4);
+  const int total = a.g.row_tiles * a.g.ks;
+  const int wgs = a.g.xcd_remap ? 8 * ((total + 7) / 8) : total;
+  hipLaunchKernelGGL((wide_xs_kernel<T, NT, MT>), dim3((unsigned)((xs_elems + 255) / 256)), dim3(256), 0, s,
+                     static_cast<const T *>(a.X_in), a.nd, a.d, a.g.steps, static_cast<T *>(a.xs), a.stop_flag);
+  hipLaunchKernelGGL((wide_product_kernel<T, NT, MT>), dim3(wgs), dim3(256), 0, s, a);
+}
+
 template <typename T>
 static hipError_t wide_launch_product(const WideArgs &a, hipStream_t s) {
-  const dim3 grid(a.g.row_tiles, a.g.ks), block(256);
-  if (a.g.nt == 1) hipLaunchKernelGGL((wide_product_kernel<T, 1>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((wide_product_kernel<T, 2>), grid, block, 0, s, a);
+  if (a.g.nt == 1) {
+    if (a.g.mt == 2) wide_launch_product_t<T, 1, 2>(a, s); else wide_launch_product_t<T, 1, 4>(a, s);
+  } else {
+    if (a.g.mt == 2) wide_launch_product_t<T, 2, 2>(a, s); else wide_launch_product_t<T, 2, 4>(a, s);
+  }
   return hipGetLastError();
 }
 
