@@ -513,8 +513,10 @@ static int wide_init_impl(const nsrgs_matrix *A, int n, int d, void *X0, int max
   a.mode = WIDE_INIT;
   a.X_out = W;
   a.stop_flag = &ctl->init_done;
-  const int groups = (nd + 255) / 256;
-  double *apply_part = reinterpret_cast<double *>(base + L.stats);   // 2 doubles per 256 rows
+  const int groups = (int)(((int64_t)nd * d + 255) / 256);
+  // 2 doubles per 256 entries; the per-block Grams are consumed (reduced)
+  // before the apply kernel runs, so their area holds the apply partials
+  double *apply_part = a.igram;
   DevCtl host{};
   int k = 0;
   const int chunk = 4;

@@ -233,7 +233,7 @@ static void finish(Server &S, const std::shared_ptr<Request> &q, int status) {
 }
 
 // Generate A on the device (row chunks), then the spectral initialization.
-static int ingest_one(Server &S, Request &q, hipStream_t s) {
+static int ingest_steps(Server &S, Request &q, hipStream_t s) {
   const int n = q.r.n, d = q.r.d, nd = n * d;
   NSRGS_HIP(hipMemcpyAsync(q.zdev, q.Z.data(), q.z_bytes, hipMemcpyHostToDevice, s), "Z upload");
   if (S.o.fmt == NSRGS_A_F32) {
@@ -252,6 +252,15 @@ static int ingest_one(Server &S, Request &q, hipStream_t s) {
   if (st != NSRGS_OK && st != NSRGS_ERR_NOT_CONVERGED) return st;
   NSRGS_HIP(hipStreamSynchronize(s), "ingest sync");
   return NSRGS_OK;
+}
+
+// ingest_steps, and on any error a wait for the stream before returning: the
+// caller then releases the request's buffers to the pool, and no kernel or
+// copy enqueued above may still be writing them.
+static int ingest_one(Server &S, Request &q, hipStream_t s) {
+  const int st = ingest_steps(S, q, s);
+  if (st != NSRGS_OK) (void)hipStreamSynchronize(s);
+  return st;
 }
 
 static void ingest_loop(Server *S, int worker) {

@@ -575,49 +575,86 @@ __global__ void __launch_bounds__(256) wide_finish_kernel(WideArgs a) {
 // Spectral initialization for d up to 32 (the same subspace iteration as the
 // narrow path: W = A Y, Cholesky-QR of W in FP64, Rayleigh-Ritz values).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) wide_gram_finish_kernel(const double *igram, int n, int d,
-                                                                DevCtl *ctl, WideCtl *w) {
+// Sum of the n per-block Grams (2 d^2 entries each) in FP64: workgroup g
+// owns entries [64 g, 64 g + 64) (lane = entry, so every load is 512
+// contiguous bytes); its four waves take every fourth block, then add their
+// partial sums in wave order.
+__global__ void __launch_bounds__(256) wide_igram_reduce_kernel(const double *igram, int n, int d,
+                                                                double *sum, const DevCtl *ctl) {
+  __shared__ double part[4][64];
+  if (__atomic_load_n(&ctl->init_done, __ATOMIC_RELAXED)) return;   // uniform
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, ne = 2 * d * d;
+  const int e = blockIdx.x * 64 + lane;
+  const int ec = e < ne ? e : ne - 1;
+  double s0 = 0.0, s1 = 0.0;
+  int i = wave;
+  for (; i + 4 < n; i += 8) {
+    s0 += igram[(size_t)i * ne + ec];
+    s1 += igram[(size_t)(i + 4) * ne + ec];
+  }
+  if (i < n) s0 += igram[(size_t)i * ne + ec];
+  part[wave][lane] = s0 + s1;
+  __syncthreads();
+  if (wave == 0 && e < ne) sum[e] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+}
+
+// Rayleigh quotient T = sym(Y^T W) and the inverse Cholesky factor of W^T W
+// (FP64) from the reduced Grams.
+__global__ void __launch_bounds__(64) wide_gram_finish_kernel(const double *gsum, int d, DevCtl *ctl, WideCtl *w) {
   constexpr int NE = kWideMaxD * kWideMaxD;
   __shared__ double G1[NE], G2[NE], Rm[NE];
   if (__atomic_load_n(&ctl->init_done, __ATOMIC_RELAXED)) return;   // uniform
   const int dd = d * d, tid = threadIdx.x;
   for (int e = tid; e < 2 * dd; e += blockDim.x) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += igram[(size_t)i * 2 * dd + e];
+    const double s = gsum[e];
     if (e < dd) G1[e] = s; else G2[e - dd] = s;
   }
   __syncthreads();
-  if (tid == 0) {
-    int bad = 0;
-    for (int r = 0; r < d; ++r)
-      for (int k = 0; k < d; ++k) w->T[r * d + k] = 0.5 * (G1[r * d + k] + G1[k * d + r]);
-    for (int j = 0; j < dd; ++j) Rm[j] = 0.0;
-    for (int j = 0; j < d; ++j) {
+  for (int e = tid; e < dd; e += blockDim.x) {
+    const int r = e / d, k = e % d;
+    w->T[e] = 0.5 * (G1[r * d + k] + G1[k * d + r]);
+    Rm[e] = 0.0;
+  }
+  __syncthreads();
+  // Cholesky W^T W = R^T R, one row of R per step: the pivot by one lane,
+  // the rest of the row by lane k (one wave, so the barriers are cheap)
+  __shared__ int s_bad;
+  if (tid == 0) s_bad = 0;
+  for (int j = 0; j < d; ++j) {
+    if (tid == 0) {
       double s = G2[j * d + j];
       for (int q = 0; q < j; ++q) s -= Rm[q * d + j] * Rm[q * d + j];
-      if (!(s > 0.0) || !isfinite(s)) { bad = 1; s = 1.0; }
-      const double rjj = sqrt(s);
-      Rm[j * d + j] = rjj;
-      for (int k = j + 1; k < d; ++k) {
-        double t = G2[j * d + k];
-        for (int q = 0; q < j; ++q) t -= Rm[q * d + j] * Rm[q * d + k];
-        Rm[j * d + k] = t / rjj;
-      }
+      if (!(s > 0.0) || !isfinite(s)) { s_bad = 1; s = 1.0; }
+      Rm[j * d + j] = sqrt(s);
     }
-    for (int j = 0; j < dd; ++j) w->Rinv[j] = 0.0;
-    for (int k = 0; k < d; ++k) {
-      w->Rinv[k * d + k] = 1.0 / Rm[k * d + k];
-      for (int r = k - 1; r >= 0; --r) {
-        double s = 0.0;
-        for (int q = r + 1; q <= k; ++q) s += Rm[r * d + q] * w->Rinv[q * d + k];
-        w->Rinv[r * d + k] = -s / Rm[r * d + r];
-      }
+    __syncthreads();
+    const int k = tid;
+    if (k > j && k < d) {
+      double t = G2[j * d + k];
+      for (int q = 0; q < j; ++q) t -= Rm[q * d + j] * Rm[q * d + k];
+      Rm[j * d + k] = t / Rm[j * d + j];
     }
-    if (bad) ctl->init_bad = 1;
+    __syncthreads();
   }
+  // R^{-1}: lane k solves column k by back substitution (in G1, free now)
+  double *Ri = G1;
+  for (int e = tid; e < dd; e += blockDim.x) Ri[e] = 0.0;
+  __syncthreads();
+  if (tid < d) {
+    const int k = tid;
+    Ri[k * d + k] = 1.0 / Rm[k * d + k];
+    for (int r = k - 1; r >= 0; --r) {
+      double s = 0.0;
+      for (int q = r + 1; q <= k; ++q) s += Rm[r * d + q] * Ri[q * d + k];
+      Ri[r * d + k] = -s / Rm[r * d + r];
+    }
+  }
+  if (tid == 0 && s_bad) ctl->init_bad = 1;
+  __syncthreads();
+  for (int e = tid; e < dd; e += blockDim.x) w->Rinv[e] = G1[e];
 }
 
-// One thread per row: Y_next = W R^{-1}, residual rows W - Y T.
+// One thread per entry (row, k): Y_next = W R^{-1}, residual W - Y T.
 template <typename T>
 __global__ void __launch_bounds__(256) wide_init_apply_kernel(const T *W, const T *Y, T *Yn, int nd, int d,
                                                               double *part, int num_groups, DevCtl *ctl,
@@ -625,7 +662,6 @@ __global__ void __launch_bounds__(256) wide_init_apply_kernel(const T *W, const 
   constexpr int NE = kWideMaxD * kWideMaxD;
   __shared__ double sR[NE], sT[NE];
   __shared__ double s_scr[kMaxWaves];
-  __shared__ int s_last;
   if (__atomic_load_n(&ctl->init_done, __ATOMIC_RELAXED)) return;   // uniform
   const int tid = threadIdx.x, dd = d * d;
   for (int e = tid; e < dd; e += blockDim.x) {
@@ -633,64 +669,53 @@ __global__ void __launch_bounds__(256) wide_init_apply_kernel(const T *W, const 
     sT[e] = w->T[e];
   }
   __syncthreads();
-  const int row = blockIdx.x * blockDim.x + tid;
-  const int rowc = row < nd ? row : nd - 1;
-  double wr[kWideMaxD], yr[kWideMaxD];
-#pragma unroll
-  for (int m = 0; m < kWideMaxD; ++m) {
-    const int mc = m < d ? m : d - 1;
-    const double wv = (double)W[(int64_t)rowc * d + mc], yv = (double)Y[(int64_t)rowc * d + mc];
-    wr[m] = m < d ? wv : 0.0;
-    yr[m] = m < d ? yv : 0.0;
+  const int64_t ent = (int64_t)blockIdx.x * blockDim.x + tid;
+  const bool ok = ent < (int64_t)nd * d;
+  const int64_t entc = ok ? ent : 0;
+  const int64_t row = entc / d;
+  const int k = (int)(entc % d);
+  double s = 0.0, t = 0.0;
+  for (int m = 0; m < d; ++m) {
+    s += (double)W[row * d + m] * sR[m * d + k];
+    t += (double)Y[row * d + m] * sT[m * d + k];
   }
-  double res2 = 0.0;
-  int bad = 0;
-  for (int k = 0; k < d; ++k) {
-    double s = 0.0, t = 0.0;
-#pragma unroll
-    for (int m = 0; m < kWideMaxD; ++m) {
-      const int mm = m < d ? m : 0;
-      s += wr[m] * sR[mm * d + k];
-      t += yr[m] * sT[mm * d + k];
-    }
-    double out = 0.0, r = 0.0;
-#pragma unroll
-    for (int m = 0; m < kWideMaxD; ++m) r = (m == k) ? wr[m] : r;
-    r -= t;
-    out = s;
-    if (row < nd) Yn[(int64_t)row * d + k] = (T)out;
-    res2 += row < nd ? r * r : 0.0;
-    bad |= (row < nd) && !isfinite(s);
-  }
+  if (ok) Yn[ent] = (T)s;
+  const double r = (double)W[entc] - t;
+  double res2 = ok ? r * r : 0.0;
+  const int bad = ok && !isfinite(s);
   res2 = block_sum(res2, s_scr);
   const double fbad = block_max((double)bad, s_scr);
   if (tid == 0) {
     part[2 * blockIdx.x] = res2;
     part[2 * blockIdx.x + 1] = fbad;
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  if (tid == 0) s_last = (atomicAdd(&ctl->arrive2, 1u) == (unsigned)num_groups - 1u);
-  __syncthreads();
-  if (s_last) {
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    double s = 0.0, b = 0.0;
+}
+
+// After the apply kernel (one workgroup; the kernel boundary orders the
+// partials): the relative residual ||W - Y T||_F / ||T||_F and the stop test.
+__global__ void __launch_bounds__(256) wide_init_check_kernel(const double *part, int num_groups, int d,
+                                                              DevCtl *ctl, const WideCtl *w, int iter, double tol) {
+  __shared__ double s_scr[kMaxWaves];
+  if (__atomic_load_n(&ctl->init_done, __ATOMIC_RELAXED)) return;   // uniform
+  const int tid = threadIdx.x, dd = d * d;
+  {
+    double sum = 0.0, b = 0.0;
     for (int g = tid; g < num_groups; g += blockDim.x) {
-      s += part[2 * g];
+      sum += part[2 * g];
       b = part[2 * g + 1] > b ? part[2 * g + 1] : b;
     }
-    s = block_sum(s, s_scr);
+    double tn = 0.0;
+    for (int e = tid; e < dd; e += blockDim.x) tn += w->T[e] * w->T[e];
+    sum = block_sum(sum, s_scr);
     b = block_max(b, s_scr);
+    tn = block_sum(tn, s_scr);
     if (tid == 0) {
-      double tn = 0.0;
-      for (int e = 0; e < dd; ++e) tn += w->T[e] * w->T[e];
-      const double rel = tn > 0.0 ? sqrt(s / tn) : 0.0;
+      const double rel = tn > 0.0 ? sqrt(sum / tn) : 0.0;
       ctl->init_res = rel;
       ctl->init_iters = iter + 1;
       if (b != 0.0 || !isfinite(rel)) ctl->init_bad = 1;
       if (iter >= 1 && rel <= tol) ctl->init_done = 1;   // the first basis is random
       if (ctl->init_bad) ctl->init_done = 1;
-      ctl->arrive2 = 0u;
     }
   }
 }
@@ -712,50 +737,61 @@ __global__ void __launch_bounds__(256) wide_init_polar_kernel(const T *Y, T *X0,
   }
 }
 
-// Ritz values: eigenvalues of T (FP64 cyclic Jacobi), descending.
-__global__ void wide_init_finish_kernel(DevCtl *ctl, WideCtl *w, int d) {
+// Ritz values: eigenvalues of T (FP64 cyclic Jacobi), descending.  One wave:
+// every lane computes the same rotation, lane k updates entry k of the two
+// rows, then of the two columns.
+__global__ void __launch_bounds__(64) wide_init_finish_kernel(DevCtl *ctl, WideCtl *w, int d) {
   constexpr int NE = kWideMaxD * kWideMaxD;
   __shared__ double M[NE];
-  if (threadIdx.x != 0) return;
-  for (int e = 0; e < d * d; ++e) M[e] = w->T[e];
+  __shared__ double s_scr[kMaxWaves];
+  const int k = threadIdx.x;
+  for (int e = k; e < d * d; e += blockDim.x) M[e] = w->T[e];
+  __syncthreads();
   for (int sweep = 0; sweep < 60; ++sweep) {
     double off = 0.0, tot = 0.0;
-    for (int p = 0; p < d; ++p)
-      for (int q = 0; q < d; ++q) {
-        tot += M[p * d + q] * M[p * d + q];
-        if (p != q) off += M[p * d + q] * M[p * d + q];
-      }
+    for (int e = k; e < d * d; e += blockDim.x) {
+      const double v = M[e] * M[e];
+      tot += v;
+      if (e / d != e % d) off += v;
+    }
+    off = block_sum(off, s_scr);
+    tot = block_sum(tot, s_scr);
     if (off <= 1e-30 * tot) break;
     for (int p = 0; p < d - 1; ++p)
       for (int q = p + 1; q < d; ++q) {
         const double apq = M[p * d + q];
-        if (apq == 0.0) continue;
+        if (apq == 0.0) continue;                       // uniform: every lane reads the same value
         const double theta = (M[q * d + q] - M[p * d + p]) / (2.0 * apq);
         const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-        for (int k = 0; k < d; ++k) {
+        const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+        __syncthreads();
+        if (k < d) {                                    // rotate rows p, q
           const double mp = M[p * d + k], mq = M[q * d + k];
-          M[p * d + k] = c * mp - s * mq;
-          M[q * d + k] = s * mp + c * mq;
+          M[p * d + k] = c * mp - sn * mq;
+          M[q * d + k] = sn * mp + c * mq;
         }
-        for (int k = 0; k < d; ++k) {
+        __syncthreads();
+        if (k < d) {                                    // rotate columns p, q
           const double mp = M[k * d + p], mq = M[k * d + q];
-          M[k * d + p] = c * mp - s * mq;
-          M[k * d + q] = s * mp + c * mq;
+          M[k * d + p] = c * mp - sn * mq;
+          M[k * d + q] = sn * mp + c * mq;
         }
+        __syncthreads();
       }
   }
-  double wv[kWideMaxD];
-  for (int i = 0; i < d; ++i) wv[i] = M[i * d + i];
-  for (int i = 0; i < d; ++i)
-    for (int j = i + 1; j < d; ++j)
-      if (wv[j] > wv[i]) {
-        const double t = wv[i];
-        wv[i] = wv[j];
-        wv[j] = t;
-      }
-  for (int i = 0; i < d; ++i) w->ritz[i] = wv[i];
-  for (int i = 0; i < d && i < kMaxD; ++i) ctl->ritz[i] = wv[i];
+  if (k == 0) {
+    double wv[kWideMaxD];
+    for (int i = 0; i < d; ++i) wv[i] = M[i * d + i];
+    for (int i = 0; i < d; ++i)
+      for (int j = i + 1; j < d; ++j)
+        if (wv[j] > wv[i]) {
+          const double t = wv[i];
+          wv[i] = wv[j];
+          wv[j] = t;
+        }
+    for (int i = 0; i < d; ++i) w->ritz[i] = wv[i];
+    for (int i = 0; i < d && i < kMaxD; ++i) ctl->ritz[i] = wv[i];
+  }
 }
 
 __global__ void wide_ctl_reset_kernel(WideCtl *w) {
@@ -874,7 +910,11 @@ static hipError_t wide_init_product_t(const WideArgs &a, hipStream_t s) {
   if ((e = wide_launch_product<T>(a, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(wide_epilogue_kernel<T>, dim3(a.n), dim3(256), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(wide_gram_finish_kernel, dim3(1), dim3(1024), 0, s, a.igram, a.n, a.d, a.ctl, a.wctl);
+  const int ne = 2 * a.d * a.d;
+  hipLaunchKernelGGL(wide_igram_reduce_kernel, dim3((ne + 63) / 64), dim3(256), 0, s, a.igram, a.n, a.d, a.gram,
+                     a.ctl);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(wide_gram_finish_kernel, dim3(1), dim3(64), 0, s, a.gram, a.d, a.ctl, a.wctl);
   return hipGetLastError();
 }
 
@@ -887,13 +927,19 @@ hipError_t launch_wide_init_product(int fmt, const WideArgs &a, hipStream_t s) {
 hipError_t launch_wide_init_apply(int fmt, const void *W, const void *Y, void *Y_next, int nd, int d,
                                   double *partials, int num_groups, DevCtl *ctl, WideCtl *wctl,
                                   int iter, double tol, hipStream_t s) {
-  const dim3 grid(num_groups), block(256);
+  (void)num_groups;
+  const int groups = (int)(((int64_t)nd * d + 255) / 256);   // one thread per entry
+  num_groups = groups;
+  const dim3 grid(groups), block(256);
   if (fmt == NSRGS_A_F64)
     hipLaunchKernelGGL(wide_init_apply_kernel<double>, grid, block, 0, s, (const double *)W, (const double *)Y,
                        (double *)Y_next, nd, d, partials, num_groups, ctl, wctl, iter, tol);
   else
     hipLaunchKernelGGL(wide_init_apply_kernel<float>, grid, block, 0, s, (const float *)W, (const float *)Y,
                        (float *)Y_next, nd, d, partials, num_groups, ctl, wctl, iter, tol);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(wide_init_check_kernel, dim3(1), dim3(256), 0, s, partials, num_groups, d, ctl, wctl, iter, tol);
   return hipGetLastError();
 }
 
