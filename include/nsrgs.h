@@ -250,7 +250,7 @@ int sync_step_symmetric(const nsrgs_matrix *A, int n, int d, double mu, int ns_s
  *            row_ptr[i], at values[row_ptr[i] d^2 + (a d + b) m + k]
  *            (entry-major within a block row).
  * All three are device arrays owned by the caller; fmt is NSRGS_A_F32 or
- * NSRGS_A_BF16 (element type of values).  1 <= d <= 8. */
+ * NSRGS_A_BF16 (element type of values).  1 <= d <= 32. */
 typedef struct {
   int32_t fmt;
   int32_t reserved;
@@ -274,9 +274,29 @@ int nsrgs_bsr_fill(const double *Z, int n, int d, double sigma, double p, uint64
 /* sync_step on block-sparse A: C_i = sum over stored j != i of A_ij X_j, then
  * the per-block step of sync_step.  X_in / X_out are FP32.  mu <= 0 selects
  * 1/n; for the incomplete observation model pass mu = 1/(np).  ws as for
- * sync_step with fmt NSRGS_A_F32.  Asynchronous. */
+ * sync_step with fmt NSRGS_A_F32 (for d > 8: sync_workspace_bytes(n, d,
+ * NSRGS_A_F32) bytes; d <= 8 needs less).  1 <= d <= 32: d <= 8 runs one
+ * fused kernel (one wave per block row); larger d runs a block-sparse product
+ * (chunks of blocks through LDS) followed by the matrix-core path's per-block
+ * epilogue.  Asynchronous. */
 int sync_step_bsr(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_steps,
                   const void *X_in, void *X_out, void *ws, size_t ws_bytes, void *stream);
+
+/* Algorithm 2 end to end on block-sparse A (the incomplete observation model
+ * of Sec. 4.1): spectral initialization (opts->init, default on) by the
+ * subspace iteration of sync_init_spectral with the block-sparse product, then
+ * at most max_iters iterations with the stop rule of opts->stop_rule (relative
+ * change, or the paper's R^t; F counts the stored blocks, the others being
+ * zero) when tol > 0.  opts->method NS_RGS or POLAR; GPM is refused
+ * (NSRGS_ERR_UNSUPPORTED): it needs the diagonal blocks, which are not stored.
+ * Symmetric steps and refinement are refused too.  The diagonal blocks count
+ * as zero, which leaves the iteration unchanged (it never reads them) and
+ * shifts the spectrum only by A_ii (= I in the paper's model, so the same
+ * eigenvectors).  X: FP32 device n*d x d; ws of sync_workspace_bytes(n, d,
+ * NSRGS_A_F32) bytes; 1 <= d <= 32.  Waits for the stream and fills *info. */
+int sync_solve_bsr(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_steps, int max_iters,
+                   double tol, void *X, void *ws, size_t ws_bytes, void *stream,
+                   const nsrgs_solve_opts *opts, nsrgs_info *info);
 
 /* Copy the monitors of the last step / init on this workspace to *info
  * (waits for `stream`). */

@@ -149,6 +149,8 @@ def lib() -> ctypes.CDLL:
         "nsrgs_bsr_count": (i32, [vp, i32, i32, dbl, ctypes.c_uint64, vp, vp, ctypes.POINTER(i64), vp]),
         "nsrgs_bsr_fill": (i32, [vp, i32, i32, dbl, dbl, ctypes.c_uint64, ctypes.POINTER(_Bsr), vp]),
         "sync_step_bsr": (i32, [ctypes.POINTER(_Bsr), i32, i32, dbl, i32, vp, vp, vp, sz, vp]),
+        "sync_solve_bsr": (i32, [ctypes.POINTER(_Bsr), i32, i32, dbl, i32, i32, dbl, vp, vp, sz, vp,
+                                 ctypes.POINTER(_SolveOpts), ctypes.POINTER(Info)]),
         "sync_read_info": (i32, [vp, sz, i32, i32, i32, ctypes.POINTER(Info), vp]),
         "sync_init_spectral": (i32, [pm, i32, i32, vp, i32, dbl, vp, sz, vp, ctypes.POINTER(Info)]),
         "sync_solve": (i32, [pm, i32, i32, dbl, i32, i32, dbl, vp, vp, sz, vp,
@@ -412,6 +414,26 @@ def step_bsr(A: BsrMatrix, n: int, d: int, X_in: torch.Tensor, X_out: torch.Tens
     m = A.c()
     _check(lib().sync_step_bsr(ctypes.byref(m), n, d, float(mu), int(ns_steps), X_in.data_ptr(), X_out.data_ptr(),
                                ws.ptr, ws.nbytes, _stream()))
+
+
+def solve_bsr(A: BsrMatrix, n: int, d: int, X: torch.Tensor, ws: Workspace, mu: float = 0.0,
+              ns_steps: int = 3, max_iters: int = 100, tol: float = 0.0, init: bool = True,
+              init_iters: int = 60, init_tol: float = 0.0, check_every: int = 16, check: bool = True,
+              method: str = "ns_rgs", stop: str = "rel_change") -> dict:
+    """sync_solve_bsr: Algorithm 2 on block-sparse A (spectral initialization with
+    the block-sparse product, then the iterations); ws = workspace(n, d, F32)."""
+    _check_x(X, n * d, d, F32, "X")
+    m = A.c()
+    opts = _SolveOpts(int(init), int(init_iters), float(init_tol), 0, None, int(check_every), 0,
+                      METHODS[method], STOP_RULES[stop])
+    info = Info()
+    st = lib().sync_solve_bsr(ctypes.byref(m), n, d, float(mu), int(ns_steps), int(max_iters), float(tol),
+                              X.data_ptr(), ws.ptr, ws.nbytes, _stream(), ctypes.byref(opts), ctypes.byref(info))
+    if check:
+        _check(st, allow=(5,))
+    out = info.as_dict(d)
+    out["status"] = st
+    return out
 
 
 def read_info(ws: Workspace) -> dict:

@@ -28,7 +28,8 @@ namespace nsrgs {
 namespace {
 
 constexpr int kBsrRowsPerGroup = 4;   // block rows (waves) per step workgroup
-constexpr int kBsrMaxD = 8;
+constexpr int kBsrStepMaxD = 8;       // the fused one-wave-per-row step kernel
+constexpr int kBsrMaxD = 32;          // storage, generator, and the step / solve through the wide epilogue
 
 // Observation indicator of block pair (bi, bj), bi != bj: the generator's mask.
 __device__ __forceinline__ bool observed(int bi, int bj, double p, uint32_t k0, uint32_t k1) {
@@ -97,13 +98,14 @@ __global__ void __launch_bounds__(256)
 bsr_fill_kernel(const double *__restrict__ Z, int n, int d, double sigma, double p, uint32_t k0, uint32_t k1,
                 const int64_t *__restrict__ row_ptr, int32_t *__restrict__ col_idx, T *__restrict__ values) {
   __shared__ int s_wave[kMaxWaves];
+  __shared__ double zi[kBsrMaxD * kBsrMaxD];
   const int i = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave, nw = blockDim.x / kWave;
   const int64_t base = row_ptr[i];
   const int64_t m = row_ptr[i + 1] - base;
   const int d2 = d * d;
-  double zi[kBsrMaxD * kBsrMaxD];
-  for (int e = 0; e < d2; ++e) zi[e] = Z[(int64_t)i * d2 + e];
+  for (int e = tid; e < d2; e += blockDim.x) zi[e] = Z[(int64_t)i * d2 + e];
+  __syncthreads();
   int64_t done = 0;
   for (int j0 = 0; j0 < n; j0 += blockDim.x) {
     const int j = j0 + tid;
@@ -205,6 +207,78 @@ bsr_step_kernel(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__
                                     s_scr);
 }
 
+// The product of block-sparse A with X for the matrix-core path's epilogue
+// (any d <= 32): P[(i d + a) 32 + c] = sum over stored j != i of (A_ij X_j)[a][c],
+// and the sum of squares of block row i's stored off-diagonal values into
+// sumsq[i] (for the objective's constant).  One workgroup per block row.  The
+// row's blocks go through LDS in chunks of KB: the values entry by entry (entry
+// e of the chunk's blocks is KB consecutive elements of the entry-major
+// layout), X_j of each block alongside.  Thread (g, c) accumulates column c of
+// rows g, g + 8, g + 16, g + 24.  A stored diagonal block or a column index
+// outside [0, n) contributes nothing (its values and X_j are staged as zeros).
+template <typename E>
+__global__ void __launch_bounds__(256)
+bsr_wide_product_kernel(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
+                        const E *__restrict__ values, int n, int d, int KB, const float *__restrict__ X,
+                        float *__restrict__ P, double *__restrict__ sumsq, const int *stop_flag) {
+  extern __shared__ float s_dyn[];
+  __shared__ double s_scr[kMaxWaves];
+  if (stop_flag) {
+    if (__atomic_load_n(stop_flag, __ATOMIC_RELAXED)) return;   // uniform
+  }
+  const int i = blockIdx.x, tid = threadIdx.x, dd = d * d;
+  const int c = tid & 31, g = tid >> 5;
+  const int cc = c < d ? c : 0;
+  float *sA = s_dyn, *sX = s_dyn + KB * dd;
+  const int64_t base = row_ptr[i];
+  const int64_t m = row_ptr[i + 1] - base;
+  const E *__restrict__ vals = values + base * dd;
+  float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  int ar[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) ar[r] = (g + 8 * r) < d ? g + 8 * r : 0;   // clamped rows, results dropped
+  double ssq = 0.0;
+  for (int64_t k0 = 0; k0 < m; k0 += KB) {
+    const int kb = (int)((m - k0) < KB ? (m - k0) : KB);
+    for (int idx = tid; idx < KB * dd; idx += blockDim.x) {
+      const int e = idx / KB, kk = idx % KB;
+      const int kkc = kk < kb ? kk : kb - 1;
+      const int jr = col_idx[base + k0 + kkc];
+      const bool use = kk < kb && jr >= 0 && jr < n && jr != i;
+      const float v = load_elem<E>(vals + (int64_t)e * m + k0 + kkc);
+      const float va = use ? v : 0.0f;
+      sA[kk * dd + e] = va;
+      ssq += (double)va * (double)va;
+    }
+    for (int idx = tid; idx < KB * dd; idx += blockDim.x) {
+      const int kk = idx / dd, e = idx % dd;
+      const int kkc = kk < kb ? kk : kb - 1;
+      const int jr = col_idx[base + k0 + kkc];
+      const bool use = kk < kb && jr >= 0 && jr < n && jr != i;
+      const int j = jr < 0 ? 0 : (jr < n ? jr : n - 1);
+      const float x = X[(int64_t)j * dd + e];
+      sX[kk * dd + e] = use ? x : 0.0f;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < kb; ++kk) {
+      const float *a = sA + kk * dd, *x = sX + kk * dd;
+      for (int b = 0; b < d; ++b) {
+        const float xb = x[b * d + cc];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = fmaf(a[ar[r] * d + b], xb, acc[r]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int a = g + 8 * r;
+    if (a < d && c < d) P[((int64_t)i * d + a) * 32 + c] = acc[r];
+  }
+  ssq = block_sum(ssq, s_scr);
+  if (tid == 0 && sumsq) sumsq[i] = ssq;
+}
+
 template <typename E, int D>
 hipError_t bsr_launch_d(const nsrgs_bsr_matrix &A, const StreamArgs &sa, hipStream_t s) {
   hipLaunchKernelGGL((bsr_step_kernel<E, D>), dim3(sa.num_panels), dim3(kWave * kBsrRowsPerGroup), 0, s,
@@ -229,6 +303,26 @@ hipError_t bsr_launch(int d, const nsrgs_bsr_matrix &A, const StreamArgs &sa, hi
     default: return hipErrorInvalidValue;
   }
 }
+
+}  // namespace
+
+// Launch of the block-sparse product above for the matrix-core epilogue.
+hipError_t launch_bsr_wide_product(const nsrgs_bsr_matrix &A, int n, int d, const float *X, float *P,
+                                   double *sumsq, const int *stop_flag, hipStream_t s) {
+  const int dd = d * d;
+  int KB = 8192 / dd;                       // two KB x d^2 float buffers in 64 KiB of LDS
+  KB = KB > 16 ? 16 : KB;
+  const size_t lds = (size_t)2 * KB * dd * sizeof(float);
+  if (A.fmt == NSRGS_A_F32)
+    hipLaunchKernelGGL(bsr_wide_product_kernel<float>, dim3(n), dim3(256), lds, s, A.row_ptr, A.col_idx,
+                       static_cast<const float *>(A.values), n, d, KB, X, P, sumsq, stop_flag);
+  else
+    hipLaunchKernelGGL(bsr_wide_product_kernel<uint16_t>, dim3(n), dim3(256), lds, s, A.row_ptr, A.col_idx,
+                       static_cast<const uint16_t *>(A.values), n, d, KB, X, P, sumsq, stop_flag);
+  return hipGetLastError();
+}
+
+namespace {
 
 int bsr_common(int n, int d, double p) {
   if (n < 2) return fail(NSRGS_ERR_INVALID_ARG, "n must be >= 2 (got %d)", n);
@@ -296,6 +390,8 @@ int sync_step_bsr(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_ste
   const uintptr_t xi = (uintptr_t)X_in, xo = (uintptr_t)X_out;
   if (xi < xo + xb && xo < xi + xb) return fail(NSRGS_ERR_INVALID_ARG, "X_in and X_out overlap");
   if (!ws || ((uintptr_t)ws & 255u)) return fail(NSRGS_ERR_INVALID_ARG, "workspace must be non-NULL and 256-byte aligned");
+  if (d > kBsrStepMaxD)
+    return bsr_wide_step(A, n, d, mu, ns_steps, X_in, X_out, ws, ws_bytes, (hipStream_t)stream);
   const size_t need = narrow_ws_bytes(n, d, NSRGS_A_F32);
   if (ws_bytes < need) return fail(NSRGS_ERR_OUT_OF_MEMORY, "workspace too small: %zu < %zu bytes", ws_bytes, need);
   StreamArgs sa{};

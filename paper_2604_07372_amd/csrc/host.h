@@ -85,6 +85,13 @@ int sym_check(const nsrgs_matrix *A, int n, int d, size_t ws_bytes);
 int sym_step_launch(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
                     void *X_out, void *ws, hipStream_t s, int iter, double tol, bool check_done);
 
+// Block-sparse A (bsr.hip): the product for the matrix-core epilogue, and
+// (runtime.hip) one step through that epilogue for d up to 32.
+hipError_t launch_bsr_wide_product(const nsrgs_bsr_matrix &A, int n, int d, const float *X, float *P,
+                                   double *sumsq, const int *stop_flag, hipStream_t s);
+int bsr_wide_step(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
+                  void *X_out, void *ws, size_t ws_bytes, hipStream_t s);
+
 // Tuning table (runtime.hip): waves per workgroup of the grouped launch.
 int tuned_batch_waves(int fmt, int dmax);
 

@@ -497,19 +497,23 @@ int sync_read_info(const void *ws, size_t ws_bytes, int n, int d, int fmt, nsrgs
 
 // Spectral initialization for 16 < d <= 32 on the matrix-core product (the
 // same subspace iteration, Cholesky-QR and polar as init_impl).
-static int wide_init_impl(const nsrgs_matrix *A, int n, int d, void *X0, int max_iters, double tol,
-                          void *ws, hipStream_t s, DevCtl *out_ctl) {
+// The subspace iteration of the initialization for the matrix-core epilogue,
+// with the product launched by `product` (dense MFMA or block-sparse): it
+// must write W = A Y's partials and run the init epilogue (launch_wide_init_post).
+extern "C++" {
+template <typename Product>
+static int wide_init_loop(int fmt, int n, int d, void *X0, int max_iters, double tol, void *ws, hipStream_t s,
+                          DevCtl *out_ctl, WideArgs a, Product product) {
   const int nd = n * d;
-  const WsLayout L = layout(n, d, A->fmt);
+  const WsLayout L = layout(n, d, fmt);
   char *base = static_cast<char *>(ws);
   DevCtl *ctl = static_cast<DevCtl *>(ws);
   void *Y[2] = {base + L.y0, base + L.y1};
   void *W = base + L.w;
   if (max_iters <= 0) max_iters = 60;
-  if (!(tol > 0.0)) tol = A->fmt == NSRGS_A_F64 ? 1e-13 : 1e-5;
+  if (!(tol > 0.0)) tol = fmt == NSRGS_A_F64 ? 1e-13 : 1e-5;
   NSRGS_HIP(launch_ctl_reset(ctl, 2, s), "ctl reset");
-  NSRGS_HIP(launch_init_random(A->fmt, Y[0], nd, d, 0x5eed5eedULL, s), "init random");
-  WideArgs a = wide_args(A, n, d, ws);
+  NSRGS_HIP(launch_init_random(fmt, Y[0], nd, d, 0x5eed5eedULL, s), "init random");
   a.mode = WIDE_INIT;
   a.X_out = W;
   a.stop_flag = &ctl->init_done;
@@ -525,8 +529,8 @@ static int wide_init_impl(const nsrgs_matrix *A, int n, int d, void *X0, int max
     for (; k < kend; ++k) {
       a.X_in = Y[k & 1];
       a.iter = k;
-      NSRGS_HIP(launch_wide_init_product(A->fmt, a, s), "init product");
-      NSRGS_HIP(launch_wide_init_apply(A->fmt, W, Y[k & 1], Y[(k + 1) & 1], nd, d, apply_part, groups, ctl,
+      NSRGS_HIP(product(a), "init product");
+      NSRGS_HIP(launch_wide_init_apply(fmt, W, Y[k & 1], Y[(k + 1) & 1], nd, d, apply_part, groups, ctl,
                                        a.wctl, k, tol, s), "init apply");
     }
     int st;
@@ -534,7 +538,7 @@ static int wide_init_impl(const nsrgs_matrix *A, int n, int d, void *X0, int max
     if (host.init_done) break;
   }
   const int done_iters = host.init_iters;
-  NSRGS_HIP(launch_wide_init_polar(A->fmt, Y[done_iters & 1], X0, n, d, ctl, s), "init polar");
+  NSRGS_HIP(launch_wide_init_polar(fmt, Y[done_iters & 1], X0, n, d, ctl, s), "init polar");
   NSRGS_HIP(launch_wide_init_finish(ctl, a.wctl, d, s), "init finish");
   int st;
   if ((st = read_ctl(ws, &host, s))) return st;
@@ -542,6 +546,14 @@ static int wide_init_impl(const nsrgs_matrix *A, int n, int d, void *X0, int max
   if (host.init_bad) return fail(NSRGS_ERR_NONFINITE, "spectral init broke down (Cholesky/polar)");
   if (!host.init_done) return NSRGS_ERR_NOT_CONVERGED;
   return NSRGS_OK;
+}
+}  // extern "C++"
+
+static int wide_init_impl(const nsrgs_matrix *A, int n, int d, void *X0, int max_iters, double tol,
+                          void *ws, hipStream_t s, DevCtl *out_ctl) {
+  const int fmt = A->fmt;
+  return wide_init_loop(fmt, n, d, X0, max_iters, tol, ws, s, out_ctl, wide_args(A, n, d, ws),
+                        [&](const WideArgs &a) { return launch_wide_init_product(fmt, a, s); });
 }
 
 static int init_impl(const nsrgs_matrix *A, int n, int d, void *X0, int max_iters, double tol,
@@ -737,6 +749,137 @@ int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, int
     if (wide && (st = read_wide_info(ws, n, d, A->fmt, info, s))) return st;
   }
   (void)init_status;
+  return result;
+}
+
+// ---- block-sparse storage through the matrix-core epilogue ----------------
+// The product is the block-sparse kernel (one column chunk, A_ii absent); the
+// epilogue, finish, objective and initialization are the dense path's.
+static WideArgs bsr_wide_args(int n, int d, void *ws) {
+  const nsrgs_matrix shape{NSRGS_A_F32, nullptr, nullptr, nullptr, 0};
+  WideArgs a = wide_args(&shape, n, d, ws);
+  a.A = nullptr;
+  a.ld = 0;
+  a.no_diag = 1;
+  a.g.ks = 1;
+  a.g.rows_pad = n * d;
+  a.g.row_tiles = n;          // one sum-of-squares partial per block row
+  return a;
+}
+
+static double *bsr_sumsq(int n, int d, void *ws) {
+  return reinterpret_cast<double *>(static_cast<char *>(ws) + layout(n, d, NSRGS_A_F32).wide +
+                                    wide_layout(n, d, NSRGS_A_F32).sumsq);
+}
+
+static int bsr_step_launch(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_steps, int method,
+                           const void *X_in, void *X_out, void *ws, hipStream_t s, int iter, double tol,
+                           int stop_rule, bool objective, bool check_done) {
+  WideArgs a = bsr_wide_args(n, d, ws);
+  a.X_in = X_in;
+  a.X_out = X_out;
+  a.mu = mu > 0.0 ? mu : 1.0 / n;
+  a.ns_steps = ns_steps;
+  a.method = method;
+  a.mode = WIDE_STEP;
+  a.iter = iter;
+  a.tol = tol;
+  a.stop_rule = stop_rule;
+  a.objective = objective ? 1 : 0;
+  a.sumsq = (objective && iter == 0) ? bsr_sumsq(n, d, ws) : nullptr;
+  a.stop_flag = check_done ? &a.ctl->done : nullptr;
+  if (objective) NSRGS_HIP(launch_wide_gram(NSRGS_A_F32, a, s), "gram launch");
+  NSRGS_HIP(launch_bsr_wide_product(*A, n, d, static_cast<const float *>(X_in), static_cast<float *>(a.part),
+                                    a.sumsq, a.stop_flag, s), "block-sparse product launch");
+  NSRGS_HIP(launch_wide_post(NSRGS_A_F32, a, s), "epilogue launch");
+  return NSRGS_OK;
+}
+
+}  // extern "C"
+
+namespace nsrgs {
+int bsr_wide_step(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
+                  void *X_out, void *ws, size_t ws_bytes, hipStream_t s) {
+  const size_t need = layout(n, d, NSRGS_A_F32).total;
+  if (ws_bytes < need)
+    return fail(NSRGS_ERR_OUT_OF_MEMORY, "workspace too small for d = %d: %zu < %zu bytes (sync_workspace_bytes)",
+                d, ws_bytes, need);
+  return bsr_step_launch(A, n, d, mu, ns_steps, WIDE_NS, X_in, X_out, ws, s, 0, 0.0, 0, false, false);
+}
+}  // namespace nsrgs
+
+extern "C" {
+
+int sync_solve_bsr(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_steps, int max_iters, double tol,
+                   void *X, void *ws, size_t ws_bytes, void *stream, const nsrgs_solve_opts *opts,
+                   nsrgs_info *info) {
+  if (n < 2) return fail(NSRGS_ERR_INVALID_ARG, "n must be >= 2 (got %d)", n);
+  if (d < 1 || d > kWideMaxD) return fail(NSRGS_ERR_INVALID_ARG, "d must be in [1, %d] (got %d)", kWideMaxD, d);
+  if ((int64_t)n * d * d >= (int64_t)1 << 31) return fail(NSRGS_ERR_INVALID_ARG, "n*d*d too large");
+  if (!A || !A->row_ptr || !A->col_idx || !A->values) return fail(NSRGS_ERR_INVALID_ARG, "NULL matrix pointer");
+  if (A->fmt != NSRGS_A_F32 && A->fmt != NSRGS_A_BF16)
+    return fail(NSRGS_ERR_UNSUPPORTED, "block-sparse values must be F32 or BF16");
+  if (!X || !aligned16(X)) return fail(NSRGS_ERR_INVALID_ARG, "X must be non-NULL and 16-byte aligned");
+  if (ns_steps < 0 || ns_steps > 64) return fail(NSRGS_ERR_INVALID_ARG, "ns_steps must be in [0, 64]");
+  if (max_iters < 0) return fail(NSRGS_ERR_INVALID_ARG, "max_iters must be >= 0");
+  if (!std::isfinite(mu)) return fail(NSRGS_ERR_INVALID_ARG, "mu must be finite");
+  int st;
+  if ((st = check_ws(ws, ws_bytes, n, d, NSRGS_A_F32, true))) return st;
+  nsrgs_solve_opts o{1, 60, 0.0, 0, nullptr, 16, 0, NSRGS_METHOD_NS_RGS, NSRGS_STOP_REL_CHANGE};
+  if (opts) o = *opts;
+  if (o.check_every <= 0) o.check_every = 16;
+  if (o.method == NSRGS_METHOD_GPM)
+    return fail(NSRGS_ERR_UNSUPPORTED, "GPM needs the diagonal blocks, which block-sparse storage omits");
+  if (o.method != NSRGS_METHOD_NS_RGS && o.method != NSRGS_METHOD_POLAR)
+    return fail(NSRGS_ERR_INVALID_ARG, "unknown method %d", (int)o.method);
+  if (o.stop_rule != NSRGS_STOP_REL_CHANGE && o.stop_rule != NSRGS_STOP_OBJECTIVE)
+    return fail(NSRGS_ERR_INVALID_ARG, "unknown stop rule %d", (int)o.stop_rule);
+  if (o.symmetric || o.refine_iters > 0)
+    return fail(NSRGS_ERR_UNSUPPORTED, "block-sparse solves take neither the symmetric step nor refinement");
+  hipStream_t s = (hipStream_t)stream;
+  const bool objective = o.stop_rule == NSRGS_STOP_OBJECTIVE;
+  const WsLayout L = layout(n, d, NSRGS_A_F32);
+  void *buf[2] = {X, static_cast<char *>(ws) + L.xalt};
+  DevCtl host{};
+  if (o.init) {
+    const int ist = wide_init_loop(NSRGS_A_F32, n, d, X, o.init_iters, o.init_tol, ws, s, &host,
+                                   bsr_wide_args(n, d, ws), [&](const WideArgs &a) {
+                                     hipError_t e = launch_bsr_wide_product(*A, n, d, static_cast<const float *>(a.X_in),
+                                                                            static_cast<float *>(a.part), nullptr,
+                                                                            a.stop_flag, s);
+                                     return e != hipSuccess ? e : launch_wide_init_post(NSRGS_A_F32, a, s);
+                                   });
+    if (ist != NSRGS_OK && ist != NSRGS_ERR_NOT_CONVERGED) {
+      if (info) fill_info(host, d, info, ist);
+      return ist;
+    }
+  }
+  NSRGS_HIP(launch_ctl_reset(static_cast<DevCtl *>(ws), 1, s), "ctl reset");
+  NSRGS_HIP(launch_wide_ctl_reset(wide_ctl(ws, n, d, NSRGS_A_F32), s), "wide ctl reset");
+  int t = 0;
+  while (t < max_iters) {
+    const int tend = std::min(max_iters, t + o.check_every);
+    for (; t < tend; ++t)
+      if ((st = bsr_step_launch(A, n, d, mu, ns_steps, o.method, buf[t & 1], buf[(t + 1) & 1], ws, s, t, tol,
+                                o.stop_rule, objective, true)))
+        return st;
+    if ((st = read_ctl(ws, &host, s))) return st;
+    if (host.done) break;
+  }
+  if ((st = read_ctl(ws, &host, s))) return st;
+  const int done_iters = host.iters;
+  if (done_iters & 1)
+    NSRGS_HIP(hipMemcpyAsync(X, buf[1], (size_t)n * d * d * sizeof(float), hipMemcpyDeviceToDevice, s), "result copy");
+  NSRGS_HIP(hipStreamSynchronize(s), "stream sync");
+  int result = NSRGS_OK;
+  if (host.nonfinite) result = fail(NSRGS_ERR_NONFINITE, "non-finite iterate at iteration %d", done_iters);
+  else if (tol > 0.0 && !host.converged) result = NSRGS_ERR_NOT_CONVERGED;
+  if (info) {
+    fill_info(host, d, info, result);
+    info->iters = done_iters;
+    info->init_residual = host.init_res;
+    if ((st = read_wide_info(ws, n, d, NSRGS_A_F32, info, s))) return st;
+  }
   return result;
 }
 

@@ -96,12 +96,19 @@ struct WideArgs {
   int stop_rule;       // 0 relative change, 1 objective ratio R^t
   int objective;       // 1: evaluate F(X^t) this step
   const int *stop_flag;
+  int no_diag;         // 1: the partials already exclude A_ii and A is not read
+                       //    (block-sparse storage); A_ii counts as zero
   WideGeom g;
 };
 
 int wide_supported_fmt(int fmt);
 hipError_t launch_wide_step(int fmt, const WideArgs &a, hipStream_t s);
 hipError_t launch_wide_init_product(int fmt, const WideArgs &a, hipStream_t s);
+// The parts around the product, for products computed elsewhere (block-sparse
+// storage): X^T X partials; epilogue + finish; init epilogue + Gram reduction.
+hipError_t launch_wide_gram(int fmt, const WideArgs &a, hipStream_t s);
+hipError_t launch_wide_post(int fmt, const WideArgs &a, hipStream_t s);
+hipError_t launch_wide_init_post(int fmt, const WideArgs &a, hipStream_t s);
 hipError_t launch_wide_init_apply(int fmt, const void *W, const void *Y, void *Y_next, int nd, int d,
                                   double *partials, int num_groups, DevCtl *ctl, WideCtl *wctl,
                                   int iter, double tol, hipStream_t s);

@@ -353,7 +353,7 @@ __global__ void __launch_bounds__(256) wide_epilogue_kernel(WideArgs a) {
     double c = 0.0;
     for (int s = 0; s < a.g.ks; ++s) c += (double)P[((size_t)s * a.g.rows_pad + row) * 32 + k];
     C[e] = c;
-    Ad[e] = (double)A[row * a.ld + (int64_t)i * d + k];
+    Ad[e] = a.no_diag ? 0.0 : (double)A[row * a.ld + (int64_t)i * d + k];
   }
   __syncthreads();
 
@@ -857,7 +857,7 @@ WideLayout wide_layout(int n, int d, int fmt) {
   L.part = off;  off += a256((size_t)g.ks_max * nd_pad * 32 * tb);
   L.xs = off;    off += a256(nd_pad * 32 * tb);                             // B operands, 2 tiles
   L.gram = off;  off += a256((size_t)kWideGramGroups * d * d * sizeof(double));
-  L.sumsq = off; off += a256((size_t)((n * d + 63) / 64) * g.ks_max * sizeof(double));
+  L.sumsq = off; off += a256(((size_t)((n * d + 63) / 64) * g.ks_max + n) * sizeof(double));
   L.igram = off; off += a256((size_t)n * 2 * d * d * sizeof(double));
   L.total = off;
   return L;
@@ -884,18 +884,50 @@ static hipError_t wide_launch_product(const WideArgs &a, hipStream_t s) {
 }
 
 template <typename T>
-static hipError_t wide_step_t(const WideArgs &a, hipStream_t s) {
-  hipError_t e;
-  if (a.objective) {
-    hipLaunchKernelGGL(wide_gram_kernel<T>, dim3(kWideGramGroups), dim3(256), 0, s,
-                       static_cast<const T *>(a.X_in), a.nd, a.d, a.gram, a.stop_flag);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  if ((e = wide_launch_product<T>(a, s)) != hipSuccess) return e;
+static hipError_t wide_gram_t(const WideArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(wide_gram_kernel<T>, dim3(kWideGramGroups), dim3(256), 0, s,
+                     static_cast<const T *>(a.X_in), a.nd, a.d, a.gram, a.stop_flag);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t wide_post_t(const WideArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(wide_epilogue_kernel<T>, dim3(a.n), dim3(256), 0, s, a);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(wide_finish_kernel, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t wide_init_post_t(const WideArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(wide_epilogue_kernel<T>, dim3(a.n), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int ne = 2 * a.d * a.d;
+  hipLaunchKernelGGL(wide_igram_reduce_kernel, dim3((ne + 63) / 64), dim3(256), 0, s, a.igram, a.n, a.d, a.gram,
+                     a.ctl);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(wide_gram_finish_kernel, dim3(1), dim3(64), 0, s, a.gram, a.d, a.ctl, a.wctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_wide_gram(int fmt, const WideArgs &a, hipStream_t s) {
+  return fmt == NSRGS_A_F64 ? wide_gram_t<double>(a, s) : wide_gram_t<float>(a, s);
+}
+hipError_t launch_wide_post(int fmt, const WideArgs &a, hipStream_t s) {
+  return fmt == NSRGS_A_F64 ? wide_post_t<double>(a, s) : wide_post_t<float>(a, s);
+}
+hipError_t launch_wide_init_post(int fmt, const WideArgs &a, hipStream_t s) {
+  return fmt == NSRGS_A_F64 ? wide_init_post_t<double>(a, s) : wide_init_post_t<float>(a, s);
+}
+
+template <typename T>
+static hipError_t wide_step_t(const WideArgs &a, hipStream_t s) {
+  hipError_t e;
+  if (a.objective && (e = wide_gram_t<T>(a, s)) != hipSuccess) return e;
+  if ((e = wide_launch_product<T>(a, s)) != hipSuccess) return e;
+  return wide_post_t<T>(a, s);
 }
 
 hipError_t launch_wide_step(int fmt, const WideArgs &a, hipStream_t s) {
@@ -908,14 +940,7 @@ template <typename T>
 static hipError_t wide_init_product_t(const WideArgs &a, hipStream_t s) {
   hipError_t e;
   if ((e = wide_launch_product<T>(a, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(wide_epilogue_kernel<T>, dim3(a.n), dim3(256), 0, s, a);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int ne = 2 * a.d * a.d;
-  hipLaunchKernelGGL(wide_igram_reduce_kernel, dim3((ne + 63) / 64), dim3(256), 0, s, a.igram, a.n, a.d, a.gram,
-                     a.ctl);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(wide_gram_finish_kernel, dim3(1), dim3(64), 0, s, a.gram, a.d, a.ctl, a.wctl);
-  return hipGetLastError();
+  return wide_init_post_t<T>(a, s);
 }
 
 hipError_t launch_wide_init_product(int fmt, const WideArgs &a, hipStream_t s) {

@@ -171,8 +171,11 @@ def test_block_sparse_entry_points_reject_on_the_host():
     L = P.lib()
     b = P._Bsr(P.F32, 0, 256, 512, 1024)
     ws = L.sync_workspace_bytes(100, 3, P.F32)
-    # d > 8, format, NULL arrays, overlap, small workspace, mu
-    assert L.sync_step_bsr(ctypes.byref(b), 100, 9, 0.0, 3, 4096, 1 << 20, 256, 1 << 30, None) == 2
+    # d > 32, format, NULL arrays, overlap, small workspace, mu
+    assert L.sync_step_bsr(ctypes.byref(b), 100, 33, 0.0, 3, 4096, 1 << 20, 256, 1 << 30, None) == 2
+    # 8 < d <= 32 runs through the matrix-core epilogue and needs its whole workspace
+    assert L.sync_step_bsr(ctypes.byref(b), 100, 9, 0.0, 3, 4096, 1 << 20, 256,
+                           L.sync_workspace_bytes(100, 9, P.F32) - 256, None) == 3
     f64 = P._Bsr(P.F64, 0, 256, 512, 1024)
     assert L.sync_step_bsr(ctypes.byref(f64), 100, 3, 0.0, 3, 4096, 1 << 20, 256, ws, None) == 2
     null = P._Bsr(P.F32, 0, 256, None, 1024)

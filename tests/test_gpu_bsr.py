@@ -92,7 +92,8 @@ def test_bsr_generator_matches_host_twin_and_dense_generator(d, p):
 
 @pytest.mark.parametrize("fmt", [P.F32, P.BF16], ids=lambda f: FMT_NAME[f])
 @pytest.mark.parametrize("p", [0.05, 0.5, 0.8, 1.0])
-@pytest.mark.parametrize("n,d", [(2, 1), (37, 3), (300, 3), (130, 4), (61, 5), (40, 8), (700, 2)])
+@pytest.mark.parametrize("n,d", [(2, 1), (37, 3), (300, 3), (130, 4), (61, 5), (40, 8), (700, 2),
+                                 (23, 9), (31, 16), (40, 25), (9, 32)])
 def test_bsr_step_parity(n, d, p, fmt):
     require_gpu()
     seed = 7000 + 31 * n + d
@@ -181,3 +182,86 @@ def test_bsr_stored_diagonal_and_out_of_range_blocks_count_nothing():
     ref = O.rgs_step(A.astype(np.float32).astype(np.float64), host(Xin), d, mu=0.3, Ts=3)
     assert np.isfinite(host(Xout)).all()
     assert np.abs(host(Xout) - ref.X).max() <= 1e-5
+
+
+@pytest.mark.parametrize("method", ["ns_rgs", "polar"])
+def test_bsr_solve_matches_oracle(method):
+    """sync_solve_bsr at d = 25 from the oracle's spectral start: 25 iterations
+    of the incomplete observation model (p = 0.5, mu = 1/(np)) against the oracle
+    on the dense masked matrix of the stored FP32 values."""
+    require_gpu()
+    n, d, p = 64, 25, 0.5
+    Z, sigma, A64 = _masked(n, d, 0.1, 4242, p)
+    B = P.generate_bsr(torch.from_numpy(Z).cuda(), sigma, 4243, p, fmt=P.F32)
+    As = oracle_matrix(A64, P.F32)
+    X0 = O.spectral_init(As, d)
+    X = to_dev(X0, torch.float32)
+    ws = P.workspace(n, d, P.F32)
+    mu = 1.0 / (n * p)
+    info = P.solve_bsr(B, n, d, X, ws, mu=mu, ns_steps=3, max_iters=25, init=False, method=method)
+    ref = O.solve(As, d, mu=mu, Ts=3, T=25, X0=host(to_dev(X0, torch.float32)),
+                  retraction="polar" if method == "polar" else "ns")
+    e_g, e_o = O.alignment_error(host(X), Z), O.alignment_error(ref.X, Z)
+    dist = O.dist_F(host(X), ref.X) / math.sqrt(n)
+    print(f"bsr solve {method}: iters {info['iters']} e {e_g:.8f} vs {e_o:.8f} d_F/sqrt(n) {dist:.2e}", flush=True)
+    assert info["iters"] == 25 and info["status"] == 0
+    assert abs(e_g - e_o) <= 1e-4 * e_o
+    assert dist <= 1e-4 * e_o
+
+
+def test_bsr_spectral_init_matches_eigh():
+    """The initialization with the block-sparse product: the diagonal blocks are
+    not stored, so it takes the top-d subspace of A without them, which for the
+    paper's model (A_ii = I) is that of A."""
+    require_gpu()
+    n, d, p = 80, 25, 0.8
+    Z, sigma, A64 = _masked(n, d, 0.1, 515, p)
+    B = P.generate_bsr(torch.from_numpy(Z).cuda(), sigma, 516, p, fmt=P.F32)
+    As = oracle_matrix(A64, P.F32)
+    blk = np.arange(n * d) // d
+    As_off = np.where(blk[:, None] == blk[None, :], 0.0, As)
+    X0_ref = O.spectral_init(As_off, d)
+    X = torch.empty((n * d, d), dtype=torch.float32, device="cuda")
+    ws = P.workspace(n, d, P.F32)
+    info = P.solve_bsr(B, n, d, X, ws, mu=1.0 / (n * p), max_iters=0, init=True, init_iters=200)
+    dist = O.dist_F(host(X), X0_ref) / math.sqrt(n)
+    print(f"bsr init: residual {info['init_residual']:.2e} d_F/sqrt(n) {dist:.2e}", flush=True)
+    assert dist <= 1e-4
+
+
+def test_bsr_solve_refuses_gpm_on_the_host():
+    require_gpu()
+    n, d = 10, 3
+    Z, sigma, A64 = _masked(n, d, 0.1, 17, 0.5)
+    B = P.generate_bsr(torch.from_numpy(Z).cuda(), sigma, 18, 0.5, fmt=P.F32)
+    X = torch.zeros((n * d, d), dtype=torch.float32, device="cuda")
+    info = P.solve_bsr(B, n, d, X, P.workspace(n, d, P.F32), method="gpm", check=False)
+    assert info["status"] == 2
+
+
+@pytest.mark.parametrize("p", [0.8, 0.5])
+def test_table1_masked_rows_on_block_sparse_storage(golden_dir, p):
+    """Table 1 (Sec. 4.1), rows p = 0.8 and 0.5, NS-RGS, on block-sparse FP32
+    storage: n = 500, d = 25, W_ii = 0 (the diagonal blocks are not stored),
+    spectral initialization with the block-sparse product, one Newton-Schulz
+    step, mu = 1/(np), stop at R^t < 1e-8 or 100 iterations.  One trial per
+    cell against the paper's mean of 10 (2%)."""
+    import os
+    require_gpu()
+    want = {(r[0], r[1]): r[2] for r in np.loadtxt(os.path.join(golden_dir, "table1_masked_relerr.txt"))}
+    n, d = 500, 25
+    Z = synth.haar_blocks(n, d, 80 + int(10 * p))
+    Zd = torch.from_numpy(Z).cuda()
+    for sigma in (0.02, 0.1, 0.2):
+        B = P.generate_bsr(Zd, sigma, 990 + int(100 * p), p, fmt=P.F32)
+        X = torch.empty((n * d, d), dtype=torch.float32, device="cuda")
+        ws = P.workspace(n, d, P.F32)
+        info = P.solve_bsr(B, n, d, X, ws, mu=1.0 / (n * p), ns_steps=1, max_iters=100, tol=1e-8,
+                           init=True, init_iters=300, stop="objective", check=False)
+        got = O.rel_err(host(X), Z, form="gram")
+        print(f"Table 1 block-sparse p={p} sigma={sigma}: nnzb {B.nnzb} iters {info['iters']} "
+              f"Rel.Err {got:.4e} (paper {want[(p, sigma)]:.2e})", flush=True)
+        assert info["status"] in (0, 5) and info["nonfinite"] == 0
+        assert abs(got / want[(p, sigma)] - 1.0) <= 0.02
+        del B, ws
+    torch.cuda.empty_cache()
