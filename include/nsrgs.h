@@ -24,6 +24,11 @@
  *   ld elements (padding columns are never used as data); base pointers are
  *   16-byte aligned.  A must be symmetric; only the off-diagonal blocks enter
  *   the gradient, the diagonal blocks enter only the spectral initialization.
+ * - Packed storage (ld == NSRGS_LD_PACKED): the upper block triangle of the
+ *   symmetric A (Sec. 2.2: A_ji = A_ij^T) in about half the memory; see
+ *   NSRGS_LD_PACKED below.  Read by sync_step_symmetric, by sync_solve with
+ *   opts->symmetric = 1 and by sync_init_spectral (d <= 16, formats F64, F32,
+ *   BF16, BF16_SPLIT); every other call refuses it with NSRGS_ERR_UNSUPPORTED.
  * - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue work
  *   on it and return without waiting unless stated otherwise.
  * - Return value: an nsrgs_status.  On error nothing has been enqueued and
@@ -73,12 +78,28 @@ typedef enum {
                              s_r = max_c |A_rc| / 448; value = s_r * e4m3(code) */
 } nsrgs_a_format;
 
+/* Packed upper-block-triangle layout of a symmetric A, selected by
+ * nsrgs_matrix.ld == NSRGS_LD_PACKED.  With ndp = n d rounded up to a multiple
+ * of 16, row r of block row i = r / d keeps the columns [c0(i), ndp),
+ * c0(i) = 16 floor(i d / 16): its part on and above the diagonal block,
+ * widened to the left to a multiple of 16 (so every 16-element group of the
+ * full layout stays whole and 16-byte aligned).  Rows follow one another
+ * without gaps: element (r, c), c0(i) <= c < ndp, is at
+ *     off(r) + c - c0(i),   off(r) = d sum_{b < i} (ndp - c0(b)) + (r - i d)(ndp - c0(i)),
+ * and the whole matrix takes nsrgs_packed_elems(n, d) elements, about
+ * (n d)^2 / 2 + n d (d + 16).  Columns c >= n d are padding (the generator
+ * writes zeros there); columns below the diagonal block that the widening
+ * keeps hold A(r, c) when the generator writes them and are never used.
+ * BF16_SPLIT keeps its low part in data_lo with the same layout. */
+#define NSRGS_LD_PACKED (-1)
+int64_t nsrgs_packed_elems(int n, int d);   /* 0 for n < 1, d < 1, d > 32 or n d >= 2^31 */
+
 typedef struct {
   int32_t fmt;             /* nsrgs_a_format                                    */
-  const void *data;        /* device; n*d rows of ld elements                   */
+  const void *data;        /* device; n*d rows of ld elements, or packed        */
   const void *data_lo;     /* device; BF16_SPLIT low part (same layout), else NULL */
   const float *row_scale;  /* device; FP8 per-row scales (n*d floats), else NULL */
-  int64_t ld;              /* leading dimension in elements                     */
+  int64_t ld;              /* leading dimension in elements, or NSRGS_LD_PACKED */
 } nsrgs_matrix;
 
 /* Monitors of the last iteration, filled from device memory by the calls
@@ -132,8 +153,10 @@ typedef struct {
                                    BF16_SPLIT copy of A), or NULL [NULL]          */
   int32_t check_every;      /* iterations enqueued between host checks [16]         */
   int32_t symmetric;        /* 1: every iteration is sync_step_symmetric's (A and
-                               A_refine exactly symmetric, formats and d as there;
-                               ws of sync_step_symmetric_workspace_bytes) [0]      */
+                               A_refine exactly symmetric, full or packed, formats
+                               and d as there; ws of
+                               sync_step_symmetric_workspace_bytes), and so is the
+                               initialization's product W = A Y [0]                */
   int32_t method;           /* nsrgs_method [NS_RGS]; POLAR and GPM need F64 or F32 */
   int32_t stop_rule;        /* nsrgs_stop_rule [REL_CHANGE]; OBJECTIVE needs F64 or
                                F32 storage and no refinement                      */
@@ -222,7 +245,8 @@ int sync_step_noalloc(const nsrgs_matrix *A, int n, int d, double mu, int ns_ste
  * hi+lo conversions are.
  * Values on and below the block diagonal are never used.  Cache lines
  * near the diagonal may still be loaded, so they must be readable memory;
- * their contents do not matter.
+ * their contents do not matter.  A may be packed (NSRGS_LD_PACKED), which
+ * halves its footprint; the result is the same as from the full layout.
  * Formats F64, F32, BF16 and BF16_SPLIT; 1 <= d <= 16.  FP8_E4M3 is refused
  * with NSRGS_ERR_UNSUPPORTED: its per-row scales make the stored A_ij and
  * A_ji differ.
@@ -316,6 +340,9 @@ int sync_read_info(const void *ws, size_t ws_bytes, int n, int d, int fmt,
  * Subspace iteration finds the dominant (largest |lambda|) subspace, which is
  * the top-d one whenever lambda_d > |lambda_min| (true below the spectral
  * threshold of the measurement model).  X0 is an n*d x d device array.
+ * A packed A (NSRGS_LD_PACKED) runs the product W = A Y on the symmetric
+ * half-stream tiles plus the diagonal blocks; ws must then hold
+ * sync_step_symmetric_workspace_bytes(n, d, fmt) bytes.
  * Waits for the stream and fills *info (nullable). */
 int sync_init_spectral(const nsrgs_matrix *A, int n, int d, void *X0,
                        int max_iters, double tol, void *ws, size_t ws_bytes,
@@ -524,7 +551,9 @@ int nsrgs_autotune_batched(const nsrgs_problem *probs, int count, int ns_steps, 
  * zero_diag_blocks != 0 sets W_ii = 0 (paper's model, A_ii = I).  p < 1 keeps
  * an off-diagonal block pair with probability p (counter (j, i, 1, 0) for
  * blocks i < j, uniform from the first output word), else A_ij = A_ji = 0.
- * Z is an n*d x d double device array; 1 <= d <= 32.  Asynchronous. */
+ * Z is an n*d x d double device array; 1 <= d <= 32.  ld == NSRGS_LD_PACKED
+ * writes the packed layout (nsrgs_packed_elems(n, d) elements at A, padding
+ * columns zero).  Asynchronous. */
 int nsrgs_generate_measurement(const double *Z, int n, int d, double sigma,
                                uint64_t seed, int zero_diag_blocks, double p,
                                int fmt, void *A, int64_t ld, void *stream);
@@ -535,6 +564,14 @@ int nsrgs_generate_measurement(const double *Z, int n, int d, double sigma,
  * e4m3 saturates to +-448.  Asynchronous. */
 int nsrgs_convert(const float *A32, int nd, int64_t ld, const nsrgs_matrix *out,
                   void *stream);
+
+/* The same conversion for a packed FP32 matrix of n blocks of size d
+ * (NSRGS_LD_PACKED layout, nsrgs_packed_elems(n, d) elements) into a packed
+ * `out` (out->ld == NSRGS_LD_PACKED) of format BF16 or BF16_SPLIT.  FP8_E4M3
+ * is refused with NSRGS_ERR_UNSUPPORTED: packed storage serves the symmetric
+ * step, which does not read FP8.  Asynchronous. */
+int nsrgs_convert_packed(const float *A32, int n, int d, const nsrgs_matrix *out,
+                         void *stream);
 
 #ifdef __cplusplus
 }

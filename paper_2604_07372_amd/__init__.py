@@ -18,10 +18,11 @@ __all__ = [
     "init_spectral", "solve", "generate", "convert", "stored", "padded_ld",
     "Info", "solve_batched", "batch_rows_per_panel", "set_tuning", "get_tuning", "TuneEntry", "Server",
     "step_variants", "TuneResult", "step_symmetric", "symmetric_workspace_bytes",
-    "BsrMatrix", "generate_bsr", "step_bsr",
+    "BsrMatrix", "generate_bsr", "step_bsr", "PACKED_LD", "packed_elems", "stored_packed", "convert_packed",
 ]
 
 F64, F32, BF16, BF16_SPLIT, FP8_E4M3 = 0, 1, 2, 3, 4
+PACKED_LD = -1   # nsrgs_matrix.ld of the packed upper-block-triangle layout (NSRGS_LD_PACKED)
 FORMATS = {"f64": F64, "f32": F32, "bf16": BF16, "bf16_split": BF16_SPLIT, "fp8": FP8_E4M3}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -157,6 +158,8 @@ def lib() -> ctypes.CDLL:
                              ctypes.POINTER(_SolveOpts), ctypes.POINTER(Info)]),
         "nsrgs_generate_measurement": (i32, [vp, i32, i32, dbl, ctypes.c_uint64, i32, dbl, i32, vp, i64, vp]),
         "nsrgs_convert": (i32, [vp, i32, i64, pm, vp]),
+        "nsrgs_packed_elems": (i64, [i32, i32]),
+        "nsrgs_convert_packed": (i32, [vp, i32, i32, pm, vp]),
         "nsrgs_set_tuning": (i32, [ctypes.POINTER(TuneEntry), i32]),
         "nsrgs_get_tuning": (i32, [ctypes.POINTER(TuneEntry), i32]),
         "nsrgs_step_variants": (i32, [i32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), i32]),
@@ -237,18 +240,22 @@ class StoredMatrix:
     """Device storage of A in one format: tensors plus the leading dimension.
 
     data     : F64 float64 / F32 float32 / BF16 and BF16_SPLIT int16 codes /
-               FP8 uint8 codes, shape (nd, ld)
+               FP8 uint8 codes, shape (nd, ld); packed=True: one dimension of
+               packed_elems(n, d) values (the upper block triangle, layout in
+               include/nsrgs.h under NSRGS_LD_PACKED)
     data_lo  : BF16_SPLIT low part, same shape
     row_scale: FP8 per-row float32 scales, shape (nd,)
     """
 
-    def __init__(self, fmt: int, data: torch.Tensor, nd: int, data_lo=None, row_scale=None):
+    def __init__(self, fmt: int, data: torch.Tensor, nd: int, data_lo=None, row_scale=None,
+                 packed: bool = False):
         self.fmt = int(fmt)
         self.data = data
         self.data_lo = data_lo
         self.row_scale = row_scale
         self.nd = int(nd)
-        self.ld = int(data.shape[1])
+        self.packed = bool(packed)
+        self.ld = PACKED_LD if packed else int(data.shape[1])
 
     def c(self) -> _Matrix:
         return _Matrix(self.fmt, _ptr(self.data), _ptr(self.data_lo), _ptr(self.row_scale), self.ld)
@@ -486,17 +493,27 @@ def solve(A: StoredMatrix, n: int, d: int, X: torch.Tensor, ws: Workspace, mu: f
     return out
 
 
+def packed_elems(n: int, d: int) -> int:
+    """Elements of the packed upper-block-triangle layout (nsrgs_packed_elems)."""
+    return int(lib().nsrgs_packed_elems(int(n), int(d)))
+
+
 def generate(Z: torch.Tensor, sigma: float, seed: int, fmt: int = F32, zero_diag_blocks: bool = False,
-             p: float = 1.0, ld: int | None = None) -> torch.Tensor:
-    """A = Z Z^T + sigma W on the device (Philox4x32-10 noise); F64 or F32, shape (nd, ld)."""
+             p: float = 1.0, ld: int | None = None, packed: bool = False) -> torch.Tensor:
+    """A = Z Z^T + sigma W on the device (Philox4x32-10 noise); F64 or F32, shape (nd, ld),
+    or with packed=True the packed upper block triangle (packed_elems(n, d) values)."""
     if not Z.is_cuda or Z.dtype != torch.float64 or Z.dim() != 2 or not Z.is_contiguous():
         raise ValueError("Z must be a contiguous float64 CUDA tensor (n*d, d)")
     nd, d = Z.shape
     n = nd // d
-    ld = ld or padded_ld(nd)
-    A = torch.empty((nd, ld), dtype=_xdtype(fmt), device=Z.device)
-    if ld > nd:
-        A[:, nd:].zero_()
+    if packed:
+        A = torch.empty((packed_elems(n, d),), dtype=_xdtype(fmt), device=Z.device)
+        ld = PACKED_LD
+    else:
+        ld = ld or padded_ld(nd)
+        A = torch.empty((nd, ld), dtype=_xdtype(fmt), device=Z.device)
+        if ld > nd:
+            A[:, nd:].zero_()
     _check(lib().nsrgs_generate_measurement(Z.data_ptr(), n, d, float(sigma), int(seed),
                                             int(zero_diag_blocks), float(p), int(fmt), A.data_ptr(),
                                             ld, _stream()))
@@ -521,6 +538,32 @@ def convert(A32: torch.Tensor, fmt: int) -> StoredMatrix:
     m = out.c()
     _check(lib().nsrgs_convert(A32.data_ptr(), nd, ld, ctypes.byref(m), _stream()))
     return out
+
+
+def convert_packed(A32: torch.Tensor, n: int, d: int, fmt: int) -> StoredMatrix:
+    """One-time conversion of a packed FP32 device matrix into packed BF16 / BF16_SPLIT."""
+    count = packed_elems(n, d)
+    if not A32.is_cuda or A32.dtype != torch.float32 or A32.dim() != 1 or A32.numel() != count:
+        raise ValueError(f"A32 must be a float32 CUDA tensor of packed_elems(n, d) = {count} values")
+    if fmt not in (BF16, BF16_SPLIT):
+        raise ValueError(f"packed conversion targets BF16 or BF16_SPLIT, not format {fmt}")
+    data = torch.empty((count,), dtype=torch.int16, device=A32.device)
+    lo = torch.empty((count,), dtype=torch.int16, device=A32.device) if fmt == BF16_SPLIT else None
+    out = StoredMatrix(fmt, data, n * d, data_lo=lo, packed=True)
+    m = out.c()
+    _check(lib().nsrgs_convert_packed(A32.data_ptr(), int(n), int(d), ctypes.byref(m), _stream()))
+    return out
+
+
+def stored_packed(A: torch.Tensor, n: int, d: int, fmt: int = F32) -> StoredMatrix:
+    """Wrap a packed float32/float64 device matrix (generate(..., packed=True)) as F32/F64
+    storage, or convert a packed float32 one into packed BF16 / BF16_SPLIT."""
+    if fmt in (F64, F32):
+        want = torch.float64 if fmt == F64 else torch.float32
+        if A.dtype != want or A.dim() != 1 or A.numel() != packed_elems(n, d):
+            raise TypeError(f"format {fmt} needs a packed {want} matrix of packed_elems(n, d) values")
+        return StoredMatrix(fmt, A, n * d, packed=True)
+    return convert_packed(A, n, d, fmt)
 
 
 def _batch_args(problems, init=False):

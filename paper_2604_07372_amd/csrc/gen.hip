@@ -2,6 +2,8 @@
 // paper's model (Sec. 2.2, eq. def:measurements; incomplete observations of
 // Sec. 4.1) from a counter-based generator, and the one-time conversion of an
 // FP32 A into the reduced storage formats of the precision forms.
+#include <algorithm>
+
 #include "device.h"
 #include "kernels.h"
 #include "wide.h"
@@ -10,6 +12,8 @@ namespace nsrgs {
 
 // One workgroup per row r; threads stride over the columns.  Element (r, c)
 // is a pure function of (Z, sigma, seed, r, c): symmetric by construction.
+// ld == NSRGS_LD_PACKED: A is the packed upper block triangle (row0 = 0); the
+// row's columns [c0, ndp) are written, zeros past n d.
 template <typename T>
 __global__ void __launch_bounds__(256)
 generate_kernel(const double *__restrict__ Z, int n, int d, double sigma, uint32_t k0,
@@ -19,8 +23,23 @@ generate_kernel(const double *__restrict__ Z, int n, int d, double sigma, uint32
   double zr[kWideMaxD];
   for (int k = 0; k < d; ++k) zr[k] = Z[(int64_t)r * d + k];
   const int br = r / d;
-  T *out = A + (int64_t)blockIdx.x * ld;
-  for (int c = threadIdx.x; c < nd; c += blockDim.x) {
+  T *out;
+  int cbeg, cend;
+  if (ld == NSRGS_LD_PACKED) {
+    const int64_t ndp = ((int64_t)nd + 15) / 16 * 16;
+    cbeg = packed_c0(br, d);
+    cend = (int)ndp;
+    out = A + packed_row_offset(r, d, ndp) - cbeg;
+  } else {
+    cbeg = 0;
+    cend = nd;
+    out = A + (int64_t)blockIdx.x * ld;
+  }
+  for (int c = cbeg + (int)threadIdx.x; c < cend; c += blockDim.x) {
+    if (c >= nd) {
+      out[c] = T(0);
+      continue;
+    }
     double v = 0.0;
     for (int k = 0; k < d; ++k) v = fma(zr[k], Z[(int64_t)c * d + k], v);
     const int bc = c / d;
@@ -101,6 +120,27 @@ convert_fp8_kernel(const float *__restrict__ A, int nd, int64_t ld, uint8_t *__r
   if (threadIdx.x == 0) scale[r] = s;
   for (int c = threadIdx.x; c < nd; c += blockDim.x)
     q[(int64_t)r * ld + c] = (uint8_t)e4m3_rne_sat(src[c] / s);
+}
+
+__global__ void __launch_bounds__(256)
+convert_bf16_flat_kernel(const float *__restrict__ A, int64_t count, uint16_t *__restrict__ hi,
+                         uint16_t *__restrict__ lo) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float a = A[i];
+    const uint32_t h = bf16_rne_bits(a);
+    hi[i] = (uint16_t)h;
+    if (lo) lo[i] = (uint16_t)bf16_rne_bits(a - __uint_as_float(h << 16));
+  }
+}
+
+hipError_t launch_convert_flat(const float *A32, int64_t count, const nsrgs_matrix &out, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (out.fmt != NSRGS_A_BF16 && out.fmt != NSRGS_A_BF16_SPLIT) return hipErrorInvalidValue;
+  const int64_t blocks = std::min<int64_t>((count + 255) / 256, 256 * 64);
+  hipLaunchKernelGGL(convert_bf16_flat_kernel, dim3((unsigned)blocks), dim3(256), 0, s, A32, count,
+                     (uint16_t *)out.data, out.fmt == NSRGS_A_BF16_SPLIT ? (uint16_t *)out.data_lo : nullptr);
+  return hipGetLastError();
 }
 
 hipError_t launch_generate_rows(const double *Z, int n, int d, double sigma, uint64_t seed,

@@ -19,7 +19,8 @@ size_t xbytes(int fmt);
 size_t align256(size_t v);
 int check_common(int n, int d);
 bool aligned16(const void *p);
-int check_matrix(const nsrgs_matrix *A, int n, int d);
+// packed_ok: the call reads the packed symmetric layout (NSRGS_LD_PACKED).
+int check_matrix(const nsrgs_matrix *A, int n, int d, bool packed_ok = false);
 int env_int(const char *name, int dflt);
 
 #define NSRGS_HIP(call, what)                          \
@@ -61,7 +62,7 @@ struct StreamConfig;
 int step_with_config(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
                      void *X_out, void *ws, hipStream_t s, const StreamConfig &cfg);
 int check_step_args(const nsrgs_matrix *A, int n, int d, int ns_steps, const void *X_in, void *X_out,
-                    void *ws, size_t ws_bytes);
+                    void *ws, size_t ws_bytes, bool packed_ok = false);
 
 // sync_step with its argument checks, the control block at `ctl` and room
 // for stats_bytes of panel monitors at `stats` (runtime.hip).
@@ -84,6 +85,8 @@ size_t step_ws_stats_offset(int n, int d, int fmt);
 int sym_check(const nsrgs_matrix *A, int n, int d, size_t ws_bytes);
 int sym_step_launch(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
                     void *X_out, void *ws, hipStream_t s, int iter, double tol, bool check_done);
+int sym_init_product(const nsrgs_matrix *A, int n, int d, const void *Y, void *W, void *parts, void *ws,
+                     hipStream_t s, int iter);
 
 // Block-sparse A (bsr.hip): the product for the matrix-core epilogue, and
 // (runtime.hip) one step through that epilogue for d up to 32.

@@ -83,5 +83,8 @@ hipError_t launch_generate_rows(const double *Z, int n, int d, double sigma, uin
                                 int row0, int nrows, hipStream_t stream);
 hipError_t launch_convert_rows(const float *A32_rows, int nd, int64_t ld, const nsrgs_matrix &out,
                                int row0, int nrows, hipStream_t stream);
+// Elementwise BF16 / BF16_SPLIT conversion of `count` contiguous values (the
+// packed layout).
+hipError_t launch_convert_flat(const float *A32, int64_t count, const nsrgs_matrix &out, hipStream_t stream);
 
 }  // namespace nsrgs

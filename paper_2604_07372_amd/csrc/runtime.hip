@@ -103,13 +103,19 @@ static int check_common_wide(int n, int d, int fmt) {
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
-int check_matrix(const nsrgs_matrix *A, int n, int d) {
+int check_matrix(const nsrgs_matrix *A, int n, int d, bool packed_ok) {
   if (!A) return fail(NSRGS_ERR_INVALID_ARG, "A is NULL");
   if (!valid_fmt(A->fmt)) return fail(NSRGS_ERR_INVALID_ARG, "unknown A format %d", (int)A->fmt);
   if (!A->data) return fail(NSRGS_ERR_INVALID_ARG, "A->data is NULL");
   const int64_t nd = (int64_t)n * d;
-  if (A->ld < nd) return fail(NSRGS_ERR_INVALID_ARG, "ld (%lld) < n*d (%lld)", (long long)A->ld, (long long)nd);
-  if (A->ld % 16) return fail(NSRGS_ERR_INVALID_ARG, "ld (%lld) must be a multiple of 16", (long long)A->ld);
+  if (A->ld == NSRGS_LD_PACKED) {
+    if (!packed_ok)
+      return fail(NSRGS_ERR_UNSUPPORTED, "packed storage is read by sync_step_symmetric, symmetric solves and "
+                  "sync_init_spectral only");
+  } else {
+    if (A->ld < nd) return fail(NSRGS_ERR_INVALID_ARG, "ld (%lld) < n*d (%lld)", (long long)A->ld, (long long)nd);
+    if (A->ld % 16) return fail(NSRGS_ERR_INVALID_ARG, "ld (%lld) must be a multiple of 16", (long long)A->ld);
+  }
   if (!aligned16(A->data)) return fail(NSRGS_ERR_INVALID_ARG, "A->data must be 16-byte aligned");
   if (A->fmt == NSRGS_A_BF16_SPLIT) {
     if (!A->data_lo) return fail(NSRGS_ERR_INVALID_ARG, "BF16_SPLIT needs data_lo");
@@ -428,10 +434,10 @@ int step_with_config(const nsrgs_matrix *A, int n, int d, double mu, int ns_step
 }
 
 int check_step_args(const nsrgs_matrix *A, int n, int d, int ns_steps, const void *X_in, void *X_out,
-                    void *ws, size_t ws_bytes) {
+                    void *ws, size_t ws_bytes, bool packed_ok) {
   int st;
   if ((st = check_common(n, d))) return st;
-  if ((st = check_matrix(A, n, d))) return st;
+  if ((st = check_matrix(A, n, d, packed_ok))) return st;
   if ((st = check_ws(ws, ws_bytes, n, d, A->fmt))) return st;
   if (!X_in || !X_out) return fail(NSRGS_ERR_INVALID_ARG, "X_in / X_out is NULL");
   if (!aligned16(X_in) || !aligned16(X_out)) return fail(NSRGS_ERR_INVALID_ARG, "X buffers must be 16-byte aligned");
@@ -556,8 +562,10 @@ static int wide_init_impl(const nsrgs_matrix *A, int n, int d, void *X0, int max
                         [&](const WideArgs &a) { return launch_wide_init_product(fmt, a, s); });
 }
 
+// sym: the product runs on the symmetric half-stream tiles (A full or packed,
+// ws sized for sync_step_symmetric).
 static int init_impl(const nsrgs_matrix *A, int n, int d, void *X0, int max_iters, double tol,
-                     void *ws, hipStream_t s, DevCtl *out_ctl) {
+                     void *ws, hipStream_t s, DevCtl *out_ctl, bool sym = false) {
   const int nd = n * d;
   const WsLayout L = layout(n, d, A->fmt);
   char *base = static_cast<char *>(ws);
@@ -596,7 +604,12 @@ static int init_impl(const nsrgs_matrix *A, int n, int d, void *X0, int max_iter
       a.iter = k;
       // Launches enqueued after the residual test has passed return at once
       // (they watch init_done), so W, T and Y keep the converged iteration.
-      NSRGS_HIP(launch_stream(1, A->fmt, cfg, a, s), "init product");
+      if (sym) {
+        const int st = sym_init_product(A, n, d, Y[k & 1], W, base + L.parts, ws, s, k);
+        if (st) return st;
+      } else {
+        NSRGS_HIP(launch_stream(1, A->fmt, cfg, a, s), "init product");
+      }
       ia.Y = Y[k & 1];
       ia.Y_next = Y[(k + 1) & 1];
       ia.iter = k;
@@ -623,12 +636,16 @@ int sync_init_spectral(const nsrgs_matrix *A, int n, int d, void *X0, int max_it
   int st;
   if (!A) return fail(NSRGS_ERR_INVALID_ARG, "A is NULL");
   if ((st = check_common_wide(n, d, A->fmt))) return st;
-  if ((st = check_matrix(A, n, d))) return st;
+  if ((st = check_matrix(A, n, d, true))) return st;
+  const bool packed = A->ld == NSRGS_LD_PACKED;
+  if (packed && d > kMaxD)
+    return fail(NSRGS_ERR_UNSUPPORTED, "packed storage is read by the symmetric tiles, d <= %d", kMaxD);
   if ((st = check_ws(ws, ws_bytes, n, d, A->fmt, d > kMaxD))) return st;
+  if (packed && (st = sym_check(A, n, d, ws_bytes))) return st;
   if (!X0 || !aligned16(X0)) return fail(NSRGS_ERR_INVALID_ARG, "X0 must be non-NULL and 16-byte aligned");
   DevCtl c{};
   st = d > kMaxD ? wide_init_impl(A, n, d, X0, max_iters, tol, ws, (hipStream_t)stream, &c)
-                 : init_impl(A, n, d, X0, max_iters, tol, ws, (hipStream_t)stream, &c);
+                 : init_impl(A, n, d, X0, max_iters, tol, ws, (hipStream_t)stream, &c, packed);
   if (info) {
     fill_info(c, d, info, st);
     info->iters = c.init_iters;
@@ -646,14 +663,14 @@ int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, int
                const nsrgs_solve_opts *opts, nsrgs_info *info) {
   int st;
   if (!A) return fail(NSRGS_ERR_INVALID_ARG, "A is NULL");
+  nsrgs_solve_opts o{1, 60, 0.0, 0, nullptr, 16, 0, NSRGS_METHOD_NS_RGS, NSRGS_STOP_REL_CHANGE};
+  if (opts) o = *opts;
   if ((st = check_common_wide(n, d, A->fmt))) return st;
-  if ((st = check_matrix(A, n, d))) return st;
+  if ((st = check_matrix(A, n, d, o.symmetric == 1))) return st;
   if (!X || !aligned16(X)) return fail(NSRGS_ERR_INVALID_ARG, "X must be non-NULL and 16-byte aligned");
   if (ns_steps < 0 || ns_steps > 64) return fail(NSRGS_ERR_INVALID_ARG, "ns_steps must be in [0, 64]");
   if (max_iters < 0) return fail(NSRGS_ERR_INVALID_ARG, "max_iters must be >= 0");
   if (!std::isfinite(mu)) return fail(NSRGS_ERR_INVALID_ARG, "mu must be finite");
-  nsrgs_solve_opts o{1, 60, 0.0, 0, nullptr, 16, 0, NSRGS_METHOD_NS_RGS, NSRGS_STOP_REL_CHANGE};
-  if (opts) o = *opts;
   if (o.check_every <= 0) o.check_every = 16;
   if (o.symmetric != 0 && o.symmetric != 1) return fail(NSRGS_ERR_INVALID_ARG, "symmetric must be 0 or 1");
   if (o.method < NSRGS_METHOD_NS_RGS || o.method > NSRGS_METHOD_GPM)
@@ -688,7 +705,7 @@ int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, int
   };
   int refine = 0;
   if (o.refine_iters > 0 && o.A_refine) {
-    if ((st = check_matrix(o.A_refine, n, d))) return st;
+    if ((st = check_matrix(o.A_refine, n, d, o.symmetric == 1))) return st;
     if (xbytes(o.A_refine->fmt) != xbytes(A->fmt))
       return fail(NSRGS_ERR_INVALID_ARG, "A_refine must use the same iterate precision as A");
     if ((st = check_ws(ws, ws_bytes, n, d, o.A_refine->fmt, wide))) return st;
@@ -703,7 +720,7 @@ int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, int
   int init_status = NSRGS_OK;
   if (o.init) {
     init_status = d > kMaxD ? wide_init_impl(A, n, d, X, o.init_iters, o.init_tol, ws, s, &host)
-                            : init_impl(A, n, d, X, o.init_iters, o.init_tol, ws, s, &host);
+                            : init_impl(A, n, d, X, o.init_iters, o.init_tol, ws, s, &host, o.symmetric == 1);
     if (init_status != NSRGS_OK && init_status != NSRGS_ERR_NOT_CONVERGED) {
       if (info) fill_info(host, d, info, init_status);
       return init_status;
@@ -919,7 +936,7 @@ int nsrgs_generate_measurement(const double *Z, int n, int d, double sigma, uint
     return fail(NSRGS_ERR_INVALID_ARG, "generator writes F64 or F32 only");
   if ((st = check_common_wide(n, d, fmt))) return st;
   if (!Z || !A) return fail(NSRGS_ERR_INVALID_ARG, "Z / A is NULL");
-  if (ld < (int64_t)n * d) return fail(NSRGS_ERR_INVALID_ARG, "ld < n*d");
+  if (ld != NSRGS_LD_PACKED && ld < (int64_t)n * d) return fail(NSRGS_ERR_INVALID_ARG, "ld < n*d");
   if (!std::isfinite(sigma) || !(p > 0.0) || p > 1.0) return fail(NSRGS_ERR_INVALID_ARG, "bad sigma or p");
   NSRGS_HIP(launch_generate(Z, n, d, sigma, seed, zero_diag_blocks, p, fmt, A, ld, (hipStream_t)stream),
             "generate");
@@ -935,6 +952,25 @@ int nsrgs_convert(const float *A32, int nd, int64_t ld, const nsrgs_matrix *out,
   if (out->fmt != NSRGS_A_BF16 && out->fmt != NSRGS_A_BF16_SPLIT && out->fmt != NSRGS_A_FP8_E4M3)
     return fail(NSRGS_ERR_INVALID_ARG, "conversion target must be BF16, BF16_SPLIT or FP8_E4M3");
   NSRGS_HIP(launch_convert(A32, nd, ld, *out, (hipStream_t)stream), "convert");
+  return NSRGS_OK;
+}
+
+int64_t nsrgs_packed_elems(int n, int d) {
+  if (n < 1 || d < 1 || d > kWideMaxD || (int64_t)n * d >= (int64_t)1 << 31) return 0;
+  return packed_elems(n, d);
+}
+
+int nsrgs_convert_packed(const float *A32, int n, int d, const nsrgs_matrix *out, void *stream) {
+  if (!A32 || !out || !out->data) return fail(NSRGS_ERR_INVALID_ARG, "NULL argument");
+  const int64_t count = nsrgs_packed_elems(n, d);
+  if (count == 0) return fail(NSRGS_ERR_INVALID_ARG, "bad n / d");
+  if (out->ld != NSRGS_LD_PACKED) return fail(NSRGS_ERR_INVALID_ARG, "out->ld must be NSRGS_LD_PACKED");
+  if (out->fmt == NSRGS_A_FP8_E4M3)
+    return fail(NSRGS_ERR_UNSUPPORTED, "packed storage serves the symmetric step, which does not read FP8");
+  if (out->fmt != NSRGS_A_BF16 && out->fmt != NSRGS_A_BF16_SPLIT)
+    return fail(NSRGS_ERR_INVALID_ARG, "conversion target must be BF16 or BF16_SPLIT");
+  if (out->fmt == NSRGS_A_BF16_SPLIT && !out->data_lo) return fail(NSRGS_ERR_INVALID_ARG, "data_lo is NULL");
+  NSRGS_HIP(launch_convert_flat(A32, count, *out, (hipStream_t)stream), "convert");
   return NSRGS_OK;
 }
 

@@ -13,10 +13,10 @@
 
 namespace nsrgs {
 
-hipError_t launch_sym_f64(int, int, int, const SymArgs &, const StreamArgs &, int, hipStream_t);
-hipError_t launch_sym_f32(int, int, int, const SymArgs &, const StreamArgs &, int, hipStream_t);
-hipError_t launch_sym_bf16(int, int, int, const SymArgs &, const StreamArgs &, int, hipStream_t);
-hipError_t launch_sym_split(int, int, int, const SymArgs &, const StreamArgs &, int, hipStream_t);
+hipError_t launch_sym_f64(int, int, int, const SymArgs &, const StreamArgs &, int, int, hipStream_t);
+hipError_t launch_sym_f32(int, int, int, const SymArgs &, const StreamArgs &, int, int, hipStream_t);
+hipError_t launch_sym_bf16(int, int, int, const SymArgs &, const StreamArgs &, int, int, hipStream_t);
+hipError_t launch_sym_split(int, int, int, const SymArgs &, const StreamArgs &, int, int, hipStream_t);
 
 namespace {
 
@@ -128,19 +128,22 @@ int sym_check(const nsrgs_matrix *A, int n, int d, size_t ws_bytes) {
   return NSRGS_OK;
 }
 
-// One symmetric step launch (tile, epilogue and monitor kernels); the
-// arguments have passed the checks.  iter / tol / stop_flag as in sync_solve.
-int sym_step_launch(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
-                    void *X_out, void *ws, hipStream_t s, int iter, double tol, bool check_done) {
+// One launch of the symmetric tiles and their epilogue.  mode 0: a step
+// (X_in = X^t, X_out = X^{t+1}, monitors into the stats area); mode 1: the
+// initialization's product (X_in = Y, X_out = W = A Y, partial Grams at
+// `parts`, reduced and factored into the control block).
+static int sym_launch(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
+                      void *X_out, void *ws, hipStream_t s, int iter, double tol, const int *stop_flag,
+                      int mode, void *parts) {
   const int nd = n * d;
   const SymConfig c = sym_config(A->fmt, d, nd);
   char *base = static_cast<char *>(ws);
   const size_t off = step_ws_bytes(n, d, A->fmt);
-  DevCtl *ctl = static_cast<DevCtl *>(ws);
   SymArgs a{};
   a.A = A->data;
   a.A_lo = A->fmt == NSRGS_A_BF16_SPLIT ? A->data_lo : nullptr;
   a.ld = A->ld;
+  a.ndp = ((int64_t)nd + 15) / 16 * 16;
   a.X_in = X_in;
   a.nd = nd;
   a.H = c.H;
@@ -151,7 +154,7 @@ int sym_step_launch(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps
   sym_partial_room(n, d, A->fmt, &prow_room, &pcol_room);
   a.prow = base + off;
   a.pcol = base + off + prow_room;
-  a.stop_flag = check_done ? &ctl->done : nullptr;
+  a.stop_flag = stop_flag;
   StreamArgs sa{};
   sa.A = A->data;
   sa.ld = A->ld;
@@ -164,20 +167,39 @@ int sym_step_launch(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps
   sa.num_panels = (nd + rows_e - 1) / rows_e;
   sa.mu = mu > 0.0 ? mu : 1.0 / n;
   sa.ns_steps = ns_steps;
-  sa.partials = base + step_ws_stats_offset(n, d, A->fmt);
-  sa.ctl = ctl;
+  sa.partials = mode == 0 ? base + step_ws_stats_offset(n, d, A->fmt) : parts;
+  sa.ctl = static_cast<DevCtl *>(ws);
   sa.iter = iter;
   sa.tol = tol;
-  sa.stop_flag = a.stop_flag;
+  sa.stop_flag = stop_flag;
   hipError_t e;
   switch (A->fmt) {
-    case NSRGS_A_F64: e = launch_sym_f64(d, c.rows, c.unroll, a, sa, c.waves, s); break;
-    case NSRGS_A_F32: e = launch_sym_f32(d, c.rows, c.unroll, a, sa, c.waves, s); break;
-    case NSRGS_A_BF16: e = launch_sym_bf16(d, c.rows, c.unroll, a, sa, c.waves, s); break;
-    default: e = launch_sym_split(d, c.rows, c.unroll, a, sa, c.waves, s); break;
+    case NSRGS_A_F64: e = launch_sym_f64(d, c.rows, c.unroll, a, sa, c.waves, mode, s); break;
+    case NSRGS_A_F32: e = launch_sym_f32(d, c.rows, c.unroll, a, sa, c.waves, mode, s); break;
+    case NSRGS_A_BF16: e = launch_sym_bf16(d, c.rows, c.unroll, a, sa, c.waves, mode, s); break;
+    default: e = launch_sym_split(d, c.rows, c.unroll, a, sa, c.waves, mode, s); break;
   }
-  NSRGS_HIP(e, "symmetric step launch");
+  NSRGS_HIP(e, mode == 0 ? "symmetric step launch" : "symmetric init product launch");
   return NSRGS_OK;
+}
+
+// One symmetric step launch (tile, epilogue and monitor kernels); the
+// arguments have passed the checks.  iter / tol / stop_flag as in sync_solve.
+int sym_step_launch(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
+                    void *X_out, void *ws, hipStream_t s, int iter, double tol, bool check_done) {
+  DevCtl *ctl = static_cast<DevCtl *>(ws);
+  return sym_launch(A, n, d, mu, ns_steps, X_in, X_out, ws, s, iter, tol, check_done ? &ctl->done : nullptr, 0,
+                    nullptr);
+}
+
+// The initialization's product W = A Y from the symmetric tiles (blocks
+// above the diagonal, each used twice) plus A_ii Y_i; partial Grams at
+// `parts` (one 2 d^2 record per epilogue panel, at most n).  Launches after
+// the residual test has passed return at once (they watch init_done).
+int sym_init_product(const nsrgs_matrix *A, int n, int d, const void *Y, void *W, void *parts, void *ws,
+                     hipStream_t s, int iter) {
+  DevCtl *ctl = static_cast<DevCtl *>(ws);
+  return sym_launch(A, n, d, 0.0, 0, Y, W, ws, s, iter, 0.0, &ctl->init_done, 1, parts);
 }
 
 }  // namespace nsrgs
@@ -195,7 +217,7 @@ size_t sync_step_symmetric_workspace_bytes(int n, int d, int fmt) {
 int sync_step_symmetric(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
                         void *X_out, void *ws, size_t ws_bytes, void *stream) {
   int st;
-  if ((st = check_step_args(A, n, d, ns_steps, X_in, X_out, ws, ws_bytes))) return st;
+  if ((st = check_step_args(A, n, d, ns_steps, X_in, X_out, ws, ws_bytes, true))) return st;
   if (!std::isfinite(mu)) return fail(NSRGS_ERR_INVALID_ARG, "mu must be finite");
   if ((st = sym_check(A, n, d, ws_bytes))) return st;
   return sym_step_launch(A, n, d, mu, ns_steps, X_in, X_out, ws, (hipStream_t)stream, 0, 0.0, false);

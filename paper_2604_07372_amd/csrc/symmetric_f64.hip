@@ -2,8 +2,8 @@
 #include "symmetric_impl.h"
 
 namespace nsrgs {
-hipError_t launch_sym_f64(int d, int rows, int unroll, const SymArgs &a, const StreamArgs &sa, int waves,
+hipError_t launch_sym_f64(int d, int rows, int unroll, const SymArgs &a, const StreamArgs &sa, int waves, int mode,
                           hipStream_t s) {
-  return sym_launch_fmt<NSRGS_A_F64>(d, rows, unroll, a, sa, waves, s);
+  return sym_launch_fmt<NSRGS_A_F64>(d, rows, unroll, a, sa, waves, mode, s);
 }
 }  // namespace nsrgs

@@ -28,7 +28,8 @@ namespace nsrgs {
 struct SymArgs {
   const void *A;
   const void *A_lo;
-  int64_t ld;
+  int64_t ld;             // elements; NSRGS_LD_PACKED: packed upper block triangle
+  int64_t ndp;            // packed: n d rounded up to 16
   const void *X_in;
   int nd;
   int H;          // strip height (rows), a multiple of d, of R and of the epilogue panel
@@ -139,10 +140,25 @@ __device__ __forceinline__ void sym_tile_rows(const SymArgs &a, const typename F
       continue;
     }
     int64_t rowoff[R];
+    if (a.ld == NSRGS_LD_PACKED) {
+      // byte offset of column 0 of each row in the packed layout (columns left
+      // of the row's stored range are never used: they lie below the block
+      // diagonal, and a clamped column-0 read lands in earlier rows' storage)
+      const int rfirst = (!MASK || row0 < nd) ? row0 : nd - 1;
+      int64_t off = packed_row_offset(rfirst, D, a.ndp);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int row = (!MASK || row0 + r < nd) ? row0 + r : nd - 1;
-      rowoff[r] = (int64_t)row * a.ld * EB;
+      for (int r = 0; r < R; ++r) {
+        const int row = (!MASK || row0 + r < nd) ? row0 + r : nd - 1;
+        const int prev = r == 0 ? row : ((!MASK || row0 + r - 1 < nd) ? row0 + r - 1 : nd - 1);
+        if (r > 0 && row != prev) off += a.ndp - packed_c0(prev / D, D);   // the previous row's length
+        rowoff[r] = (off - packed_c0(row / D, D)) * EB;
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int row = (!MASK || row0 + r < nd) ? row0 + r : nd - 1;
+        rowoff[r] = (int64_t)row * a.ld * EB;
+      }
     }
     uint4 raw[R][U], rawlo[R][U];
 #pragma unroll
@@ -266,7 +282,26 @@ sym_tile_kernel(SymArgs a, const typename Fmt<FMT>::acc_t *__restrict__ X) {
 // One workgroup per BE blocks: C for each row = the row sums of the tiles of
 // its strip (chunks in order) + the column sums of the tiles above it in its
 // column (strips in order), then the per-block epilogue of the step.
-template <int FMT, int D, int BE>
+// One element A(r, c) of the storage (full or packed), as the accumulation type.
+template <int FMT>
+__device__ __forceinline__ typename Fmt<FMT>::acc_t sym_elem(const SymArgs &a, int d, int r, int c) {
+  using T = typename Fmt<FMT>::acc_t;
+  const int64_t idx = a.ld == NSRGS_LD_PACKED ? packed_row_offset(r, d, a.ndp) + c - packed_c0(r / d, d)
+                                               : (int64_t)r * a.ld + c;
+  if constexpr (FMT == NSRGS_A_F64) {
+    return static_cast<const double *>(a.A)[idx];
+  } else if constexpr (FMT == NSRGS_A_F32) {
+    return static_cast<const float *>(a.A)[idx];
+  } else {
+    const float hi = __uint_as_float((uint32_t)static_cast<const uint16_t *>(a.A)[idx] << 16);
+    if constexpr (FMT == NSRGS_A_BF16_SPLIT)
+      return hi + __uint_as_float((uint32_t)static_cast<const uint16_t *>(a.A_lo)[idx] << 16);
+    else
+      return (T)hi;
+  }
+}
+
+template <int FMT, int D, int BE, int MODE>
 __global__ void __launch_bounds__(256) sym_epilogue_kernel(SymArgs a, StreamArgs sa) {
   using T = typename Fmt<FMT>::acc_t;
   constexpr int NE = BE * D * D;
@@ -300,13 +335,53 @@ __global__ void __launch_bounds__(256) sym_epilogue_kernel(SymArgs a, StreamArgs
     sX[e] = row < nd ? x : T(0);
   }
   __syncthreads();
-  block_step_epilogue<T, D, BE>(sa.n, sa.mu, sa.ns_steps, nd, row0, static_cast<T *>(sa.X_out),
-                                static_cast<PanelStat *>(sa.partials) + blockIdx.x, sX, sC, sG, sT, sF,
-                                sM, s_scr);
+  if constexpr (MODE == 0) {
+    block_step_epilogue<T, D, BE>(sa.n, sa.mu, sa.ns_steps, nd, row0, static_cast<T *>(sa.X_out),
+                                  static_cast<PanelStat *>(sa.partials) + blockIdx.x, sX, sC, sG, sT, sF,
+                                  sM, s_scr);
+  } else {
+    // W = A Y for the panel's rows: the off-diagonal sums plus A_ii Y_i (the
+    // tiles leave the diagonal blocks out), and the panel's partial Grams
+    // Y^T W and W^T W for the Cholesky-QR of the initialization.
+    for (int e = tid; e < NE; e += blockDim.x) {
+      const int row = row0 + e / D, k = e % D;
+      const int b0 = (e / (D * D)) * D * D, ar = (e / D) % D;
+      T s = T(0);
+      if (row < nd) {
+        const int ib = row / D;
+#pragma unroll
+        for (int m = 0; m < D; ++m) s = fmaT(sym_elem<FMT>(a, D, row, ib * D + m), sX[b0 + m * D + k], s);
+      }
+      sG[e] = sC[e] + s;
+      (void)ar;
+    }
+    __syncthreads();
+    T *__restrict__ Wo = static_cast<T *>(sa.X_out);
+    for (int e = tid; e < NE; e += blockDim.x) {
+      const int row = row0 + e / D;
+      if (row < nd) Wo[(int64_t)row * D + (e % D)] = sG[e];
+    }
+    T *part = static_cast<T *>(sa.partials) + (int64_t)blockIdx.x * 2 * D * D;
+    for (int e = tid; e < D * D; e += blockDim.x) {
+      const int ar = e / D, k = e % D;
+      T g1 = 0, g2 = 0;
+      for (int r = 0; r < BE * D; ++r) {
+        if (row0 + r < nd) {
+          g1 = fmaT(sX[r * D + ar], sG[r * D + k], g1);
+          g2 = fmaT(sG[r * D + ar], sG[r * D + k], g2);
+        }
+      }
+      part[e] = g1;
+      part[D * D + e] = g2;
+    }
+  }
 }
 
+// mode 0: one step (tile, epilogue, monitor reduction); mode 1: the
+// initialization's product W = A Y with the partial Grams and their FP64
+// reduction / Cholesky factor (finish_gram).
 template <int FMT, int D, int R, int U>
-hipError_t sym_launch_shape(const SymArgs &a, const StreamArgs &sa, int waves, hipStream_t s) {
+hipError_t sym_launch_shape(const SymArgs &a, const StreamArgs &sa, int waves, int mode, hipStream_t s) {
   using T = typename Fmt<FMT>::acc_t;
   constexpr int BE = sym_epi_blocks(D);
   const size_t lds = (size_t)waves * a.H * D * sizeof(T);
@@ -314,19 +389,26 @@ hipError_t sym_launch_shape(const SymArgs &a, const StreamArgs &sa, int waves, h
                      s, a, static_cast<const T *>(a.X_in));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((sym_epilogue_kernel<FMT, D, BE>), dim3(sa.num_panels), dim3(256), 0, s, a, sa);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((stream_finish_kernel<T, D, 0>), dim3(1), dim3(256), 0, s, sa);
+  if (mode == 0) {
+    hipLaunchKernelGGL((sym_epilogue_kernel<FMT, D, BE, 0>), dim3(sa.num_panels), dim3(256), 0, s, a, sa);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((stream_finish_kernel<T, D, 0>), dim3(1), dim3(256), 0, s, sa);
+  } else {
+    hipLaunchKernelGGL((sym_epilogue_kernel<FMT, D, BE, 1>), dim3(sa.num_panels), dim3(256), 0, s, a, sa);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((stream_finish_kernel<T, D, 1>), dim3(1), dim3(256), 0, s, sa);
+  }
   return hipGetLastError();
 }
 
 // Dispatch over the compiled (d, R, U) shapes for one format.
 template <int FMT>
 hipError_t sym_launch_fmt(int d, int rows, int unroll, const SymArgs &a, const StreamArgs &sa, int waves,
-                          hipStream_t s) {
+                          int mode, hipStream_t s) {
 #define NSRGS_SYM_CASE(DD, RR, UU) \
-  if (d == DD && rows == RR && unroll == UU) return sym_launch_shape<FMT, DD, RR, UU>(a, sa, waves, s);
+  if (d == DD && rows == RR && unroll == UU) return sym_launch_shape<FMT, DD, RR, UU>(a, sa, waves, mode, s);
   NSRGS_SYM_SHAPES(NSRGS_SYM_CASE)
 #undef NSRGS_SYM_CASE
   return hipErrorInvalidValue;

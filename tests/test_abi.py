@@ -219,3 +219,68 @@ def test_solve_rejects_unknown_method_and_stop_rule():
     o = P._SolveOpts(0, 60, 0.0, 0, None, 16, 1, 1, 0)             # symmetric + exact polar
     st = L.sync_solve(ctypes.byref(m), 100, 3, 0.0, 3, 10, 0.0, 4096, 256, 1 << 30, None, ctypes.byref(o), None)
     assert st == 2
+
+
+def _packed_count(n, d):
+    """Elements of the packed upper-block-triangle layout, summed row by row
+    from its definition: row r of block i = r // d keeps columns
+    [16 floor(i d / 16), ndp), ndp = n d rounded up to 16."""
+    import numpy as np
+    nd = n * d
+    ndp = -(-nd // 16) * 16
+    i = np.arange(nd, dtype=np.int64) // d
+    return int(np.sum(ndp - 16 * ((i * d) // 16)))
+
+
+@pytest.mark.parametrize("n,d", [(1, 1), (2, 1), (2, 3), (5, 2), (17, 16), (37, 3), (100, 7), (211, 5),
+                                 (300, 12), (1000, 16), (20000, 3), (9, 32)])
+def test_packed_element_count(n, d):
+    assert P.lib().nsrgs_packed_elems(n, d) == _packed_count(n, d)
+
+
+def test_packed_footprint_is_half_of_the_full_layout():
+    n, d = 20000, 3
+    full = n * d * P.padded_ld(n * d) * 4
+    packed = P.lib().nsrgs_packed_elems(n, d) * 4
+    assert packed <= 7.21e9 and full >= 14.4e9
+    assert abs(packed / full - 0.5) < 0.002
+    for bad in [(0, 3), (10, 0), (10, 33), (1 << 20, 2048)]:
+        assert P.lib().nsrgs_packed_elems(*bad) == 0
+
+
+def test_packed_storage_is_refused_where_it_is_not_read():
+    """Only the symmetric step, symmetric solves and the initialization read
+    the packed layout; every other call refuses it on the host."""
+    L = P.lib()
+    n, d = 100, 3
+    pk = P._Matrix(P.F32, 16, None, None, P.PACKED_LD)
+    ws = L.sync_step_symmetric_workspace_bytes(n, d, P.F32)
+    info = P.Info()
+    assert L.sync_step(ctypes.byref(pk), n, d, 0.0, 3, 4096, 1 << 20, 256, ws, None) == 2
+    assert "packed" in L.nsrgs_last_error().decode()
+    assert L.sync_step_polar(ctypes.byref(pk), n, d, 0.0, 4096, 1 << 20, 256, 1 << 30, None) == 2
+    assert L.sync_step_gpm(ctypes.byref(pk), n, d, 4096, 1 << 20, 256, 1 << 30, None) == 2
+    assert L.sync_step_noalloc(ctypes.byref(pk), n, d, 0.0, 3, 4096, 1 << 20, None) == 2
+    # a solve that is not symmetric
+    o = P._SolveOpts(0, 60, 0.0, 0, None, 16, 0)
+    assert L.sync_solve(ctypes.byref(pk), n, d, 0.0, 3, 10, 0.0, 4096, 256, ws, None, ctypes.byref(o),
+                        ctypes.byref(info)) == 2
+    # symmetric: the format must be stored symmetrically, the workspace sized for the tiles
+    f8 = P._Matrix(P.FP8_E4M3, 16, None, 32, P.PACKED_LD)
+    assert L.sync_step_symmetric(ctypes.byref(f8), n, d, 0.0, 3, 4096, 1 << 20, 256, ws, None) == 2
+    assert L.sync_step_symmetric(ctypes.byref(pk), n, d, 0.0, 3, 4096, 1 << 20, 256,
+                                 L.sync_workspace_bytes(n, d, P.F32), None) == 3
+    # the initialization on packed storage needs the symmetric workspace and d <= 16
+    assert L.sync_init_spectral(ctypes.byref(pk), n, d, 4096, 0, 0.0, 256, L.sync_workspace_bytes(n, d, P.F32),
+                                None, ctypes.byref(info)) == 3
+    assert L.sync_init_spectral(ctypes.byref(pk), 30, 17, 4096, 0, 0.0, 256, 1 << 30, None,
+                                ctypes.byref(info)) == 2
+    # packed conversion: BF16 / BF16_SPLIT only, out must be packed
+    out = P._Matrix(P.BF16, 16, None, None, P.PACKED_LD)
+    out8 = P._Matrix(P.FP8_E4M3, 16, None, 32, P.PACKED_LD)
+    assert L.nsrgs_convert_packed(16, n, d, ctypes.byref(out8), None) == 2
+    assert L.nsrgs_convert_packed(16, n, d, ctypes.byref(_mat(P.BF16)), None) == 1
+    assert L.nsrgs_convert_packed(16, 0, d, ctypes.byref(out), None) == 1
+    assert L.nsrgs_convert_packed(None, n, d, ctypes.byref(out), None) == 1
+    # the generator writes packed storage for d <= 32 only
+    assert L.nsrgs_generate_measurement(16, n, 33, 1.0, 0, 0, 1.0, P.F32, 16, P.PACKED_LD, None) == 1

@@ -193,3 +193,34 @@ def test_fullsize_bsr_step_sampled_blocks(big, p):
     assert np.isfinite(Xo).all()
     del B, ws
     torch.cuda.empty_cache()
+
+
+def test_fullsize_packed_symmetric_step(big):
+    """The full-size matrix in packed storage (about half the bytes of the
+    full layout): the symmetric step gives the full layout's result bit for
+    bit, and so the oracle's on the sampled blocks."""
+    A32p = P.generate(torch.from_numpy(big["Z"]).cuda(), big["sigma"], SEED, fmt=P.F32, packed=True)
+    packed_bytes = A32p.numel() * 4
+    full_bytes = big["A32"].numel() * 4
+    print(f"full size packed: {packed_bytes / 1e9:.3f} GB vs {full_bytes / 1e9:.3f} GB", flush=True)
+    assert packed_bytes <= 7.21e9 and packed_bytes < 0.501 * full_bytes
+    Ap = P.stored_packed(A32p, N, D, P.F32)
+    Af = P.stored(big["A32"], P.F32)
+    Xin = torch.from_numpy(big["X"]).cuda()
+    Xp, Xf = torch.empty_like(Xin), torch.empty_like(Xin)
+    ws = P.workspace(N, D, P.F32, symmetric=True)
+    P.step_symmetric(Ap, N, D, Xin, Xp, ws)
+    P.step_symmetric(Af, N, D, Xin, Xf, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(Xp, Xf)
+    Xo = host(Xp)
+    Xh = big["X"].astype(np.float64)
+    rows_stored = _stored_rows(big["A_rows"], P.F32)
+    tol = step_tolerance(rows_stored, Xh, N, P.F32)
+    worst = 0.0
+    for k, i in enumerate(big["blocks"]):
+        ref = O.block_step(rows_stored[k * D:(k + 1) * D], Xh, D, int(i), Ts=3)
+        worst = max(worst, float(np.abs(Xo[i * D:(i + 1) * D] - ref).max()))
+    assert worst <= tol
+    del ws, Ap, A32p
+    torch.cuda.empty_cache()

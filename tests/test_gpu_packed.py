@@ -1,0 +1,216 @@
+"""Packed upper-block-triangle storage of the symmetric A (Sec. 2.2: A_ji =
+A_ij^T), through the C ABI: the generator and the BF16 conversions write the
+layout, and the symmetric step, the symmetric solve and the spectral
+initialization read it.  The layout is rebuilt on the host from its
+definition (include/nsrgs.h, NSRGS_LD_PACKED) row by row, independently of
+the library's offset arithmetic."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2604_07372_amd as P
+import synth
+from oracle import nsrgs as O
+
+from gpu_common import FMT_NAME, host, oracle_matrix, require_gpu, step_tolerance, to_dev, xdtype
+
+pytestmark = pytest.mark.gpu
+
+SYM_FMTS = [P.F64, P.F32, P.BF16, P.BF16_SPLIT]
+SHAPES = [(2, 1), (2, 3), (5, 2), (37, 3), (341, 3), (700, 3), (1500, 1), (100, 4), (61, 5), (47, 7),
+          (150, 6), (400, 8), (3, 8), (33, 10), (130, 10), (90, 12), (20, 16), (70, 16)]
+
+
+def pack_host(A: np.ndarray, n: int, d: int) -> np.ndarray:
+    """Row r of block i = r // d keeps the columns [16 floor(i d / 16), ndp) of
+    the matrix padded with zero columns to ndp = n d rounded up to 16; rows
+    follow one another."""
+    nd = n * d
+    ndp = -(-nd // 16) * 16
+    Af = np.zeros((nd, ndp), dtype=A.dtype)
+    Af[:, :nd] = A[:, :nd]
+    return np.concatenate([Af[r, 16 * (((r // d) * d) // 16):] for r in range(nd)])
+
+
+def stored_mask(n: int, d: int) -> np.ndarray:
+    """Which packed positions lie on or above the block diagonal inside the
+    matrix (the entries the method reads), in packed order."""
+    nd = n * d
+    ndp = -(-nd // 16) * 16
+    out = []
+    for r in range(nd):
+        i = r // d
+        c = np.arange(16 * ((i * d) // 16), ndp)
+        out.append((c >= i * d) & (c < nd))
+    return np.concatenate(out)
+
+
+def symmetric_problem(n, d, c=0.3, seed=0, eps=0.05):
+    """The generator's host twin, made exactly symmetric from its upper triangle."""
+    Z = synth.haar_blocks(n, d, seed)
+    A64 = synth.measurement_matrix(Z, synth.sigma_for(c, n, d), seed + 1)
+    A64 = np.triu(A64) + np.triu(A64, 1).T
+    X = synth.perturbed_start(Z, eps, seed + 2)
+    return Z, A64, X
+
+
+def packed_matrix(A64: np.ndarray, n: int, d: int, fmt: int) -> P.StoredMatrix:
+    """A64 in packed storage of `fmt` (the reduced formats by the library's
+    packed conversion of the FP32 values)."""
+    if fmt == P.F64:
+        return P.stored_packed(torch.from_numpy(pack_host(A64, n, d)).cuda(), n, d, P.F64)
+    v32 = torch.from_numpy(pack_host(A64.astype(np.float32), n, d)).cuda()
+    return P.stored_packed(v32, n, d, fmt)
+
+
+def full_matrix(A64: np.ndarray, fmt: int) -> P.StoredMatrix:
+    if fmt == P.F64:
+        return P.upload(A64, P.F64)
+    A32 = P.upload(A64, P.F32)
+    return A32 if fmt == P.F32 else P.convert(A32.data, fmt)
+
+
+@pytest.mark.parametrize("fmt", [P.F64, P.F32], ids=lambda f: FMT_NAME[f])
+@pytest.mark.parametrize("n,d,zero_diag,p", [(37, 3, False, 1.0), (211, 5, True, 1.0), (64, 16, False, 0.6),
+                                             (9, 32, False, 1.0), (1000, 1, False, 1.0), (150, 7, True, 0.3)])
+def test_generator_writes_the_packed_layout(n, d, zero_diag, p, fmt):
+    """Packed output = the full output's upper block triangle (widened to
+    16-column groups), bit for bit, with zero padding columns."""
+    require_gpu()
+    print(f"packed generator n={n} d={d} fmt={FMT_NAME[fmt]}", flush=True)
+    Z = torch.from_numpy(synth.haar_blocks(n, d, 3)).cuda()
+    sigma = synth.sigma_for(0.3, n, d)
+    full = P.generate(Z, sigma, 11, fmt=fmt, zero_diag_blocks=zero_diag, p=p)
+    pk = P.generate(Z, sigma, 11, fmt=fmt, zero_diag_blocks=zero_diag, p=p, packed=True)
+    torch.cuda.synchronize()
+    assert pk.numel() == P.packed_elems(n, d)
+    want = pack_host(full.cpu().numpy(), n, d)
+    assert np.array_equal(pk.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("fmt", [P.BF16, P.BF16_SPLIT], ids=lambda f: FMT_NAME[f])
+@pytest.mark.parametrize("n,d", [(37, 3), (130, 10), (20, 16)])
+def test_packed_conversion_matches_the_full_conversion(n, d, fmt):
+    require_gpu()
+    Z = torch.from_numpy(synth.haar_blocks(n, d, 5)).cuda()
+    full = P.generate(Z, 0.7, 12, fmt=P.F32)
+    pk = P.generate(Z, 0.7, 12, fmt=P.F32, packed=True)
+    cf = P.convert(full, fmt)
+    cp = P.convert_packed(pk, n, d, fmt)
+    torch.cuda.synchronize()
+    assert np.array_equal(cp.data.cpu().numpy(), pack_host(cf.data.cpu().numpy(), n, d))
+    if fmt == P.BF16_SPLIT:
+        assert np.array_equal(cp.data_lo.cpu().numpy(), pack_host(cf.data_lo.cpu().numpy(), n, d))
+    assert cp.nbytes < 0.5 * cf.nbytes + 64 * n * d * (d + 16)
+
+
+@pytest.mark.parametrize("fmt", SYM_FMTS, ids=lambda f: FMT_NAME[f])
+@pytest.mark.parametrize("n,d", SHAPES)
+def test_packed_symmetric_step_parity(n, d, fmt):
+    """One step on packed storage: the oracle's step within the format's bound,
+    and bit for bit the symmetric step on the full layout (same tiles, same
+    order of additions)."""
+    require_gpu()
+    print(f"packed symmetric step n={n} d={d} fmt={FMT_NAME[fmt]}", flush=True)
+    Z, A64, X = symmetric_problem(n, d, seed=2000 * n + d)
+    Ap = packed_matrix(A64, n, d, fmt)
+    Af = full_matrix(A64, fmt)
+    As = oracle_matrix(A64, fmt)
+    Xin = to_dev(X, xdtype(fmt))
+    ws = P.workspace(n, d, fmt, symmetric=True)
+    Xp, Xf = torch.empty_like(Xin), torch.empty_like(Xin)
+    P.step_symmetric(Ap, n, d, Xin, Xp, ws)
+    info = P.read_info(ws)
+    P.step_symmetric(Af, n, d, Xin, Xf, ws)
+    torch.cuda.synchronize()
+    Xh = host(Xin)
+    ref = O.rgs_step(As, Xh, d, mu=1.0 / n, Ts=3)
+    err = np.abs(host(Xp) - ref.X).max()
+    assert err <= step_tolerance(As, Xh, n, fmt), err
+    assert torch.equal(Xp, Xf)
+    assert abs(info["rel_change"] - ref.rel_change) <= 1e-3 * ref.rel_change + 1e-6
+    assert info["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("d", [1, 3, 5, 8, 16])
+def test_packed_entries_below_the_diagonal_and_padding_are_never_used(d):
+    """NaN in every packed position below the block diagonal (the widening to
+    16-column groups keeps some) and in the padding columns."""
+    require_gpu()
+    n = 211
+    Z, A64, X = symmetric_problem(n, d, seed=41 + d)
+    v = pack_host(A64.astype(np.float32), n, d)
+    v[~stored_mask(n, d)] = np.nan
+    Ap = P.stored_packed(torch.from_numpy(v).cuda(), n, d, P.F32)
+    Xin = to_dev(X, torch.float32)
+    Xout = torch.empty_like(Xin)
+    ws = P.workspace(n, d, P.F32, symmetric=True)
+    P.step_symmetric(Ap, n, d, Xin, Xout, ws)
+    torch.cuda.synchronize()
+    As = oracle_matrix(A64, P.F32)
+    ref = O.rgs_step(As, host(Xin), d, mu=1.0 / n, Ts=3)
+    assert np.isfinite(host(Xout)).all()
+    assert np.abs(host(Xout) - ref.X).max() <= step_tolerance(As, host(Xin), n, P.F32)
+
+
+@pytest.mark.parametrize("fmt", [P.F64, P.F32], ids=lambda f: FMT_NAME[f])
+@pytest.mark.parametrize("n,d", [(100, 3), (300, 4), (90, 12), (40, 16)])
+def test_packed_spectral_init_matches_eigh(n, d, fmt):
+    """The initialization on packed storage (the symmetric tiles plus the
+    diagonal blocks for W = A Y): Ritz values and X0 = sgn(Y) of the top-d
+    eigenvectors."""
+    require_gpu()
+    print(f"packed init n={n} d={d} fmt={FMT_NAME[fmt]}", flush=True)
+    Z = synth.haar_blocks(n, d, 7)
+    A = synth.measurement_matrix(Z, synth.sigma_for(0.3, n, d), 7)
+    A = np.triu(A) + np.triu(A, 1).T
+    As = oracle_matrix(A, fmt)
+    Y, w, _ = O.spectral_subspace(As, d)
+    X0_ref = O.sgn_blocks(Y, d)
+    X0 = torch.empty((n * d, d), dtype=xdtype(fmt), device="cuda")
+    ws = P.workspace(n, d, fmt, symmetric=True)
+    tol = 1e-13 if fmt == P.F64 else 1e-5
+    info = P.init_spectral(packed_matrix(A, n, d, fmt), n, d, X0, ws, max_iters=400, tol=tol)
+    assert info["converged"] == 1
+    bound = 1e-9 if fmt == P.F64 else 2e-4
+    assert O.dist_F(host(X0), X0_ref) / math.sqrt(n) <= bound
+    assert np.allclose(info["ritz"][:d], w, rtol=1e-12 if fmt == P.F64 else 1e-5)
+
+
+@pytest.mark.parametrize("form", ["f32", "bf16+refine", "tol"])
+def test_packed_symmetric_solve_equals_full_symmetric_solve(form):
+    """sync_solve with symmetric = 1 on packed storage: the same initialization
+    and iterations as on the full layout, so the same result bit for bit."""
+    require_gpu()
+    n, d = 2000, 3
+    print(f"packed symmetric solve {form}", flush=True)
+    Z = torch.from_numpy(synth.haar_blocks(n, d, 21)).cuda()
+    sigma = synth.sigma_for(0.2, n, d)
+    A32 = P.generate(Z, sigma, 22, fmt=P.F32)
+    A32p = P.generate(Z, sigma, 22, fmt=P.F32, packed=True)
+    Af, Afp = P.stored(A32, P.F32), P.stored_packed(A32p, n, d, P.F32)
+    if form == "bf16+refine":
+        Am, Amp = P.convert(A32, P.BF16), P.convert_packed(A32p, n, d, P.BF16)
+        kw, kwp = dict(refine_iters=10, A_refine=Af), dict(refine_iters=10, A_refine=Afp)
+    else:
+        Am, Amp, kw, kwp = Af, Afp, {}, {}
+    tol, iters = (1e-6, 300) if form == "tol" else (0.0, 120)
+    ws = P.workspace(n, d, Am.fmt, symmetric=True)
+    Xf = torch.empty((n * d, d), dtype=torch.float32, device="cuda")
+    Xp = torch.empty_like(Xf)
+    inf_f = P.solve(Am, n, d, Xf, ws, max_iters=iters, tol=tol, symmetric=True, **kw)
+    inf_p = P.solve(Amp, n, d, Xp, ws, max_iters=iters, tol=tol, symmetric=True, **kwp)
+    torch.cuda.synchronize()
+    assert inf_p["iters"] == inf_f["iters"]
+    assert torch.equal(Xp, Xf)
+    # and the streaming (non-symmetric) solve's estimate, up to rounding
+    wsd = P.workspace(n, d, Am.fmt)
+    Xd = torch.empty_like(Xf)
+    P.solve(Am, n, d, Xd, wsd, max_iters=iters, tol=tol, **kw)
+    torch.cuda.synchronize()
+    Zh = Z.cpu().numpy()
+    ep, ed = O.alignment_error(host(Xp), Zh), O.alignment_error(host(Xd), Zh)
+    print(f"  iters {inf_p['iters']}, alignment error {ep:.9f} (streaming solve {ed:.9f})", flush=True)
+    assert abs(ep - ed) <= 1e-5 * ed
