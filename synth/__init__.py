@@ -35,7 +35,7 @@ __all__ = [
     "PHILOX_M0", "PHILOX_M1", "PHILOX_W0", "PHILOX_W1",
     "philox4x32_10", "noise_elements", "mask_blocks",
     "haar_blocks", "measurement_matrix", "measurement_rows",
-    "perturbed_start", "sigma_for", "TAG_NOISE", "TAG_MASK",
+    "perturbed_start", "sigma_for", "TAG_NOISE", "TAG_MASK", "stiefel_start",
 ]
 
 # Philox4x32 constants from the SC'11 paper / Random123 distribution.
@@ -182,3 +182,17 @@ def perturbed_start(Z: np.ndarray, eps: float, seed: int) -> np.ndarray:
 def sigma_for(c: float, n: int, d: int) -> float:
     """Noise level sigma = c * sqrt(n / d) (the scaling of Theorem 3.1)."""
     return float(c) * math.sqrt(n / d)
+
+
+def stiefel_start(n: int, d: int, p: int, seed: int) -> np.ndarray:
+    """n random d x p blocks with orthonormal rows (S_i S_i^T = I_d), stacked as
+    an (n*d, p) float64 array: the transposed Q factor of an i.i.d. Gaussian
+    p x d matrix, sign-corrected like ``haar_blocks`` (a Haar point of the
+    Stiefel manifold; a random start of the Burer-Monteiro relaxation)."""
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((n, p, d))
+    q, r = np.linalg.qr(g)                       # q: (n, p, d), orthonormal columns
+    s = np.sign(np.diagonal(r, axis1=1, axis2=2))
+    s[s == 0] = 1.0
+    q = q * s[:, None, :]
+    return np.ascontiguousarray(np.swapaxes(q, 1, 2).reshape(n * d, p))
