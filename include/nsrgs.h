@@ -361,6 +361,44 @@ int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps,
                int max_iters, double tol, void *X, void *ws, size_t ws_bytes,
                void *stream, const nsrgs_solve_opts *opts, nsrgs_info *info);
 
+/* ---- NS-RGS on the Stiefel manifold St(p, d)^n -----------------------------
+ * The extension of the method to the Stiefel manifold that the paper names
+ * as future work (Sec. 6), on St(p, d) = {S in R^{d x p} : S S^T = I_d}, the
+ * manifold of the Burer-Monteiro relaxation recalled in Sec. 1 (d <= p).
+ * The iterate S (device, n*d x p, row-major, block i rows [i d, (i+1) d)) is
+ * double for F64 storage of A, float for F32.  One step of Algorithm 2 with
+ * every d x d quantity widened to d x p:
+ *     G_i = (n - 1) S_i - sum_{j != i} A_ij S_j
+ *     P_i = G_i - sym(G_i S_i^T) S_i,   sym(M) = (M + M^T) / 2
+ *     F_i = S_i - mu P_i,   S_i <- Ts steps of S <- (3 S - S S^T S) / 2
+ * (mu <= 0: 1/n).  P_i is the orthogonal projection onto the tangent space
+ * at S_i; the Newton-Schulz steps tend to the polar factor of F_i.  At p = d
+ * and S_i in O(d) this is sync_step's iteration.  A (full layout, F64 or
+ * F32) is streamed once per step on the matrix cores; the d x p block
+ * arithmetic is FP64.  Limits: 2 <= n, 1 <= d <= p <= 32, n d p < 2^31.
+ * ws holds sync_stiefel_workspace_bytes(n, d, p, fmt) bytes (0 when
+ * unsupported), 256-byte aligned, prepared by sync_workspace_init; it is
+ * also a valid sync_workspace_bytes(n, d, fmt) workspace, so sync_read_info
+ * reads the monitors of the last step (relative change, max_i ||I - F_i
+ * F_i^T||_F).  sync_step_stiefel is asynchronous.
+ * sync_solve_stiefel runs at most max_iters steps from the start held in S
+ * (for p > d a random point of St(p, d)^n: the relaxation of Sec. 1) and
+ * writes the result to S; tol > 0 stops after the first step with
+ * ||S^{t+1} - S^t||_F / ||S^t||_F <= tol.  It waits for the stream and fills
+ * *info (nullable; init_residual, ritz and objective are not set).
+ * sync_stiefel_round writes X (n*d x d) with X_i = sgn(S_i V), V the p x d
+ * matrix of top-d eigenvectors of S^T S (FP64 Jacobi), the rounding of a
+ * Stiefel point to O(d)^n; it waits for the stream and returns
+ * NSRGS_ERR_NONFINITE if some S_i V is singular or not finite. */
+size_t sync_stiefel_workspace_bytes(int n, int d, int p, int fmt);
+int sync_step_stiefel(const nsrgs_matrix *A, int n, int d, int p, double mu, int ns_steps,
+                      const void *S_in, void *S_out, void *ws, size_t ws_bytes, void *stream);
+int sync_solve_stiefel(const nsrgs_matrix *A, int n, int d, int p, double mu, int ns_steps,
+                       int max_iters, double tol, void *S, void *ws, size_t ws_bytes,
+                       void *stream, nsrgs_info *info);
+int sync_stiefel_round(const void *S, int n, int d, int p, int fmt, void *X, void *ws,
+                       size_t ws_bytes, void *stream);
+
 /* ---- batched solves: many problems per launch -----------------------------
  * Independent problems of uneven size (n, d) share every launch.  The unit of
  * work is one panel of B d rows of one problem (B fixed per d); the last panel

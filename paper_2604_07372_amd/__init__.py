@@ -19,6 +19,7 @@ __all__ = [
     "Info", "solve_batched", "batch_rows_per_panel", "set_tuning", "get_tuning", "TuneEntry", "Server",
     "step_variants", "TuneResult", "step_symmetric", "symmetric_workspace_bytes",
     "BsrMatrix", "generate_bsr", "step_bsr", "PACKED_LD", "packed_elems", "stored_packed", "convert_packed",
+    "stiefel_workspace", "step_stiefel", "solve_stiefel", "stiefel_round",
 ]
 
 F64, F32, BF16, BF16_SPLIT, FP8_E4M3 = 0, 1, 2, 3, 4
@@ -159,6 +160,10 @@ def lib() -> ctypes.CDLL:
         "nsrgs_generate_measurement": (i32, [vp, i32, i32, dbl, ctypes.c_uint64, i32, dbl, i32, vp, i64, vp]),
         "nsrgs_convert": (i32, [vp, i32, i64, pm, vp]),
         "nsrgs_packed_elems": (i64, [i32, i32]),
+        "sync_stiefel_workspace_bytes": (sz, [i32, i32, i32, i32]),
+        "sync_step_stiefel": (i32, [pm, i32, i32, i32, dbl, i32, vp, vp, vp, sz, vp]),
+        "sync_solve_stiefel": (i32, [pm, i32, i32, i32, dbl, i32, i32, dbl, vp, vp, sz, vp, ctypes.POINTER(Info)]),
+        "sync_stiefel_round": (i32, [vp, i32, i32, i32, i32, vp, vp, sz, vp]),
         "nsrgs_convert_packed": (i32, [vp, i32, i32, pm, vp]),
         "nsrgs_set_tuning": (i32, [ctypes.POINTER(TuneEntry), i32]),
         "nsrgs_get_tuning": (i32, [ctypes.POINTER(TuneEntry), i32]),
@@ -366,6 +371,64 @@ def step_symmetric(A: StoredMatrix, n: int, d: int, X_in: torch.Tensor, X_out: t
     m = A.c()
     _check(lib().sync_step_symmetric(ctypes.byref(m), n, d, float(mu), int(ns_steps), X_in.data_ptr(),
                                      X_out.data_ptr(), ws.ptr, ws.nbytes, _stream()))
+
+
+class _StiefelWorkspace(Workspace):
+    """Workspace of the Stiefel calls (also a single-problem workspace of (n, d, fmt))."""
+
+    def __init__(self, n: int, d: int, p: int, fmt: int, device="cuda"):
+        nbytes = lib().sync_stiefel_workspace_bytes(n, d, p, fmt)
+        if nbytes == 0:
+            raise NsrgsError(1, f"invalid Stiefel workspace request n={n} d={d} p={p} fmt={fmt}")
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-buf.data_ptr()) % 256
+        self._buf = buf
+        self.tensor = buf[off: off + nbytes]
+        self.nbytes = nbytes
+        self.n, self.d, self.p, self.fmt = n, d, p, fmt
+        _check(lib().sync_workspace_init(self.ptr, nbytes, _stream()))
+
+
+def stiefel_workspace(n: int, d: int, p: int, fmt: int, device="cuda") -> Workspace:
+    return _StiefelWorkspace(n, d, p, fmt, device)
+
+
+def _check_s(S: torch.Tensor, nd: int, p: int, fmt: int, name: str):
+    if not S.is_cuda or S.dtype != _xdtype(fmt) or tuple(S.shape) != (nd, p) or not S.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {_xdtype(fmt)} CUDA tensor of shape ({nd}, {p})")
+
+
+def step_stiefel(A: StoredMatrix, n: int, d: int, p: int, S_in: torch.Tensor, S_out: torch.Tensor,
+                 ws: Workspace, mu: float = 0.0, ns_steps: int = 3) -> None:
+    """sync_step_stiefel: one NS-RGS step on St(p, d)^n (S: n*d x p, rows of each
+    d x p block orthonormal); ws from stiefel_workspace(n, d, p, fmt)."""
+    _check_s(S_in, n * d, p, A.fmt, "S_in")
+    _check_s(S_out, n * d, p, A.fmt, "S_out")
+    m = A.c()
+    _check(lib().sync_step_stiefel(ctypes.byref(m), n, d, p, float(mu), int(ns_steps), S_in.data_ptr(),
+                                   S_out.data_ptr(), ws.ptr, ws.nbytes, _stream()))
+
+
+def solve_stiefel(A: StoredMatrix, n: int, d: int, p: int, S: torch.Tensor, ws: Workspace, mu: float = 0.0,
+                  ns_steps: int = 3, max_iters: int = 100, tol: float = 0.0, check: bool = True) -> dict:
+    """sync_solve_stiefel: at most max_iters steps from the start held in S (result in S)."""
+    _check_s(S, n * d, p, A.fmt, "S")
+    m = A.c()
+    info = Info()
+    st = lib().sync_solve_stiefel(ctypes.byref(m), n, d, p, float(mu), int(ns_steps), int(max_iters), float(tol),
+                                  S.data_ptr(), ws.ptr, ws.nbytes, _stream(), ctypes.byref(info))
+    if check:
+        _check(st, allow=(5,))
+    out = info.as_dict(d)
+    out["status"] = st
+    return out
+
+
+def stiefel_round(S: torch.Tensor, n: int, d: int, p: int, fmt: int, X: torch.Tensor, ws: Workspace) -> None:
+    """sync_stiefel_round: X_i = sgn(S_i V), V the top-d eigenvectors of S^T S."""
+    _check_s(S, n * d, p, fmt, "S")
+    _check_x(X, n * d, d, fmt, "X")
+    _check(lib().sync_stiefel_round(S.data_ptr(), n, d, p, int(fmt), X.data_ptr(), ws.ptr, ws.nbytes, _stream()))
 
 
 def symmetric_workspace_bytes(n: int, d: int, fmt: int) -> int:

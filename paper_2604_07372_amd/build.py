@@ -30,7 +30,7 @@ LIB = os.path.join(PKG, "libnsrgs.so")
 SOURCES = (["batched_f64.hip", "batched_f32.hip", "batched_bf16.hip"]
            + [f"symmetric_{f}.hip" for f in ("split", "f64", "bf16", "f32")]
            + [f"stream_{f}_{part}.hip" for f in ("fp8", "split", "f64", "bf16", "f32") for part in ("m0c", "m0b", "m0a", "m1")]
-           + ["stream.hip", "init.hip", "gen.hip", "runtime.hip", "batched.hip", "server.hip", "autotune.hip", "symmetric.hip", "bsr.hip", "noalloc.hip", "wide.hip"])
+           + ["stream.hip", "init.hip", "gen.hip", "runtime.hip", "batched.hip", "server.hip", "autotune.hip", "symmetric.hip", "bsr.hip", "noalloc.hip", "wide.hip", "stiefel.hip"])
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -319,7 +319,10 @@ static int check_step_io(const nsrgs_matrix *A, int n, int d, double mu, int ns_
 }
 
 // ---- matrix-core path (wide.h): d up to 32 and the three retractions ------
-static WideArgs wide_args(const nsrgs_matrix *A, int n, int d, void *ws) {
+}  // extern "C"
+
+namespace nsrgs {
+WideArgs wide_args(const nsrgs_matrix *A, int n, int d, void *ws) {
   const WsLayout L = layout(n, d, A->fmt);
   const WideLayout W = wide_layout(n, d, A->fmt);
   char *base = static_cast<char *>(ws) + L.wide;
@@ -328,6 +331,7 @@ static WideArgs wide_args(const nsrgs_matrix *A, int n, int d, void *ws) {
   a.ld = A->ld;
   a.n = n;
   a.d = d;
+  a.p = d;
   a.nd = n * d;
   a.part = base + W.part;
   a.xs = base + W.xs;
@@ -340,6 +344,9 @@ static WideArgs wide_args(const nsrgs_matrix *A, int n, int d, void *ws) {
   a.g = wide_geom(n, d, A->fmt);
   return a;
 }
+}  // namespace nsrgs
+
+extern "C" {
 
 static WideCtl *wide_ctl(void *ws, int n, int d, int fmt) {
   return reinterpret_cast<WideCtl *>(static_cast<char *>(ws) + layout(n, d, fmt).wide + wide_layout(n, d, fmt).ctl);

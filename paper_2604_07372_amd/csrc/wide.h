@@ -98,8 +98,14 @@ struct WideArgs {
   const int *stop_flag;
   int no_diag;         // 1: the partials already exclude A_ii and A is not read
                        //    (block-sparse storage); A_ii counts as zero
+  int p;               // columns of X (d, or the Stiefel width p >= d)
   WideGeom g;
 };
+
+// The arguments of a matrix-core launch bound to the single-problem
+// workspace ws (its matrix-core region; sync_workspace_bytes layout) with
+// p = d (runtime.hip).
+WideArgs wide_args(const nsrgs_matrix *A, int n, int d, void *ws);
 
 int wide_supported_fmt(int fmt);
 hipError_t launch_wide_step(int fmt, const WideArgs &a, hipStream_t s);
@@ -116,5 +122,14 @@ hipError_t launch_wide_init_polar(int fmt, const void *Y, void *X0, int n, int d
                                   hipStream_t s);
 hipError_t launch_wide_init_finish(DevCtl *ctl, WideCtl *wctl, int d, hipStream_t s);
 hipError_t launch_wide_ctl_reset(WideCtl *wctl, hipStream_t s);
+
+// NS-RGS on St(p, d)^n (d x p blocks with orthonormal rows, p <= 32): the
+// product A S (p columns), the per-block Stiefel step and the monitors.
+hipError_t launch_wide_stiefel_step(int fmt, const WideArgs &a, hipStream_t s);
+// Rounding of S to O(d)^n: X_i = sgn(S_i V), V the top-d eigenvectors of
+// S^T S (p x p, FP64 Jacobi).  gram: kWideGramGroups p^2 doubles; basis:
+// p d doubles; ctl->init_bad is set if a polar factor fails.
+hipError_t launch_stiefel_round(int fmt, const void *S, int n, int d, int p, double *gram, double *basis,
+                                void *X, DevCtl *ctl, hipStream_t s);
 
 }  // namespace nsrgs

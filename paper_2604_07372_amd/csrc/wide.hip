@@ -803,6 +803,196 @@ __global__ void wide_ctl_reset_kernel(WideCtl *w) {
   w->have_const = 0;
 }
 
+
+// ---------------------------------------------------------------------------
+// NS-RGS on the Stiefel manifold St(p, d) = {S in R^{d x p} : S S^T = I_d},
+// the extension of the method the paper names as future work (Sec. 6), for
+// d <= p <= 32: every step of Algorithm 2 written for d x p blocks,
+//   G_i = (n - 1) S_i - sum_{j != i} A_ij S_j
+//   P_i = G_i - sym(G_i S_i^T) S_i          (projection onto T_S St)
+//   F_i = S_i - mu P_i,   S_i <- Ts steps of S <- (3 S - S S^T S) / 2.
+// At p = d and S_i in O(d) the projection is Algorithm 2's.
+// ---------------------------------------------------------------------------
+// out (r x c) = op(A) op(B) over an inner dimension m, row-major in LDS:
+// A is r x m (m x r when TA), B is m x c (c x m when TB).  Ends with a barrier.
+template <bool TA, bool TB>
+__device__ inline void wmm_rect(double *out, const double *A, const double *B, int r, int m, int c) {
+  for (int e = threadIdx.x; e < r * c; e += blockDim.x) {
+    const int i = e / c, k = e % c;
+    double s0 = 0.0, s1 = 0.0;
+    int j = 0;
+    for (; j + 1 < m; j += 2) {
+      s0 += (TA ? A[j * r + i] : A[i * m + j]) * (TB ? B[k * m + j] : B[j * c + k]);
+      s1 += (TA ? A[(j + 1) * r + i] : A[i * m + j + 1]) * (TB ? B[k * m + j + 1] : B[(j + 1) * c + k]);
+    }
+    if (j < m) s0 += (TA ? A[j * r + i] : A[i * m + j]) * (TB ? B[k * m + j] : B[j * c + k]);
+    out[e] = s0 + s1;
+  }
+  __syncthreads();
+}
+
+// One workgroup per block i: C_i from the partials (diagonal block included,
+// as the product streams whole rows), the Stiefel step in FP64, S_i^{t+1} and
+// the block's monitors (||S^{t+1} - S^t||^2, ||S^t||^2, ||I - F_i F_i^T||_F).
+template <typename T>
+__global__ void __launch_bounds__(256) wide_stiefel_epilogue_kernel(WideArgs a) {
+  constexpr int NE = kWideMaxD * kWideMaxD;
+  __shared__ double sm[7][NE];
+  __shared__ double s_scr4[4 * kMaxWaves];
+  if (a.stop_flag) {
+    if (__atomic_load_n(a.stop_flag, __ATOMIC_RELAXED)) return;   // uniform
+  }
+  const int i = blockIdx.x, d = a.d, p = a.p, dd = d * d, dp = d * p, tid = threadIdx.x;
+  double *S = sm[0], *C = sm[1], *Ad = sm[2], *G = sm[3], *F = sm[4], *M = sm[5], *W = sm[6];
+  const T *__restrict__ Sin = static_cast<const T *>(a.X_in);
+  const T *__restrict__ Pp = static_cast<const T *>(a.part);
+  const T *__restrict__ A = static_cast<const T *>(a.A);
+  for (int e = tid; e < dp; e += blockDim.x) {
+    const int r = e / p, k = e % p;
+    const int64_t row = (int64_t)i * d + r;
+    S[e] = (double)Sin[row * p + k];
+    double c = 0.0;
+    for (int s = 0; s < a.g.ks; ++s) c += (double)Pp[((size_t)s * a.g.rows_pad + row) * 32 + k];
+    C[e] = c;
+  }
+  for (int e = tid; e < dd; e += blockDim.x) {
+    const int64_t row = (int64_t)i * d + e / d;
+    Ad[e] = (double)A[row * a.ld + (int64_t)i * d + e % d];
+  }
+  __syncthreads();
+  wmm_rect<false, false>(W, Ad, S, d, d, p);                    // A_ii S_i
+  const double nm1 = (double)(a.n - 1), mu = a.mu;
+  for (int e = tid; e < dp; e += blockDim.x) G[e] = nm1 * S[e] - (C[e] - W[e]);
+  __syncthreads();
+  wmm_rect<false, true>(M, G, S, d, p, d);                      // G_i S_i^T
+  for (int e = tid; e < dd; e += blockDim.x) Ad[e] = 0.5 * (M[e] + M[(e % d) * d + e / d]);
+  __syncthreads();
+  wmm_rect<false, false>(W, Ad, S, d, d, p);                    // sym(G_i S_i^T) S_i
+  for (int e = tid; e < dp; e += blockDim.x) F[e] = S[e] - mu * (G[e] - W[e]);
+  __syncthreads();
+  wmm_rect<false, true>(M, F, F, d, p, d);                      // F_i F_i^T
+  double red[4] = {0.0, 0.0, 0.0, 0.0};                         // x2 dx2 nonfin def2
+  for (int e = tid; e < dd; e += blockDim.x) {
+    const double v = ((e / d) == (e % d) ? 1.0 : 0.0) - M[e];
+    red[3] += v * v;
+  }
+  double *cur = F, *nxt = G;
+  for (int st = 0; st < a.ns_steps; ++st) {
+    if (st > 0) wmm_rect<false, true>(M, cur, cur, d, p, d);
+    wmm_rect<false, false>(W, M, cur, d, d, p);                 // (S S^T) S
+    for (int e = tid; e < dp; e += blockDim.x) nxt[e] = 1.5 * cur[e] - 0.5 * W[e];
+    __syncthreads();
+    double *t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  T *__restrict__ So = static_cast<T *>(a.X_out);
+  for (int e = tid; e < dp; e += blockDim.x) {
+    const T v = (T)cur[e];
+    So[((int64_t)i * d + e / p) * p + e % p] = v;
+    const double dv = (double)v - S[e];
+    red[0] += S[e] * S[e];
+    red[1] += dv * dv;
+    red[2] += isfinite(v) ? 0.0 : 1.0;
+  }
+  block_sum_n<4>(red, s_scr4);
+  if (tid == 0) {
+    const double dmax = sqrt(red[3]);
+    a.stats[i] = WideStat{red[1], red[0], dmax, (red[2] != 0.0 || !isfinite(dmax)) ? 1.0 : 0.0, 0.0, 0.0, 0.0, 0.0};
+  }
+}
+
+// One wave: the Gram S^T S from its partial sums, its eigenvectors by FP64
+// cyclic Jacobi (rotations accumulated in E), and the d columns of the largest
+// eigenvalues into basis (p x d, descending).
+__global__ void __launch_bounds__(64) stiefel_basis_kernel(const double *gram, int p, int d, double *basis) {
+  constexpr int NE = kWideMaxD * kWideMaxD;
+  __shared__ double M[NE], E[NE];
+  __shared__ double s_scr[kMaxWaves];
+  __shared__ int order[kWideMaxD];
+  const int k = threadIdx.x, pp = p * p;
+  for (int e = k; e < pp; e += blockDim.x) {
+    double s = 0.0;
+    for (int g = 0; g < kWideGramGroups; ++g) s += gram[(size_t)g * pp + e];
+    M[e] = s;
+    E[e] = (e / p == e % p) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int e = k; e < pp; e += blockDim.x) {   // exact symmetry before the rotations
+    const int r = e / p, c = e % p;
+    if (r < c) {
+      const double v = 0.5 * (M[e] + M[c * p + r]);
+      M[e] = v;
+      M[c * p + r] = v;
+    }
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int e = k; e < pp; e += blockDim.x) {
+      const double v = M[e] * M[e];
+      tot += v;
+      if (e / p != e % p) off += v;
+    }
+    off = block_sum(off, s_scr);
+    tot = block_sum(tot, s_scr);
+    if (off <= 1e-30 * tot) break;
+    for (int a = 0; a < p - 1; ++a)
+      for (int b = a + 1; b < p; ++b) {
+        const double apq = M[a * p + b];
+        if (apq == 0.0) continue;                       // uniform: every lane reads the same value
+        const double theta = (M[b * p + b] - M[a * p + a]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+        __syncthreads();
+        if (k < p) {                                    // rows a, b of M
+          const double ma = M[a * p + k], mb = M[b * p + k];
+          M[a * p + k] = c * ma - sn * mb;
+          M[b * p + k] = sn * ma + c * mb;
+        }
+        __syncthreads();
+        if (k < p) {                                    // columns a, b of M and of E
+          const double ma = M[k * p + a], mb = M[k * p + b];
+          M[k * p + a] = c * ma - sn * mb;
+          M[k * p + b] = sn * ma + c * mb;
+          const double ea = E[k * p + a], eb = E[k * p + b];
+          E[k * p + a] = c * ea - sn * eb;
+          E[k * p + b] = sn * ea + c * eb;
+        }
+        __syncthreads();
+      }
+  }
+  if (k == 0) {
+    for (int j = 0; j < p; ++j) order[j] = j;
+    for (int x = 0; x < p; ++x)
+      for (int y = x + 1; y < p; ++y)
+        if (M[order[y] * p + order[y]] > M[order[x] * p + order[x]]) {
+          const int t = order[x];
+          order[x] = order[y];
+          order[y] = t;
+        }
+  }
+  __syncthreads();
+  for (int e = k; e < p * d; e += blockDim.x) basis[e] = E[(e / d) * p + order[e % d]];
+}
+
+// One workgroup per block: X_i = sgn(S_i V) (d x d, FP64 polar).
+template <typename T>
+__global__ void __launch_bounds__(256) stiefel_round_kernel(const T *S, const double *basis, T *X, int d, int p,
+                                                            DevCtl *ctl) {
+  constexpr int NE = kWideMaxD * kWideMaxD;
+  __shared__ double sS[NE], sV[NE], sM[NE], sN[NE], sQ[NE];
+  __shared__ double s_scr[kMaxWaves];
+  const int b = blockIdx.x, dd = d * d;
+  for (int e = threadIdx.x; e < d * p; e += blockDim.x) sS[e] = (double)S[(int64_t)b * d * p + e];
+  for (int e = threadIdx.x; e < p * d; e += blockDim.x) sV[e] = basis[e];
+  __syncthreads();
+  wmm_rect<false, false>(sQ, sS, sV, d, p, d);
+  const int steps = wide_polar(sQ, sM, sN, d, s_scr);
+  for (int e = threadIdx.x; e < dd; e += blockDim.x) X[(int64_t)b * dd + e] = (T)sQ[e];
+  if (threadIdx.x == 0 && steps < 0) atomicOr(&ctl->init_bad, 1);
+}
+
 // ---------------------------------------------------------------------------
 // Geometry, workspace and launches.
 // ---------------------------------------------------------------------------
@@ -869,7 +1059,7 @@ static void wide_launch_product_t(const WideArgs &a, hipStream_t s) {
   const int total = a.g.row_tiles * a.g.ks;
   const int wgs = a.g.xcd_remap ? 8 * ((total + 7) / 8) : total;
   hipLaunchKernelGGL((wide_xs_kernel<T, NT, MT>), dim3((unsigned)((xs_elems + 255) / 256)), dim3(256), 0, s,
-                     static_cast<const T *>(a.X_in), a.nd, a.d, a.g.steps, static_cast<T *>(a.xs), a.stop_flag);
+                     static_cast<const T *>(a.X_in), a.nd, a.p, a.g.steps, static_cast<T *>(a.xs), a.stop_flag);
   hipLaunchKernelGGL((wide_product_kernel<T, NT, MT>), dim3(wgs), dim3(256), 0, s, a);
 }
 
@@ -986,6 +1176,43 @@ hipError_t launch_wide_init_finish(DevCtl *ctl, WideCtl *wctl, int d, hipStream_
 
 hipError_t launch_wide_ctl_reset(WideCtl *wctl, hipStream_t s) {
   hipLaunchKernelGGL(wide_ctl_reset_kernel, dim3(1), dim3(64), 0, s, wctl);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t wide_stiefel_step_t(const WideArgs &a, hipStream_t s) {
+  hipError_t e;
+  if ((e = wide_launch_product<T>(a, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(wide_stiefel_epilogue_kernel<T>, dim3(a.n), dim3(256), 0, s, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(wide_finish_kernel, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_wide_stiefel_step(int fmt, const WideArgs &a, hipStream_t s) {
+  if (fmt == NSRGS_A_F64) return wide_stiefel_step_t<double>(a, s);
+  if (fmt == NSRGS_A_F32) return wide_stiefel_step_t<float>(a, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_stiefel_round(int fmt, const void *S, int n, int d, int p, double *gram, double *basis,
+                                void *X, DevCtl *ctl, hipStream_t s) {
+  hipError_t e;
+  if (fmt == NSRGS_A_F64)
+    hipLaunchKernelGGL(wide_gram_kernel<double>, dim3(kWideGramGroups), dim3(256), 0, s,
+                       static_cast<const double *>(S), n * d, p, gram, (const int *)nullptr);
+  else
+    hipLaunchKernelGGL(wide_gram_kernel<float>, dim3(kWideGramGroups), dim3(256), 0, s,
+                       static_cast<const float *>(S), n * d, p, gram, (const int *)nullptr);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(stiefel_basis_kernel, dim3(1), dim3(64), 0, s, gram, p, d, basis);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (fmt == NSRGS_A_F64)
+    hipLaunchKernelGGL(stiefel_round_kernel<double>, dim3(n), dim3(256), 0, s, static_cast<const double *>(S), basis,
+                       static_cast<double *>(X), d, p, ctl);
+  else
+    hipLaunchKernelGGL(stiefel_round_kernel<float>, dim3(n), dim3(256), 0, s, static_cast<const float *>(S), basis,
+                       static_cast<float *>(X), d, p, ctl);
   return hipGetLastError();
 }
 

@@ -284,3 +284,31 @@ def test_packed_storage_is_refused_where_it_is_not_read():
     assert L.nsrgs_convert_packed(None, n, d, ctypes.byref(out), None) == 1
     # the generator writes packed storage for d <= 32 only
     assert L.nsrgs_generate_measurement(16, n, 33, 1.0, 0, 0, 1.0, P.F32, 16, P.PACKED_LD, None) == 1
+
+
+def test_stiefel_entry_points_reject_on_the_host():
+    L = P.lib()
+    n, d, p = 100, 3, 5
+    ws = L.sync_stiefel_workspace_bytes(n, d, p, P.F32)
+    assert ws >= L.sync_workspace_bytes(n, d, P.F32) + n * d * p * 4
+    assert L.sync_stiefel_workspace_bytes(n, 4, 3, P.F32) == 0        # p < d
+    assert L.sync_stiefel_workspace_bytes(n, 3, 33, P.F32) == 0       # p > 32
+    assert L.sync_stiefel_workspace_bytes(n, 3, 5, P.BF16) == 0       # F64 / F32 only
+    assert L.sync_stiefel_workspace_bytes(1, 3, 5, P.F32) == 0
+    m = _mat()
+    info = P.Info()
+    big = 1 << 30
+    assert L.sync_step_stiefel(ctypes.byref(m), n, 4, 3, 0.0, 3, 4096, 1 << 20, 256, big, None) == 1
+    assert L.sync_step_stiefel(ctypes.byref(_mat(P.BF16)), n, d, p, 0.0, 3, 4096, 1 << 20, 256, big, None) == 2
+    assert L.sync_step_stiefel(ctypes.byref(m), n, d, p, 0.0, 3, 4096, 1 << 20, 256, ws - 256, None) == 3
+    assert L.sync_step_stiefel(ctypes.byref(m), n, d, p, 0.0, 3, 4096, 4096 + 64, 256, ws, None) == 1   # overlap
+    assert L.sync_step_stiefel(ctypes.byref(m), n, d, p, float("nan"), 3, 4096, 1 << 20, 256, ws, None) == 1
+    pk = P._Matrix(P.F32, 16, None, None, P.PACKED_LD)
+    assert L.sync_step_stiefel(ctypes.byref(pk), n, d, p, 0.0, 3, 4096, 1 << 20, 256, ws, None) == 2
+    assert L.sync_solve_stiefel(ctypes.byref(m), n, d, p, 0.0, 3, -1, 0.0, 4096, 256, ws, None,
+                                ctypes.byref(info)) == 1
+    assert L.sync_solve_stiefel(ctypes.byref(m), n, d, p, 0.0, 3, 10, 0.0, None, 256, ws, None,
+                                ctypes.byref(info)) == 1
+    assert L.sync_stiefel_round(4096, n, d, p, P.F32, 4096, 256, ws, None) == 1            # overlap
+    assert L.sync_stiefel_round(4096, n, d, p, P.FP8_E4M3, 1 << 20, 256, big, None) == 2
+    assert L.sync_stiefel_round(4096, n, d, p, P.F32, 1 << 20, 256, 1024, None) == 3
