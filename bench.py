@@ -53,32 +53,64 @@ def traffic_from_profile(name="step_f32_n20000_d3_counters.json", files=("stream
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(budget_s: float = 12.0):
-    """The FP64 oracle's NS-RGS step timed on the host cores, on a bounded
-    sample: the n = 2000 sub-instance of the same model (A 6000 x 6000), one
-    oracle step per repetition, scaled to n = 20000 by the (nd)^2 cost ratio."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(budget_s: float = 8.0, blocks: int = 200):
+    """The FP64 oracle timed on the host cores on a bounded sample of the
+    headline workload itself: oracle.block_step (Algorithm 2 for one block i,
+    from the d rows of A that hold A_i1..A_in and the whole iterate) for
+    `blocks` sampled blocks of the n = 20000 problem, with every host thread
+    and with one thread.  The rows are regenerated on the host by the
+    generator's twin, untimed.  A Jacobi sweep does the same work for every
+    block, so one iteration takes n times the mean time per block."""
     import numpy as np
     import synth
     from oracle import nsrgs as O
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
+        threadpool_limits = None
         threads = os.cpu_count()
-    n, d = 2000, D
+    n, d = N, D
+    rng = np.random.default_rng(3)
+    sample = np.sort(rng.choice(n, blocks, replace=False))
     Z = synth.haar_blocks(n, d, SEED)
-    A = synth.measurement_matrix(Z, synth.sigma_for(C_NOISE, n, d), SEED)
+    rows = (sample[:, None] * d + np.arange(d)).ravel()
+    A_rows = synth.measurement_rows(Z, synth.sigma_for(C_NOISE, n, d), SEED, rows)
     X = synth.perturbed_start(Z, 0.05, SEED + 1)
-    O.rgs_step(A, X, d, Ts=3)
-    reps, t0 = 0, time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        X = O.rgs_step(A, X, d, Ts=3).X
-        reps += 1
-    dt = (time.perf_counter() - t0) / reps
-    scale = (N * D / (n * d)) ** 2
-    return {"value": 1.0 / (dt * scale), "unit": "iter/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{reps} FP64 oracle steps on the n=2000 sub-instance (A 6000x6000), "
-                      f"{dt * 1e3:.2f} ms each, scaled by (60000/6000)^2 = {scale:.0f} to n=20000"}
+
+    def per_block(limit_s):
+        O.block_step(A_rows[:d], X, d, int(sample[0]), Ts=3)
+        done, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < limit_s:
+            k = done % blocks
+            O.block_step(A_rows[k * d:(k + 1) * d], X, d, int(sample[k]), Ts=3)
+            done += 1
+        return (time.perf_counter() - t0) / done, done
+
+    t_all, c_all = per_block(budget_s)
+    t_one, c_one = None, 0
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            t_one, c_one = per_block(budget_s / 2)
+    return {"value": 1.0 / (t_all * n), "unit": "iter/s", "cores": int(threads), "kind": "oracle",
+            "cpu_model": _cpu_model(),
+            "value_1_thread": (1.0 / (t_one * n)) if t_one else None,
+            "sample": f"oracle.block_step on {blocks} sampled blocks of the n=20000, d=3 problem "
+                      f"(rows regenerated on the host): {c_all} block steps at {t_all * 1e3:.3f} ms each with "
+                      f"{threads} threads, {c_one} at {(t_one or 0) * 1e3:.3f} ms with 1 thread; "
+                      f"one iteration = {n} block steps"}
 
 
 def batched_bench(iters: int = 100, base_iters: int = 10, count: int = 512, seed0: int = 1000):
@@ -210,11 +242,15 @@ def masked_bench(Zd, sigma, dense_ms: float, steps: int, warmup: int, p: float =
     return out
 
 
-def serving_bench(window_s: float = 10.0, rate: float = 50.0, seed0: int = 5000):
-    """Poisson arrivals at `rate` requests/s for `window_s` seconds; each request:
-    n log-uniform in [100, 20000], d in {3, 4}, sigma = 0.2 sqrt(n/d), Haar ground
-    truth, A generated on the device and stored in BF16, stop at relative change
-    1e-6 or 300 iterations.  Reports p50/p99 latency (submit to result) and solves/s."""
+def serving_bench(window_s: float = 60.0, warmup_s: float = 10.0, rate: float = 50.0, seed0: int = 5000):
+    """Poisson arrivals at `rate` requests/s for warmup_s + window_s seconds;
+    each request: n log-uniform in [100, 20000], d in {3, 4}, sigma = 0.2
+    sqrt(n/d), Haar ground truth, A generated on the device and stored in
+    BF16, stop at relative change 1e-6 or 300 iterations.  Requests that
+    arrive in the first warmup_s seconds warm the server up and are not
+    counted.  Reports p50/p99 latency (submit to result) of the measured
+    requests, its parts (queueing, ingest = generation + spectral
+    initialization, iterations), and solves/s."""
     import numpy as np
     import paper_2604_07372_amd as P
     import synth
@@ -222,35 +258,55 @@ def serving_bench(window_s: float = 10.0, rate: float = 50.0, seed0: int = 5000)
     arrivals, reqs = [], []
     t = 0.0
     k = 0
+    total = warmup_s + window_s
     while True:
         t += rng.exponential(1.0 / rate)
-        if t > window_s:
+        if t > total:
             break
         n = int(np.floor(np.exp(rng.uniform(np.log(100), np.log(20000)))))
         d = int(rng.choice([3, 4]))
         reqs.append((synth.haar_blocks(n, d, seed0 + k), synth.sigma_for(C_NOISE, n, d), seed0 + k))
         arrivals.append(t)
         k += 1
-    print(f"[bench] serving: {len(reqs)} requests over {window_s:.0f} s", file=sys.stderr, flush=True)
+    print(f"[bench] serving: {len(reqs)} requests over {total:.0f} s ({warmup_s:.0f} s warm-up)",
+          file=sys.stderr, flush=True)
+    ids = []
     with P.Server(fmt=P.BF16) as srv:
         base = srv.clock()
         for (Z, sigma, seed), ta in zip(reqs, arrivals):
             while srv.clock() - base < ta:
                 time.sleep(0.0002)
-            srv.submit(Z, sigma, seed, tol=1e-6, max_iters=300)
+            ids.append(srv.submit(Z, sigma, seed, tol=1e-6, max_iters=300)[0])
         srv.wait_idle(300.0)
         res = srv.poll(len(reqs) + 8)
         st = srv.stats()
-    iters = [r["iters"] for r in res]
-    out = {"requests": len(reqs), "rate_per_s": rate, "window_s": window_s,
-           "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
-           "mean_latency_s": st["mean_latency_s"], "solves_per_s": st["solves_per_s"],
-           "completed": st["completed"], "rejected": st["rejected"],
-           "converged": sum(r["converged"] for r in res), "max_active_seen": st["max_active_seen"],
+    measured = {i for i, ta in zip(ids, arrivals) if ta >= warmup_s}
+    mres = [r for r in res if r["id"] in measured]
+    lat = np.array([r["t_done"] - r["t_submit"] for r in mres])
+    queue = np.array([r["t_admit"] - r["t_submit"] for r in mres])
+    ingest = np.array([r["t_start"] - r["t_admit"] for r in mres])
+    solve = np.array([r["t_done"] - r["t_start"] for r in mres])
+    iters = [r["iters"] for r in mres]
+    span = (max(r["t_done"] for r in mres) - (base + warmup_s)) if mres else 0.0
+
+    def pct(v, q):
+        return float(np.percentile(v, q)) if len(v) else None
+
+    out = {"requests": len(mres), "warmup_requests": len(reqs) - len(measured), "rate_per_s": rate,
+           "window_s": window_s, "warmup_s": warmup_s,
+           "p50_latency_s": pct(lat, 50), "p99_latency_s": pct(lat, 99),
+           "mean_latency_s": float(lat.mean()) if len(lat) else None,
+           "solves_per_s": len(mres) / span if span > 0 else None,
+           "latency_parts_p50_s": {"queue": pct(queue, 50), "ingest": pct(ingest, 50), "iterations": pct(solve, 50)},
+           "latency_parts_p99_s": {"queue": pct(queue, 99), "ingest": pct(ingest, 99), "iterations": pct(solve, 99)},
+           "completed": sum(1 for r in mres if r["status"] in (0, 5)), "rejected": st["rejected"],
+           "converged": sum(r["converged"] for r in mres), "max_active_seen": st["max_active_seen"],
            "mean_iters": float(np.mean(iters)) if iters else 0.0,
            "pool_peak_GB": st["pool_peak_bytes"] / 1e9}
     print(f"[bench] serving: p50 {out['p50_latency_s'] * 1e3:.1f} ms, p99 {out['p99_latency_s'] * 1e3:.1f} ms, "
-          f"{out['solves_per_s']:.1f} solves/s", file=sys.stderr, flush=True)
+          f"{out['solves_per_s']:.1f} solves/s; p50 parts: queue {out['latency_parts_p50_s']['queue'] * 1e3:.1f} ms, "
+          f"ingest {out['latency_parts_p50_s']['ingest'] * 1e3:.1f} ms, "
+          f"iterations {out['latency_parts_p50_s']['iterations'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
     return out
 
 
@@ -341,6 +397,73 @@ def alignment_error(X, Z) -> float:
     return float(np.linalg.norm(X - Z @ (U @ Vt)) / math.sqrt(Z.shape[0] // d))
 
 
+def config1_bench(steps: int = 500, warmup: int = 50, iters: int = SOLVE_ITERS):
+    """n = 2000, d = 3, FP32 A (6000 x 6000, 144 MB).  The whole A fits the
+    256 MB Infinity Cache (MALL), so after the first pass sync_step reads it
+    from there: its GB/s is cache bandwidth, not HBM.  Times sync_step, and
+    for sigma in {0.5, 0.1 sqrt(n/d), 0.3 sqrt(n/d)} runs the 200-iteration
+    solve and reports its alignment error and its distance to the same solve
+    on the FP64 copy of A (the FP64 path, which the tests hold to the FP64
+    oracle at 1e-10)."""
+    import numpy as np
+    import torch
+    import paper_2604_07372_amd as P
+    import synth
+    n, d = 2000, 3
+    nd = n * d
+    out = {"n": n, "d": d, "a_bytes": nd * nd * 4, "mall_resident": True}
+    Z = synth.haar_blocks(n, d, 1)
+    Zd = torch.from_numpy(Z).cuda()
+    sigma = synth.sigma_for(0.2, n, d)
+    A32 = P.stored(P.generate(Zd, sigma, 1, fmt=P.F32), P.F32)
+    ws = P.workspace(n, d, P.F32)
+    X0 = torch.from_numpy(synth.perturbed_start(Z, 0.05, 2)).cuda().float()
+    Xa, Xb = X0.clone(), torch.empty_like(X0)
+    for _ in range(warmup):
+        P.step(A32, n, d, Xa, Xb, ws)
+        Xa, Xb = Xb, Xa
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        P.step(A32, n, d, Xa, Xb, ws)
+        Xa, Xb = Xb, Xa
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / steps
+    alg = nd * nd * 4 + 2 * nd * d * 4
+    out.update({"ms_per_step": ms, "iters_per_s": 1e3 / ms, "alg_GBps": alg / (ms * 1e-3) / 1e9,
+                "note": "A resident in the 256 MB MALL: GB/s above the 8 TB/s HBM peak are cache bandwidth"})
+    solves = {}
+    for label, sg in (("0.5", 0.5), ("0.1sqrt(n/d)", synth.sigma_for(0.1, n, d)),
+                      ("0.3sqrt(n/d)", synth.sigma_for(0.3, n, d))):
+        res = {}
+        for fmt in (P.F32, P.F64):
+            Am = P.stored(P.generate(Zd, sg, 3, fmt=fmt), fmt)
+            w = P.workspace(n, d, fmt)
+            X = torch.empty((nd, d), dtype=torch.float64 if fmt == P.F64 else torch.float32, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P.solve(Am, n, d, X, w, ns_steps=3, max_iters=iters)
+            res[fmt] = (X.cpu().double().numpy(), time.perf_counter() - t0)
+        e32, e64 = alignment_error(res[P.F32][0], Z), alignment_error(res[P.F64][0], Z)
+        solves[label] = {"sigma": sg, "solve_s_f32": res[P.F32][1], "align_err_f32": e32, "align_err_f64": e64,
+                         "align_err_rel_vs_f64": abs(e32 - e64) / e64,
+                         "dF_vs_f64_sqrt_n": dist_F(res[P.F32][0], res[P.F64][0]) / math.sqrt(n)}
+    out["solves"] = solves
+    print(f"[bench] config n=2000: {ms * 1e3:.1f} us/iter, {out['alg_GBps']:.0f} GB/s (MALL-resident); "
+          + ", ".join(f"sigma {k}: err {v['align_err_f32']:.5f} (rel vs f64 {v['align_err_rel_vs_f64']:.1e})"
+                      for k, v in solves.items()), file=sys.stderr, flush=True)
+    return out
+
+
+def dist_F(X, Y) -> float:
+    """min over Q in O(d) of ||X - Y Q||_F, Q from the SVD of Y^T X."""
+    import numpy as np
+    U, _, Vt = np.linalg.svd(Y.T @ X)
+    return float(np.linalg.norm(X - Y @ (U @ Vt)))
+
+
 def copy_calibration(reps: int = 3) -> int:
     """A plain copy of known size (1 GiB read + 1 GiB written per launch), for
     scaling the HBM byte counters of a profiler to bytes."""
@@ -368,7 +491,9 @@ def main(argv=None):
     ap.add_argument("--no-masked", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-table1", action="store_true")
-    ap.add_argument("--serving-window", type=float, default=10.0)
+    ap.add_argument("--no-config1", action="store_true")
+    ap.add_argument("--serving-window", type=float, default=60.0)
+    ap.add_argument("--serving-warmup", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--tuning", default="",
@@ -513,6 +638,7 @@ def main(argv=None):
     if a.save_tuning:
         autotune.save_table(a.save_tuning)
     solve = {}
+    finals = {}
     if not a.no_solve:
         pred = sigma * math.sqrt(d * (d - 1) / (2.0 * n))
         for name in fmts:
@@ -526,7 +652,9 @@ def main(argv=None):
             t0 = time.perf_counter()
             info = P.solve(Am, n, d, X, ws, ns_steps=3, max_iters=SOLVE_ITERS, **kw)
             dt = time.perf_counter() - t0
-            e = alignment_error(X.cpu().double().numpy(), Z)
+            Xh = X.cpu().double().numpy()
+            finals[name] = Xh
+            e = alignment_error(Xh, Z)
             solve[name] = {"solve_s": dt, "align_err": e, "first_order_pred": pred,
                            "iters": info["iters"], "init_residual": info["init_residual"],
                            "refine_iters": kw.get("refine_iters", 0)}
@@ -549,6 +677,28 @@ def main(argv=None):
                                               "refine_iters": kw.get("refine_iters", 0)}
                 print(f"[bench] solve {name} symmetric: {dt:.3f} s, align err {e:.6f}", file=sys.stderr, flush=True)
                 del ws
+        # Error of each precision form against the FP64 solve: the same solve on
+        # the FP64 A (the generator's values before rounding), on the FP64 path,
+        # which the tests hold to the FP64 oracle at 1e-10.  Reported over the
+        # whole iterate and over a 2000-block subsample.
+        A64 = P.generate(Zd, sigma, SEED, fmt=P.F64)
+        ws64 = P.workspace(n, d, P.F64)
+        X64 = torch.empty((nd, d), dtype=torch.float64, device=dev)
+        P.solve(P.stored(A64, P.F64), n, d, X64, ws64, ns_steps=3, max_iters=SOLVE_ITERS)
+        X64h = X64.cpu().numpy()
+        del A64, ws64, X64
+        torch.cuda.empty_cache()
+        e64 = alignment_error(X64h, Z)
+        sub = np.sort(np.random.default_rng(9).choice(n, 2000, replace=False))
+        subrows = (sub[:, None] * d + np.arange(d)).ravel()
+        solve["f64_reference"] = {"align_err": e64, "iters": SOLVE_ITERS}
+        for name, Xh in finals.items():
+            solve[name]["err_vs_fp64"] = {
+                "dF_sqrt_n": dist_F(Xh, X64h) / math.sqrt(n),
+                "dF_sqrt_n_2000_block_subsample": dist_F(Xh[subrows], X64h[subrows]) / math.sqrt(2000),
+                "align_err_rel": abs(solve[name]["align_err"] - e64) / e64}
+            print(f"[bench] solve {name} vs FP64: d_F/sqrt(n) {solve[name]['err_vs_fp64']['dF_sqrt_n']:.2e}, "
+                  f"alignment error rel. {solve[name]['err_vs_fp64']['align_err_rel']:.2e}", file=sys.stderr, flush=True)
         ref = solve.get("f32", {}).get("align_err")
         if ref:
             for name in solve:
@@ -574,8 +724,9 @@ def main(argv=None):
         f"p={pm}": masked_bench(Zd, sigma, results["f32"]["ms_per_step"], a.steps, a.warmup, p=pm)
         for pm in (0.5, 0.2)}
     table1 = None if a.no_table1 else table1_bench()
+    config1 = None if a.no_config1 else config1_bench()
     batched = None if a.no_batched else batched_bench()
-    serving = None if a.no_serving else serving_bench(window_s=a.serving_window)
+    serving = None if a.no_serving else serving_bench(window_s=a.serving_window, warmup_s=a.serving_warmup)
 
     f32 = results["f32"]
     roof = {"bound": "hbm", "achieved": f32["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -610,6 +761,7 @@ def main(argv=None):
         "masked_step": masked,
         "solve": solve,
         "table1_shape": table1,
+        "config_n2000": config1,
         "batched": batched,
         "serving": serving,
     }
