@@ -270,9 +270,12 @@ int sync_step_symmetric(const nsrgs_matrix *A, int n, int d, double mu, int ns_s
  *   row_ptr  n + 1 offsets: block row i holds blocks row_ptr[i] .. row_ptr[i+1]-1;
  *   col_idx  their block columns, ascending, in [0, n) and != i (a stored
  *            diagonal block, or an index outside [0, n), contributes nothing);
- *   values   entry (a, b) of the k-th block of row i, with m = row_ptr[i+1] -
- *            row_ptr[i], at values[row_ptr[i] d^2 + (a d + b) m + k]
- *            (entry-major within a block row).
+ *   values   the blocks of row i in groups of 64: group g = k / 64 holds
+ *            w = min(64, m - 64 g) blocks (m = row_ptr[i+1] - row_ptr[i]),
+ *            entry-major, so entry (a, b) of the k-th block is at
+ *            values[row_ptr[i] d^2 + 64 g d^2 + (a d + b) w + k mod 64]
+ *            (one entry of a group's blocks is contiguous, and so is the
+ *            whole group).
  * All three are device arrays owned by the caller; fmt is NSRGS_A_F32 or
  * NSRGS_A_BF16 (element type of values).  1 <= d <= 32. */
 typedef struct {
@@ -297,12 +300,18 @@ int nsrgs_bsr_fill(const double *Z, int n, int d, double sigma, double p, uint64
 
 /* sync_step on block-sparse A: C_i = sum over stored j != i of A_ij X_j, then
  * the per-block step of sync_step.  X_in / X_out are FP32.  mu <= 0 selects
- * 1/n; for the incomplete observation model pass mu = 1/(np).  ws as for
- * sync_step with fmt NSRGS_A_F32 (for d > 8: sync_workspace_bytes(n, d,
- * NSRGS_A_F32) bytes; d <= 8 needs less).  1 <= d <= 32: d <= 8 runs one
- * fused kernel (one wave per block row); larger d runs a block-sparse product
- * (chunks of blocks through LDS) followed by the matrix-core path's per-block
- * epilogue.  Asynchronous. */
+ * 1/n; for the incomplete observation model pass mu = 1/(np).  1 <= d <= 32.
+ * For d <= 8, with ws of sync_step_bsr_workspace_bytes(n, d) bytes the step
+ * runs sliced: block columns are cut into slices whose X fits 64 KiB of LDS,
+ * each workgroup streams its block rows' blocks of one slice (their X_j read
+ * from LDS), and an epilogue adds the slices' partial sums in slice order;
+ * with a smaller ws (at least the sync_step part of sync_workspace_bytes) it
+ * runs one fused kernel, one wave per block row, reading X_j through the
+ * caches.  Both give the same C_i up to the order of additions.  For d > 8
+ * ws must hold sync_workspace_bytes(n, d, NSRGS_A_F32) bytes, and a
+ * block-sparse product (chunks of blocks through LDS) is followed by the
+ * matrix-core path's per-block epilogue.  Asynchronous. */
+size_t sync_step_bsr_workspace_bytes(int n, int d);   /* 0 for unsupported (n, d) */
 int sync_step_bsr(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_steps,
                   const void *X_in, void *X_out, void *ws, size_t ws_bytes, void *stream);
 

@@ -151,6 +151,7 @@ def lib() -> ctypes.CDLL:
         "nsrgs_bsr_count": (i32, [vp, i32, i32, dbl, ctypes.c_uint64, vp, vp, ctypes.POINTER(i64), vp]),
         "nsrgs_bsr_fill": (i32, [vp, i32, i32, dbl, dbl, ctypes.c_uint64, ctypes.POINTER(_Bsr), vp]),
         "sync_step_bsr": (i32, [ctypes.POINTER(_Bsr), i32, i32, dbl, i32, vp, vp, vp, sz, vp]),
+        "sync_step_bsr_workspace_bytes": (sz, [i32, i32]),
         "sync_solve_bsr": (i32, [ctypes.POINTER(_Bsr), i32, i32, dbl, i32, i32, dbl, vp, vp, sz, vp,
                                  ctypes.POINTER(_SolveOpts), ctypes.POINTER(Info)]),
         "sync_read_info": (i32, [vp, sz, i32, i32, i32, ctypes.POINTER(Info), vp]),
@@ -290,9 +291,13 @@ def stored(A: torch.Tensor, fmt: int = F32) -> StoredMatrix:
 class Workspace:
     """Device workspace for one (n, d, precision) problem; prepared on creation."""
 
-    def __init__(self, n: int, d: int, fmt: int, device="cuda", symmetric: bool = False):
-        nbytes = (lib().sync_step_symmetric_workspace_bytes(n, d, fmt) if symmetric
-                  else lib().sync_workspace_bytes(n, d, fmt))
+    def __init__(self, n: int, d: int, fmt: int, device="cuda", symmetric: bool = False, bsr: bool = False):
+        if bsr:
+            nbytes = lib().sync_step_bsr_workspace_bytes(n, d)
+        elif symmetric:
+            nbytes = lib().sync_step_symmetric_workspace_bytes(n, d, fmt)
+        else:
+            nbytes = lib().sync_workspace_bytes(n, d, fmt)
         if nbytes == 0:
             raise NsrgsError(1, f"invalid workspace request n={n} d={d} fmt={fmt}")
         buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
@@ -308,9 +313,11 @@ class Workspace:
         return self.tensor.data_ptr()
 
 
-def workspace(n: int, d: int, fmt: int, device="cuda", symmetric: bool = False) -> Workspace:
-    """symmetric=True sizes it for step_symmetric (which also serves every other call)."""
-    return Workspace(n, d, fmt, device, symmetric)
+def workspace(n: int, d: int, fmt: int, device="cuda", symmetric: bool = False, bsr: bool = False) -> Workspace:
+    """symmetric=True sizes it for step_symmetric (which also serves every other call);
+    bsr=True for the sliced block-sparse step (sync_step_bsr_workspace_bytes, also a
+    valid sync_workspace_bytes(n, d, F32) workspace)."""
+    return Workspace(n, d, fmt, device, symmetric, bsr)
 
 
 def _xdtype(fmt: int):
@@ -438,7 +445,8 @@ def symmetric_workspace_bytes(n: int, d: int, fmt: int) -> int:
 class BsrMatrix:
     """Block-sparse A of the incomplete observation model (device arrays; layout
     in include/nsrgs.h): row_ptr (n + 1, int64), col_idx (nnzb, int32), values
-    (nnzb d^2, FP32 or BF16 bits), entry-major within each block row."""
+    (nnzb d^2, FP32 or BF16 bits), in groups of 64 blocks per block row, entry-major
+    within each group."""
 
     def __init__(self, fmt: int, row_ptr: torch.Tensor, col_idx: torch.Tensor, values: torch.Tensor,
                  n: int, d: int, nnzb: int):

@@ -10,7 +10,10 @@ lane's data; the kernels are written to avoid divergent branches around live
 state, and this check makes sure no generated kernel has the pattern again.
 
 Only vector work counts: lane reads/writes (v_readlane, v_writelane,
-v_readfirstlane) ignore exec, and scalar instructions are not masked.
+v_readfirstlane) ignore exec, and scalar instructions are not masked.  A join
+block of an if / else first switches exec to the else lanes
+(s_andn2_saveexec_b64); vector work after that switch is the else branch's
+own, not the pattern.
 """
 from __future__ import annotations
 
@@ -65,6 +68,8 @@ def find_masked_joins(text: str) -> list[tuple[str, int, list[str]]]:
                 continue
             if _is_restore(t):
                 break
+            if _NARROW.match(t) and not extra:
+                break             # the block opens an else branch: its vector work has that branch's mask
             if _LABEL.match(t) or t.startswith(("s_cbranch", "s_branch", "s_endpgm", "s_setpc")):
                 extra = []        # left the block without a restore: not this pattern
                 break

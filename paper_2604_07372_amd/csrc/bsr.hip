@@ -4,10 +4,12 @@
 // (block-sparse rows), so an iteration reads about p of the dense bytes.
 //
 // Storage (nsrgs_bsr_matrix): block row i holds m_i = row_ptr[i+1] - row_ptr[i]
-// blocks with ascending block columns col_idx[row_ptr[i] ..]; entry (a, b) of
-// its k-th block is values[row_ptr[i] d^2 + (a d + b) m_i + k].  A block row's
-// values are entry-major, so the loads of one entry over 64 consecutive
-// blocks are one contiguous 64-element read.
+// blocks with ascending block columns col_idx[row_ptr[i] ..].  Its blocks are
+// grouped by 64: group g = k / 64 holds w_g = min(64, m_i - 64 g) blocks,
+// entry-major, so entry (a, b) of the k-th block is at
+//     values[row_ptr[i] d^2 + 64 g d^2 + (a d + b) w_g + k mod 64].
+// The loads of one entry over a group's blocks are one contiguous read, and
+// a group's d^2 entries are one contiguous run of memory.
 //
 // Generator: the same elements as nsrgs_generate_measurement with the same
 // observation mask, in three launches (count per block row, prefix sum, fill).
@@ -26,6 +28,13 @@
 
 namespace nsrgs {
 namespace {
+
+// Offset of entry e of the k-th block of a block row of m blocks, from the
+// row's first value (the grouped layout above).
+__host__ __device__ __forceinline__ int64_t bsr_entry_off(int64_t k, int e, int64_t m, int d2) {
+  const int64_t g0 = k & ~(int64_t)63, w = (m - g0) < 64 ? (m - g0) : 64;
+  return g0 * d2 + (int64_t)e * w + (k & 63);
+}
 
 constexpr int kBsrRowsPerGroup = 4;   // block rows (waves) per step workgroup
 constexpr int kBsrStepMaxD = 8;       // the fused one-wave-per-row step kernel
@@ -131,7 +140,7 @@ bsr_fill_kernel(const double *__restrict__ Z, int n, int d, double sigma, double
             const uint32_t lo = (uint32_t)(r < c ? r : c), hi = (uint32_t)(r < c ? c : r);
             v += sigma * normal_from(philox4x32_10(U4{hi, lo, 0u, 0u}, k0, k1));
           }
-          values[base * d2 + (int64_t)(a * d + b) * m + k] = store_elem<T>(v);
+          values[base * d2 + bsr_entry_off(k, a * d + b, m, d2)] = store_elem<T>(v);
         }
     }
     done += tot;
@@ -139,23 +148,33 @@ bsr_fill_kernel(const double *__restrict__ Z, int n, int d, double sigma, double
   }
 }
 
-template <typename E>
-__device__ __forceinline__ float load_elem(const E *p);
-template <>
-__device__ __forceinline__ float load_elem<float>(const float *p) { return __builtin_nontemporal_load(p); }
-template <>
-__device__ __forceinline__ float load_elem<uint16_t>(const uint16_t *p) {
-  return __uint_as_float((uint32_t)__builtin_nontemporal_load(p) << 16);
+// Loads of the streamed arrays (values, column indices): non-temporal (NT) or
+// ordinary.  An entry's 64-element run rarely starts on a cache line, so
+// consecutive chunks of a block row share a line at each run's ends; an
+// ordinary load keeps that line for the next chunk.
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_stream(const T *p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <typename E, bool NT>
+__device__ __forceinline__ float load_elem(const E *p) {
+  if constexpr (sizeof(E) == 4) return ld_stream<NT>(p);
+  else return __uint_as_float((uint32_t)ld_stream<NT>(p) << 16);
 }
 
-// One wave per block row, kBsrRowsPerGroup block rows per workgroup.
-template <typename E, int D>
+// One wave per block row, kBsrRowsPerGroup block rows per workgroup.  Lane l
+// takes the row's blocks k0 + l + 64 u (u < UN) of each chunk of 64 UN; the
+// next chunk's column indices are loaded while this chunk's X_j gathers and
+// products run, so the index -> gather dependence does not stall every chunk.
+template <typename E, int D, bool NT, int UN>
 __global__ void __launch_bounds__(kWave * kBsrRowsPerGroup)
 bsr_step_kernel(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
                 const E *__restrict__ values, StreamArgs sa) {
   constexpr int D2 = D * D;
   constexpr int NB = kBsrRowsPerGroup;
   constexpr int NE = NB * D2;
+  constexpr int CH = kWave * UN;
   __shared__ double s_scr[kMaxWaves];
   __shared__ float sbuf[6 * NE];
   const int tid = threadIdx.x, lane = tid & (kWave - 1);
@@ -167,31 +186,53 @@ bsr_step_kernel(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__
   const int64_t base = row_ptr[ic];
   const int64_t m = i < n ? row_ptr[ic + 1] - base : 0;   // wave-uniform
   const E *__restrict__ vals = values + base * D2;
+  const int32_t *__restrict__ cols = col_idx + base;
   float acc[D2];
 #pragma unroll
   for (int e = 0; e < D2; ++e) acc[e] = 0.0f;
-  for (int64_t k0 = 0; k0 < m; k0 += kWave) {
-    const int64_t k = k0 + lane;
-    const bool ok = k < m;
-    const int64_t kc = ok ? k : m - 1;                  // clamped: in-bounds, masked below
-    // streamed once, non-temporal like the values, so that X stays in cache
-    const int jr = __builtin_nontemporal_load(col_idx + base + kc);
-    const int j = jr < 0 ? 0 : (jr < n ? jr : n - 1);   // out-of-range indices read in bounds
-    const bool use = ok && jr == j && j != ic;          // and, like a stored diagonal block, count 0
-    float a[D2], x[D2];
+  int jr_next[UN];
 #pragma unroll
-    for (int e = 0; e < D2; ++e) a[e] = load_elem<E>(vals + (int64_t)e * m + kc);
+  for (int u = 0; u < UN; ++u) {
+    const int64_t k = (int64_t)u * kWave + lane;
+    jr_next[u] = m > 0 ? ld_stream<NT>(cols + (k < m ? k : m - 1)) : 0;
+  }
+  for (int64_t k0 = 0; k0 < m; k0 += CH) {
+    int jr[UN];
 #pragma unroll
-    for (int e = 0; e < D2; ++e) x[e] = X[(int64_t)j * D2 + e];
+    for (int u = 0; u < UN; ++u) jr[u] = jr_next[u];
+    float a[UN][D2], x[UN][D2];
+    bool use[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int64_t k = k0 + (int64_t)u * kWave + lane;
+      const bool ok = k < m;
+      const int64_t kc = ok ? k : m - 1;                // clamped: in-bounds, masked below
+#pragma unroll
+      for (int e = 0; e < D2; ++e) a[u][e] = load_elem<E, NT>(vals + bsr_entry_off(kc, e, m, D2));
+      const int j = jr[u] < 0 ? 0 : (jr[u] < n ? jr[u] : n - 1);   // out-of-range indices read in bounds
+      use[u] = ok && jr[u] == j && j != ic;             // and, like a stored diagonal block, count 0
+#pragma unroll
+      for (int e = 0; e < D2; ++e) x[u][e] = X[(int64_t)j * D2 + e];
+    }
+    if (k0 + CH < m) {                                  // wave-uniform
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        const int64_t k = k0 + CH + (int64_t)u * kWave + lane;
+        jr_next[u] = ld_stream<NT>(cols + (k < m ? k : m - 1));
+      }
+    }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int e = 0; e < D2; ++e) a[e] = use ? a[e] : 0.0f;
+    for (int u = 0; u < UN; ++u) {
 #pragma unroll
-    for (int r = 0; r < D; ++r)
+      for (int e = 0; e < D2; ++e) a[u][e] = use[u] ? a[u][e] : 0.0f;
 #pragma unroll
-      for (int b = 0; b < D; ++b)
+      for (int r = 0; r < D; ++r)
 #pragma unroll
-        for (int c = 0; c < D; ++c) acc[r * D + c] = fmaf(a[r * D + b], x[b * D + c], acc[r * D + c]);
+        for (int b = 0; b < D; ++b)
+#pragma unroll
+          for (int c = 0; c < D; ++c) acc[r * D + c] = fmaf(a[u][r * D + b], x[u][b * D + c], acc[r * D + c]);
+    }
   }
   float *sX = sbuf, *sC = sX + NE, *sG = sC + NE, *sT = sG + NE, *sF = sT + NE, *sM = sF + NE;
 #pragma unroll
@@ -205,6 +246,317 @@ bsr_step_kernel(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__
                                     static_cast<float *>(sa.X_out),
                                     static_cast<PanelStat *>(sa.partials) + blockIdx.x, sX, sC, sG, sT, sF, sM,
                                     s_scr);
+}
+
+// ---------------------------------------------------------------------------
+// Sliced step (d <= 8).  The fused kernel above gathers X_j from the caches
+// for every block; at the benchmark's size those gathers (36 B of scattered
+// lines per 40 B of streamed A) cost as much cache bandwidth as the stream.
+// Here the block columns are cut into slices of W blocks whose X fills 128
+// KiB of LDS, and a workgroup (slice s, a group of 64 block rows, one per CU)
+// loads X of its slice into LDS once, then streams its rows' blocks with
+// columns in the slice (a contiguous range of each row, col_idx being
+// ascending) and gathers X_j from LDS.  Each of its 16 waves takes 4 rows one
+// after the other, with the next chunk of 64 blocks (the next row's first
+// at a row's end) in flight while the current one is used.  Per-(slice, row)
+// partial sums go to the workspace; an epilogue kernel adds them in slice
+// order and runs the per-block step.  The row ranges of the slices come from
+// a binary search per (slice, row).
+// ---------------------------------------------------------------------------
+constexpr int kBsrSliceBytes = 131072;
+constexpr int kBsrSliceMaxD = 6;          // d >= 7 needs more registers than 8 waves per CU leave: fused kernel
+constexpr int kBsrSliceRPW = 4;           // block rows per wave
+// Waves per workgroup: 16 while a wave's chunk, X slice and sums fit 128
+// VGPRs (d <= 4), else 8.
+__host__ __device__ constexpr int bsr_slice_waves(int d) { return d <= 4 ? 16 : 8; }
+
+__host__ __device__ constexpr int bsr_xs(int d) { return (d * d + 3) / 4 * 4; }   // floats per X_j in LDS
+// Two workgroups per CU (NSRGS_BSR_OCC = 2, d <= 3): 64 KiB slices and at most
+// 64 VGPRs per lane, so that twice as many loads are in flight per CU.
+inline bool bsr_two_per_cu(int d) { return d <= 3 && env_int("NSRGS_BSR_OCC", 1) == 2; }
+// Slice width in blocks: what the LDS slice holds, or less with NSRGS_BSR_SLICE_W.
+inline int bsr_slice_w(int d) {
+  const int bytes = bsr_two_per_cu(d) ? kBsrSliceBytes / 2 : kBsrSliceBytes;
+  const int w = bytes / (4 * bsr_xs(d)), f = env_int("NSRGS_BSR_SLICE_W", 0);
+  return (f > 0 && f < w) ? f : w;
+}
+inline int bsr_slices(int n, int d) { return (n + bsr_slice_w(d) - 1) / bsr_slice_w(d); }
+
+// bounds[s n + i] = first k of block row i with col_idx >= s W, s = 0 .. S.
+__global__ void __launch_bounds__(256)
+bsr_bounds_kernel(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx, int n, int S, int W,
+                  int32_t *__restrict__ bounds) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)(S + 1) * n) return;
+  const int s = (int)(t / n), i = (int)(t % n);
+  const int64_t base = row_ptr[i];
+  const int64_t key = (int64_t)s * W;
+  int64_t lo = 0, hi = row_ptr[i + 1] - base;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) / 2;
+    if (col_idx[base + mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  bounds[t] = (int32_t)lo;
+}
+
+// One chunk of 64 UN blocks of a row: lane l's blocks k = k0 + l + 64 u
+// (clamped to the row's range in this slice), their column indices and d^2
+// values.  Buffer loads: the row's arrays are buffer resources (wave-uniform),
+// the entry offset e m is a scalar offset and the lane's block offset the only
+// per-lane address, so no per-lane 64-bit address arithmetic.  (The host runs
+// this kernel only when a row's values span less than 2^31 bytes.)
+struct BsrRow {
+  __amdgpu_buffer_rsrc_t vals, cols;
+  int64_t m;
+};
+
+template <typename E>
+__device__ __forceinline__ BsrRow bsr_row(const E *values, const int32_t *col_idx, int64_t base, int64_t m, int d2) {
+  // word 3 of a raw buffer resource on this GPU family; num_records in bytes
+  // (loads past it read 0)
+  constexpr int kRaw = 0x00020000;
+  BsrRow r;
+  r.vals = __builtin_amdgcn_make_buffer_rsrc((void *)(values + base * d2), (short)0,
+                                             (int)(m * d2 * (int64_t)sizeof(E)), kRaw);
+  r.cols = __builtin_amdgcn_make_buffer_rsrc((void *)(col_idx + base), (short)0, (int)(m * 4), kRaw);
+  r.m = m;
+  return r;
+}
+
+template <typename E, bool NT>
+__device__ __forceinline__ float bsr_buf_elem(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  constexpr int aux = NT ? 2 : 0;                       // bit 1: non-temporal
+  if constexpr (sizeof(E) == 4)
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, aux));
+  else
+    return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, aux) << 16);
+}
+
+template <typename E, int D, bool NT, int UN>
+__device__ __forceinline__ void bsr_chunk_load(const BsrRow &row, int64_t k0, int64_t hi, int lane,
+                                               float (&a)[UN][D * D], int (&jr)[UN]) {
+  constexpr int aux = NT ? 2 : 0;
+#pragma unroll
+  for (int u = 0; u < UN; ++u) {
+    const int64_t k = k0 + u * kWave + lane;
+    const int kc = (int)(k < hi ? k : hi - 1);
+    jr[u] = (int)__builtin_amdgcn_raw_buffer_load_b32(row.cols, kc * 4, 0, aux);
+    // entry e of block kc: group start 64 g d^2 + k mod 64, then e w_g
+    const int g0 = kc & ~63;
+    const int w = (int)(row.m - g0 < 64 ? row.m - g0 : 64);
+    int off = (g0 * (D * D) + (kc & 63)) * (int)sizeof(E);
+#pragma unroll
+    for (int e = 0; e < D * D; ++e) {
+      a[u][e] = bsr_buf_elem<E, NT>(row.vals, off, 0);
+      off += w * (int)sizeof(E);
+    }
+  }
+}
+
+template <typename E, int D, bool NT, int UN, int NW, int MINW = 1>
+__global__ void __launch_bounds__(kWave * NW, MINW)
+bsr_slice_kernel(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
+                 const E *__restrict__ values, const int32_t *__restrict__ bounds, const float *__restrict__ X,
+                 int n, int W, float *__restrict__ part) {
+  constexpr int D2 = D * D, XS = bsr_xs(D), XQ = XS / 4, RPW = kBsrSliceRPW, CH = kWave * UN;
+  constexpr int ROWS = NW * kBsrSliceRPW;
+  extern __shared__ float4 sX4[];
+  float *sXf = reinterpret_cast<float *>(sX4);
+  const int tid = threadIdx.x, lane = tid & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+  const int g = blockIdx.x, s = blockIdx.y;
+  const int j0 = s * W, jn = min(W, n - j0);
+  // this wave's rows (wave-uniform), read while the slice of X is staged
+  BsrRow row[RPW];
+  int64_t rlo[RPW], rhi[RPW];
+#pragma unroll
+  for (int q = 0; q < RPW; ++q) {
+    const int i = g * ROWS + q * NW + wave;
+    const int ic = i < n ? i : n - 1;
+    const int64_t b = row_ptr[ic];
+    row[q] = bsr_row<E>(values, col_idx, b, row_ptr[ic + 1] - b, D2);
+    rlo[q] = bounds[(int64_t)s * n + ic];
+    rhi[q] = i < n ? bounds[(int64_t)(s + 1) * n + ic] : rlo[q];   // rows past n have no blocks
+  }
+  for (int idx = tid; idx < jn * XS; idx += blockDim.x) {
+    const int jl = idx / XS, e = idx % XS;
+    sXf[idx] = e < D2 ? X[(int64_t)(j0 + jl) * D2 + e] : 0.0f;
+  }
+  __syncthreads();
+  float an[UN][D2];
+  int jn_next[UN];
+  bool have = false;                                    // wave-uniform: a chunk is in flight
+  if (rhi[0] > rlo[0]) {
+    bsr_chunk_load<E, D, NT, UN>(row[0], rlo[0], rhi[0], lane, an, jn_next);
+    have = true;
+  }
+#pragma unroll
+  for (int q = 0; q < RPW; ++q) {
+    const int i = g * ROWS + q * NW + wave;
+    float acc[D2];
+#pragma unroll
+    for (int e = 0; e < D2; ++e) acc[e] = 0.0f;
+    if (!have && rhi[q] > rlo[q]) {                     // wave-uniform
+      bsr_chunk_load<E, D, NT, UN>(row[q], rlo[q], rhi[q], lane, an, jn_next);
+      have = true;
+    }
+    for (int64_t k0 = rlo[q]; k0 < rhi[q]; k0 += CH) {
+      float a[UN][D2];
+      int jr[UN];
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        jr[u] = jn_next[u];
+#pragma unroll
+        for (int e = 0; e < D2; ++e) a[u][e] = an[u][e];
+      }
+      have = false;
+      if (k0 + CH < rhi[q]) {                           // wave-uniform: the row's next chunk in flight
+        bsr_chunk_load<E, D, NT, UN>(row[q], k0 + CH, rhi[q], lane, an, jn_next);
+        have = true;
+      } else if (q + 1 < RPW) {
+        if (rhi[q + 1] > rlo[q + 1]) {                  // or the next row's first
+          bsr_chunk_load<E, D, NT, UN>(row[q + 1], rlo[q + 1], rhi[q + 1], lane, an, jn_next);
+          have = true;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        const bool ok = k0 + u * kWave + lane < rhi[q];
+        const int jl = jr[u] - j0;
+        const bool inside = jl >= 0 && jl < jn;         // ascending columns keep every stored one inside
+        const bool use = ok && inside && jr[u] != i;
+        const int jlc = inside ? jl : 0;
+        float x[XS];
+#pragma unroll
+        for (int qq = 0; qq < XQ; ++qq) {
+          const float4 v = sX4[jlc * XQ + qq];
+          x[4 * qq] = v.x;
+          x[4 * qq + 1] = v.y;
+          x[4 * qq + 2] = v.z;
+          x[4 * qq + 3] = v.w;
+        }
+#pragma unroll
+        for (int e = 0; e < D2; ++e) a[u][e] = use ? a[u][e] : 0.0f;
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+          for (int b = 0; b < D; ++b)
+#pragma unroll
+            for (int c = 0; c < D; ++c) acc[r * D + c] = fmaf(a[u][r * D + b], x[b * D + c], acc[r * D + c]);
+      }
+    }
+    // the row's d^2 sums over the wave by the transpose-reduce (a few shuffles
+    // instead of six per entry); lanes holding the same entry hold equal sums
+    wave_tr_step<float, D2, 0>(acc, lane);
+    if (i < n) part[((int64_t)s * n + i) * D2 + wave_tr_entry<D2>(lane)] = acc[0];
+  }
+}
+
+// C_i = the slices' partial sums in slice order, then the per-block step.
+template <int D>
+__global__ void __launch_bounds__(kWave * kBsrRowsPerGroup)
+bsr_slice_epilogue_kernel(const float *__restrict__ part, int S, StreamArgs sa) {
+  constexpr int D2 = D * D;
+  constexpr int NB = kBsrRowsPerGroup;
+  constexpr int NE = NB * D2;
+  __shared__ double s_scr[kMaxWaves];
+  __shared__ float sbuf[6 * NE];
+  const int tid = threadIdx.x, n = sa.n;
+  const float *__restrict__ X = static_cast<const float *>(sa.X_in);
+  float *sX = sbuf, *sC = sX + NE, *sG = sC + NE, *sT = sG + NE, *sF = sT + NE, *sM = sF + NE;
+  for (int t = tid; t < NE; t += blockDim.x) {
+    const int i = blockIdx.x * NB + t / D2, e = t % D2;
+    float c = 0.0f;
+    if (i < n)
+      for (int s = 0; s < S; ++s) c += part[((int64_t)s * n + i) * D2 + e];
+    sC[t] = c;
+    sX[t] = i < n ? X[(int64_t)i * D2 + e] : 0.0f;
+  }
+  __syncthreads();
+  block_step_epilogue<float, D, NB>(n, sa.mu, sa.ns_steps, sa.nd, blockIdx.x * NB * D,
+                                    static_cast<float *>(sa.X_out),
+                                    static_cast<PanelStat *>(sa.partials) + blockIdx.x, sX, sC, sG, sT, sF, sM,
+                                    s_scr);
+}
+
+template <typename E, int D>
+hipError_t bsr_slice_launch_d(const nsrgs_bsr_matrix &A, const StreamArgs &sa, int32_t *bounds, float *part,
+                              hipStream_t s) {
+  const int n = sa.n, W = bsr_slice_w(D), S = bsr_slices(n, D);
+  const int64_t nb = (int64_t)(S + 1) * n;
+  hipLaunchKernelGGL(bsr_bounds_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, A.row_ptr, A.col_idx,
+                     n, S, W, bounds);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t lds = (size_t)W * bsr_xs(D) * sizeof(float);
+  const E *vals = static_cast<const E *>(A.values);
+  const float *Xf = static_cast<const float *>(sa.X_in);
+  // Load hint (NSRGS_BSR_NT, default ordinary loads: a chunk's first and last
+  // cache lines are shared with its neighbours) and chunk size
+  // (NSRGS_BSR_UN = 1, 2 or 4 blocks per lane; 2 by default for d <= 3,
+  // where two chunks' registers fit 16 waves per CU; 4 runs 8 waves).
+  const bool nt = env_int("NSRGS_BSR_NT", 0) != 0;
+  const int fu = env_int("NSRGS_BSR_UN", D <= 3 ? 2 : 1);
+  const int un = D <= 3 && (fu == 2 || fu == 4) ? fu : 1;
+#define NSRGS_BSR_SLICE(NTV, UNV, NWV, MINW)                                                               \
+  {                                                                                                          \
+    static const bool ok_ = hipFuncSetAttribute((const void *)bsr_slice_kernel<E, D, NTV, UNV, NWV, MINW>,   \
+                                                hipFuncAttributeMaxDynamicSharedMemorySize,                  \
+                                                kBsrSliceBytes) == hipSuccess;                               \
+    if (!ok_) return hipErrorInvalidConfiguration;                                                         \
+    const dim3 grid_((n + NWV * kBsrSliceRPW - 1) / (NWV * kBsrSliceRPW), S);                                \
+    hipLaunchKernelGGL((bsr_slice_kernel<E, D, NTV, UNV, NWV, MINW>), grid_, dim3(kWave * NWV), lds, s,      \
+                       A.row_ptr, A.col_idx, vals, bounds, Xf, n, W, part);                                  \
+  }
+  // (more than 64 KiB of dynamic LDS has to be allowed per kernel, once)
+  constexpr int NW1 = bsr_slice_waves(D);
+  if (bsr_two_per_cu(D)) {
+    if constexpr (D <= 3) {
+      if (nt) NSRGS_BSR_SLICE(true, 1, 16, 8) else NSRGS_BSR_SLICE(false, 1, 16, 8)
+    }
+  } else if (un == 4) {
+    if constexpr (D <= 3) {
+      if (nt) NSRGS_BSR_SLICE(true, 4, 8, 1) else NSRGS_BSR_SLICE(false, 4, 8, 1)
+    }
+  } else if (un == 2) {
+    if constexpr (D <= 3) {
+      if (nt) NSRGS_BSR_SLICE(true, 2, 16, 1) else NSRGS_BSR_SLICE(false, 2, 16, 1)
+    }
+  } else {
+    if (nt) NSRGS_BSR_SLICE(true, 1, NW1, 1) else NSRGS_BSR_SLICE(false, 1, NW1, 1)
+  }
+#undef NSRGS_BSR_SLICE
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((bsr_slice_epilogue_kernel<D>), dim3(sa.num_panels), dim3(kWave * kBsrRowsPerGroup), 0, s,
+                     part, S, sa);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((stream_finish_kernel<float, D, 0>), dim3(1), dim3(256), 0, s, sa);
+  return hipGetLastError();
+}
+
+template <typename E>
+hipError_t bsr_slice_launch(int d, const nsrgs_bsr_matrix &A, const StreamArgs &sa, int32_t *bounds, float *part,
+                            hipStream_t s) {
+  switch (d) {
+    case 1: return bsr_slice_launch_d<E, 1>(A, sa, bounds, part, s);
+    case 2: return bsr_slice_launch_d<E, 2>(A, sa, bounds, part, s);
+    case 3: return bsr_slice_launch_d<E, 3>(A, sa, bounds, part, s);
+    case 4: return bsr_slice_launch_d<E, 4>(A, sa, bounds, part, s);
+    case 5: return bsr_slice_launch_d<E, 5>(A, sa, bounds, part, s);
+    case 6: return bsr_slice_launch_d<E, 6>(A, sa, bounds, part, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Workspace of the sliced step: the sync_step part, then the slice bounds and
+// the partial sums.
+size_t bsr_slice_table_off(int n, int d) { return narrow_ws_bytes(n, d, NSRGS_A_F32); }
+size_t bsr_slice_part_off(int n, int d) {
+  return bsr_slice_table_off(n, d) + align256((size_t)(bsr_slices(n, d) + 1) * n * sizeof(int32_t));
+}
+size_t bsr_slice_ws_bytes(int n, int d) {
+  return bsr_slice_part_off(n, d) + align256((size_t)bsr_slices(n, d) * n * d * d * sizeof(float));
 }
 
 // The product of block-sparse A with X for the matrix-core path's epilogue
@@ -245,7 +597,7 @@ bsr_wide_product_kernel(const int64_t *__restrict__ row_ptr, const int32_t *__re
       const int kkc = kk < kb ? kk : kb - 1;
       const int jr = col_idx[base + k0 + kkc];
       const bool use = kk < kb && jr >= 0 && jr < n && jr != i;
-      const float v = load_elem<E>(vals + (int64_t)e * m + k0 + kkc);
+      const float v = load_elem<E, true>(vals + bsr_entry_off(k0 + kkc, e, m, dd));
       const float va = use ? v : 0.0f;
       sA[kk * dd + e] = va;
       ssq += (double)va * (double)va;
@@ -279,10 +631,23 @@ bsr_wide_product_kernel(const int64_t *__restrict__ row_ptr, const int32_t *__re
   if (tid == 0 && sumsq) sumsq[i] = ssq;
 }
 
+// Load hint and blocks per lane per chunk: NSRGS_BSR_NT (1: non-temporal
+// loads of the streamed arrays), NSRGS_BSR_UN (2: two blocks per lane, d <= 4).
 template <typename E, int D>
 hipError_t bsr_launch_d(const nsrgs_bsr_matrix &A, const StreamArgs &sa, hipStream_t s) {
-  hipLaunchKernelGGL((bsr_step_kernel<E, D>), dim3(sa.num_panels), dim3(kWave * kBsrRowsPerGroup), 0, s,
-                     A.row_ptr, A.col_idx, static_cast<const E *>(A.values), sa);
+  const bool nt = env_int("NSRGS_BSR_NT", 1) != 0;
+  const int un = (D <= 4 && env_int("NSRGS_BSR_UN", 1) == 2) ? 2 : 1;
+  const dim3 grid(sa.num_panels), block(kWave * kBsrRowsPerGroup);
+  const E *vals = static_cast<const E *>(A.values);
+  if (un == 2) {
+    if constexpr (D <= 4) {
+      if (nt) hipLaunchKernelGGL((bsr_step_kernel<E, D, true, 2>), grid, block, 0, s, A.row_ptr, A.col_idx, vals, sa);
+      else hipLaunchKernelGGL((bsr_step_kernel<E, D, false, 2>), grid, block, 0, s, A.row_ptr, A.col_idx, vals, sa);
+    }
+  } else {
+    if (nt) hipLaunchKernelGGL((bsr_step_kernel<E, D, true, 1>), grid, block, 0, s, A.row_ptr, A.col_idx, vals, sa);
+    else hipLaunchKernelGGL((bsr_step_kernel<E, D, false, 1>), grid, block, 0, s, A.row_ptr, A.col_idx, vals, sa);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((stream_finish_kernel<float, D, 0>), dim3(1), dim3(256), 0, s, sa);
@@ -392,6 +757,8 @@ int sync_step_bsr(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_ste
   if (!ws || ((uintptr_t)ws & 255u)) return fail(NSRGS_ERR_INVALID_ARG, "workspace must be non-NULL and 256-byte aligned");
   if (d > kBsrStepMaxD)
     return bsr_wide_step(A, n, d, mu, ns_steps, X_in, X_out, ws, ws_bytes, (hipStream_t)stream);
+  const bool sliced = d <= kBsrSliceMaxD && ws_bytes >= bsr_slice_ws_bytes(n, d) &&
+                      (int64_t)n * d * d * 4 < ((int64_t)1 << 31) && env_int("NSRGS_BSR_SLICED", 1) != 0;
   const size_t need = narrow_ws_bytes(n, d, NSRGS_A_F32);
   if (ws_bytes < need) return fail(NSRGS_ERR_OUT_OF_MEMORY, "workspace too small: %zu < %zu bytes", ws_bytes, need);
   StreamArgs sa{};
@@ -406,9 +773,26 @@ int sync_step_bsr(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_ste
   sa.partials = static_cast<char *>(ws) + step_ws_stats_offset(n, d, NSRGS_A_F32);
   sa.ctl = static_cast<DevCtl *>(ws);
   hipStream_t s = (hipStream_t)stream;
-  const hipError_t e = A->fmt == NSRGS_A_F32 ? bsr_launch<float>(d, *A, sa, s) : bsr_launch<uint16_t>(d, *A, sa, s);
+  hipError_t e;
+  if (sliced) {
+    char *base = static_cast<char *>(ws);
+    int32_t *bounds = reinterpret_cast<int32_t *>(base + bsr_slice_table_off(n, d));
+    float *part = reinterpret_cast<float *>(base + bsr_slice_part_off(n, d));
+    e = A->fmt == NSRGS_A_F32 ? bsr_slice_launch<float>(d, *A, sa, bounds, part, s)
+                              : bsr_slice_launch<uint16_t>(d, *A, sa, bounds, part, s);
+  } else {
+    e = A->fmt == NSRGS_A_F32 ? bsr_launch<float>(d, *A, sa, s) : bsr_launch<uint16_t>(d, *A, sa, s);
+  }
   NSRGS_HIP(e, "bsr step launch");
   return NSRGS_OK;
+}
+
+size_t sync_step_bsr_workspace_bytes(int n, int d) {
+  if (n < 2 || d < 1 || d > kBsrMaxD || (int64_t)n * d * d >= (int64_t)1 << 31) return 0;
+  const size_t full = sync_workspace_bytes(n, d, NSRGS_A_F32);
+  if (d > kBsrSliceMaxD) return full;
+  const size_t sl = bsr_slice_ws_bytes(n, d);
+  return sl > full ? sl : full;
 }
 
 }  // extern "C"

@@ -226,6 +226,53 @@ __device__ __forceinline__ T block_max(T v, T *scratch) {
   return s;
 }
 
+// ---- transpose-reduce over the 64 lanes of a wave ------------------------
+// (M values per lane, each to be summed over the wave)
+// Each of 6 steps pairs lanes that differ in one bit: one lane of the pair
+// keeps the lower half of its values, the other the upper half, and each adds
+// the partner's copy of what it keeps (an odd middle value is kept and summed
+// by both).  After the last step every value a lane holds is the full 64-lane
+// sum of one entry; wave_tr_entry gives which.  The additions are in a fixed
+// order, and lanes holding the same entry hold bitwise equal sums.
+constexpr int wave_tr_count(int m, int steps) {
+  return steps == 0 ? m : wave_tr_count(m / 2 + (m & 1), steps - 1);
+}
+
+template <typename T, int M, int STEP>
+__device__ __forceinline__ void wave_tr_step(T *v, int lane) {
+  if constexpr (STEP < 6) {
+    constexpr int off = 32 >> STEP;
+    constexpr int h = M / 2;
+    const bool hi = (lane & off) != 0;
+#pragma unroll
+    for (int i = 0; i < h; ++i) {
+      const T keep = hi ? v[h + i] : v[i];
+      const T send = hi ? v[i] : v[h + i];
+      v[i] = keep + __shfl_xor(send, off, kWave);
+    }
+    if constexpr (M & 1) v[h] = v[M - 1] + __shfl_xor(v[M - 1], off, kWave);
+    wave_tr_step<T, h + (M & 1), STEP + 1>(v, lane);
+  }
+}
+
+// For N <= 64 each lane ends with one value; the entry it holds, found by
+// walking the steps backwards from position 0 (a value at position p < h
+// after a step came from p, or from h + p in the lane that kept the upper
+// half; the odd middle value came from the last position).
+template <int N>
+__device__ __forceinline__ int wave_tr_entry(int lane) {
+  static_assert(wave_tr_count(N, 6) == 1, "one value per lane after the reduction");
+  int p = 0;
+#pragma unroll
+  for (int st = 5; st >= 0; --st) {
+    const int m = wave_tr_count(N, st);
+    const int h = m / 2;
+    const bool hi = ((lane >> (5 - st)) & 1) != 0;
+    p = p < h ? (hi ? h + p : p) : m - 1;
+  }
+  return p;
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of the
 // 4 x 32-bit multiply-xor bijection keyed by (k0, k1), key bumped between rounds.
 struct U4 {

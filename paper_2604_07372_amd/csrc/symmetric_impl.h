@@ -53,52 +53,6 @@ struct SymArgs {
 constexpr int sym_epi_blocks(int d) { return d == 1 ? 64 : d == 2 ? 32 : d <= 4 ? 16 : d == 5 ? 8 : d == 6 ? 6 : 4; }
 constexpr int kSymMaxD = 16;
 
-// ---- transpose-reduce over the 64 lanes of a wave ------------------------
-// Each of 6 steps pairs lanes that differ in one bit: one lane of the pair
-// keeps the lower half of its values, the other the upper half, and each adds
-// the partner's copy of what it keeps (an odd middle value is kept and summed
-// by both).  After the last step every value a lane holds is the full 64-lane
-// sum of one entry; sym_tr_entry gives which.  The additions are in a fixed
-// order, and lanes holding the same entry hold bitwise equal sums.
-constexpr int sym_tr_count(int m, int steps) {
-  return steps == 0 ? m : sym_tr_count(m / 2 + (m & 1), steps - 1);
-}
-
-template <typename T, int M, int STEP>
-__device__ __forceinline__ void sym_tr_step(T *v, int lane) {
-  if constexpr (STEP < 6) {
-    constexpr int off = 32 >> STEP;
-    constexpr int h = M / 2;
-    const bool hi = (lane & off) != 0;
-#pragma unroll
-    for (int i = 0; i < h; ++i) {
-      const T keep = hi ? v[h + i] : v[i];
-      const T send = hi ? v[i] : v[h + i];
-      v[i] = keep + __shfl_xor(send, off, kWave);
-    }
-    if constexpr (M & 1) v[h] = v[M - 1] + __shfl_xor(v[M - 1], off, kWave);
-    sym_tr_step<T, h + (M & 1), STEP + 1>(v, lane);
-  }
-}
-
-// For N <= 64 each lane ends with one value; the entry it holds, found by
-// walking the steps backwards from position 0 (a value at position p < h
-// after a step came from p, or from h + p in the lane that kept the upper
-// half; the odd middle value came from the last position).
-template <int N>
-__device__ __forceinline__ int sym_tr_entry(int lane) {
-  static_assert(sym_tr_count(N, 6) == 1, "one value per lane after the reduction");
-  int p = 0;
-#pragma unroll
-  for (int st = 5; st >= 0; --st) {
-    const int m = sym_tr_count(N, st);
-    const int h = m / 2;
-    const bool hi = ((lane >> (5 - st)) & 1) != 0;
-    p = p < h ? (hi ? h + p : p) : m - 1;
-  }
-  return p;
-}
-
 // The rows [strip0, strip1) of one tile for this wave's columns.
 template <int FMT, int D, int R, int U, bool MASK>
 __device__ __forceinline__ void sym_tile_rows(const SymArgs &a, const typename Fmt<FMT>::acc_t *__restrict__ X,
@@ -116,7 +70,7 @@ __device__ __forceinline__ void sym_tile_rows(const SymArgs &a, const typename F
   const char *__restrict__ Ab = static_cast<const char *>(a.A);
   const char *__restrict__ Alo = static_cast<const char *>(a.A_lo);
 
-  const int ridx = sym_tr_entry<N>(lane);
+  const int ridx = wave_tr_entry<N>(lane);
 
   // masked path: block index of each column (-1 past nd, so nothing counts)
   int cblk[U][V];
@@ -201,7 +155,7 @@ __device__ __forceinline__ void sym_tile_rows(const SymArgs &a, const typename F
           }
       }
     }
-    sym_tr_step<T, N, 0>(acc, lane);
+    wave_tr_step<T, N, 0>(acc, lane);
     out[ridx] = acc[0];
   }
 }

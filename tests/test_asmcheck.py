@@ -41,6 +41,40 @@ GOOD = """_Zkernel:
 """
 
 
+ELSE = """_Zkernel:
+\ts_and_saveexec_b64 s[6:7], vcc
+\ts_xor_b64 s[6:7], exec, s[6:7]
+\ts_cbranch_execz .LBB0_7
+\tv_mov_b32_e32 v1, 1
+.LBB0_7:
+\ts_andn2_saveexec_b64 s[0:1], s[6:7]
+\tv_mov_b64_e32 v[6:7], 0
+\ts_or_b64 exec, exec, s[0:1]
+\ts_endpgm
+"""
+
+ELSE_LATE = """_Zkernel:
+\ts_and_saveexec_b64 s[6:7], vcc
+\ts_xor_b64 s[6:7], exec, s[6:7]
+\ts_cbranch_execz .LBB0_7
+\tv_mov_b32_e32 v1, 1
+.LBB0_7:
+\tv_mov_b32_e32 v9, v1
+\ts_andn2_saveexec_b64 s[0:1], s[6:7]
+\tv_mov_b64_e32 v[6:7], 0
+\ts_or_b64 exec, exec, s[0:1]
+\ts_endpgm
+"""
+
+
+def test_accepts_the_else_branch_of_an_if_else():
+    # the join block switches exec to the else lanes before its vector work
+    assert asmcheck.find_masked_joins(ELSE) == []
+    # but a copy placed before that switch still runs under the then-mask
+    found = asmcheck.find_masked_joins(ELSE_LATE)
+    assert len(found) == 1 and found[0][2][0].startswith("v_mov_b32_e32 v9")
+
+
 def test_flags_copies_before_the_exec_restore():
     found = asmcheck.find_masked_joins(BAD)
     assert len(found) == 1

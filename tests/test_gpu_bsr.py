@@ -39,6 +39,13 @@ def _orthogonal_start(Z, eps, seed):
     return out
 
 
+def _entry_off(k, e, m, d2):
+    """Offset of entry e of a row's k-th block from the row's first value: groups
+    of 64 blocks, each entry-major over its w = min(64, m - 64 g) blocks."""
+    g0 = (k // 64) * 64
+    return g0 * d2 + e * min(64, m - g0) + k % 64
+
+
 def _dense_from_bsr(B: P.BsrMatrix, n, d):
     """Expand the device arrays on the host (test-side reading of the layout)."""
     rp = B.row_ptr.cpu().numpy()
@@ -53,7 +60,7 @@ def _dense_from_bsr(B: P.BsrMatrix, n, d):
         m = rp[i + 1] - rp[i]
         for k in range(m):
             j = ci[rp[i] + k]
-            blk = np.array([vals[rp[i] * d * d + e * m + k] for e in range(d * d)]).reshape(d, d)
+            blk = np.array([vals[rp[i] * d * d + _entry_off(k, e, m, d * d)] for e in range(d * d)]).reshape(d, d)
             A[i * d:(i + 1) * d, j * d:(j + 1) * d] = blk
     return A, rp, ci
 
@@ -90,20 +97,36 @@ def test_bsr_generator_matches_host_twin_and_dense_generator(d, p):
     assert np.array_equal(A, np.where(off, dense, 0.0))
 
 
+# d <= 6 has two kernels: "sliced" (X of a column slice in LDS; with
+# slice_w, slices of that many blocks, so that small n has several) and
+# "fused" (one wave per block row, X through the caches); d = 7, 8 run the
+# fused one and d > 8 the matrix-core epilogue.
+BSR_SHAPES = [(2, 1), (37, 3), (300, 3), (130, 4), (61, 5), (40, 8), (700, 2), (23, 9), (31, 16), (40, 25), (9, 32)]
+BSR_PATHS = ([(n, d, path) for n, d in BSR_SHAPES if d <= 6 for path in ("sliced", "fused", "slice_w")]
+             + [(n, d, "fused") for n, d in BSR_SHAPES if 6 < d <= 8]
+             + [(n, d, "wide") for n, d in BSR_SHAPES if d > 8] + [(1500, 4, "sliced"), (700, 6, "sliced")])
+
+
+def _bsr_path(path, monkeypatch):
+    monkeypatch.setenv("NSRGS_BSR_SLICED", "0" if path == "fused" else "1")
+    if path == "slice_w":
+        monkeypatch.setenv("NSRGS_BSR_SLICE_W", "7")
+
+
 @pytest.mark.parametrize("fmt", [P.F32, P.BF16], ids=lambda f: FMT_NAME[f])
 @pytest.mark.parametrize("p", [0.05, 0.5, 0.8, 1.0])
-@pytest.mark.parametrize("n,d", [(2, 1), (37, 3), (300, 3), (130, 4), (61, 5), (40, 8), (700, 2),
-                                 (23, 9), (31, 16), (40, 25), (9, 32)])
-def test_bsr_step_parity(n, d, p, fmt):
+@pytest.mark.parametrize("n,d,path", BSR_PATHS)
+def test_bsr_step_parity(n, d, path, p, fmt, monkeypatch):
     require_gpu()
+    _bsr_path(path, monkeypatch)
     seed = 7000 + 31 * n + d
-    print(f"bsr step parity n={n} d={d} p={p} fmt={FMT_NAME[fmt]}", flush=True)
+    print(f"bsr step parity n={n} d={d} {path} p={p} fmt={FMT_NAME[fmt]}", flush=True)
     Z, sigma, A64 = _masked(n, d, 0.3, seed, p)
     B = P.generate_bsr(torch.from_numpy(Z).cuda(), sigma, seed + 1, p, fmt=fmt)
     X = _orthogonal_start(Z, 0.05, seed + 2)
     Xin = to_dev(X, torch.float32)
     Xout = torch.empty_like(Xin)
-    ws = P.workspace(n, d, P.F32)
+    ws = P.workspace(n, d, P.F32, bsr=True)
     mu = 1.0 / (n * p) if n * p >= 2 else 1.0 / n     # the paper's 1/(np) where it is a sensible step
     P.step_bsr(B, n, d, Xin, Xout, ws, mu=mu)
     torch.cuda.synchronize()
@@ -118,10 +141,13 @@ def test_bsr_step_parity(n, d, p, fmt):
     assert info["nonfinite"] == 0
 
 
-def test_bsr_step_equals_dense_step_on_the_masked_matrix():
+@pytest.mark.parametrize("path", ["sliced", "fused", "slice_w"])
+def test_bsr_step_equals_dense_step_on_the_masked_matrix(path, monkeypatch):
     """The block-sparse step and sync_step on the dense masked A of the same
-    generator agree to the accumulation rounding."""
+    generator agree to the accumulation rounding; the step is bitwise
+    repeatable."""
     require_gpu()
+    _bsr_path(path, monkeypatch)
     n, d, p = 900, 3, 0.5
     Z, sigma, A64 = _masked(n, d, 0.3, 11, p)
     Zd = torch.from_numpy(Z).cuda()
@@ -129,7 +155,7 @@ def test_bsr_step_equals_dense_step_on_the_masked_matrix():
     Ad = P.stored(P.generate(Zd, sigma, 12, fmt=P.F32, p=p), P.F32)
     Xin = to_dev(_orthogonal_start(Z, 0.05, 13), torch.float32)
     out_b, out_d = torch.empty_like(Xin), torch.empty_like(Xin)
-    ws = P.workspace(n, d, P.F32)
+    ws = P.workspace(n, d, P.F32, bsr=True)
     mu = 1.0 / (n * p)
     P.step_bsr(B, n, d, Xin, out_b, ws, mu=mu)
     P.step(Ad, n, d, Xin, out_d, ws, mu=mu)
@@ -141,10 +167,12 @@ def test_bsr_step_equals_dense_step_on_the_masked_matrix():
     assert np.abs(host(out_b) - host(out_d)).max() <= 2 * step_tolerance(As, host(Xin), n, P.F32)
 
 
-def test_bsr_stored_diagonal_and_out_of_range_blocks_count_nothing():
+@pytest.mark.parametrize("path", ["sliced", "fused", "slice_w"])
+def test_bsr_stored_diagonal_and_out_of_range_blocks_count_nothing(path, monkeypatch):
     """A hand-built block-sparse matrix with a NaN diagonal block and a NaN
     block at an out-of-range column gives the oracle's step without them."""
     require_gpu()
+    _bsr_path(path, monkeypatch)
     n, d = 6, 2
     rng = np.random.default_rng(3)
     pairs = [(0, 1), (0, 4), (1, 3), (2, 5), (3, 4)]
@@ -170,13 +198,13 @@ def test_bsr_stored_diagonal_and_out_of_range_blocks_count_nothing():
             blk = (np.full((d, d), np.nan) if (j == i or j >= n)
                    else A[i * d:(i + 1) * d, j * d:(j + 1) * d])
             for e in range(d * d):
-                vals[rp[i] * d * d + e * m + k] = blk.flat[e]
+                vals[rp[i] * d * d + _entry_off(k, e, m, d * d)] = blk.flat[e]
     B = P.BsrMatrix(P.F32, torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(), torch.from_numpy(vals).cuda(),
                     n, d, int(rp[-1]))
     Z = synth.haar_blocks(n, d, 5)
     Xin = to_dev(synth.perturbed_start(Z, 0.05, 6), torch.float32)
     Xout = torch.empty_like(Xin)
-    ws = P.workspace(n, d, P.F32)
+    ws = P.workspace(n, d, P.F32, bsr=True)
     P.step_bsr(B, n, d, Xin, Xout, ws, mu=0.3)
     torch.cuda.synchronize()
     ref = O.rgs_step(A.astype(np.float32).astype(np.float64), host(Xin), d, mu=0.3, Ts=3)

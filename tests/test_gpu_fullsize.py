@@ -158,17 +158,19 @@ def test_fullsize_bf16_refined_solve_matches_fp32(big):
     assert d <= 1e-3
 
 
+@pytest.mark.parametrize("path", ["sliced", "fused"])
 @pytest.mark.parametrize("p", [0.5, 0.2])
-def test_fullsize_bsr_step_sampled_blocks(big, p):
+def test_fullsize_bsr_step_sampled_blocks(big, p, path, monkeypatch):
     """sync_step_bsr at the size bench.py times it (n = 20000, d = 3, block-sparse
     FP32 storage of the incomplete observation model, mu = 1/(np)), on sampled
     block rows of about p n stored blocks each: the rows are regenerated on the
     host by the generator's twin (mask included) and stepped by the oracle."""
+    monkeypatch.setenv("NSRGS_BSR_SLICED", "1" if path == "sliced" else "0")
     Z = big["Z"]
     B = P.generate_bsr(torch.from_numpy(Z).cuda(), big["sigma"], SEED, p, fmt=P.F32)
     Xin = torch.from_numpy(big["X"]).cuda()
     Xout = torch.full_like(Xin, float("nan"))
-    ws = P.workspace(N, D, P.F32)
+    ws = P.workspace(N, D, P.F32, bsr=True)
     mu = 1.0 / (N * p)
     P.step_bsr(B, N, D, Xin, Xout, ws, mu=mu)
     torch.cuda.synchronize()
