@@ -271,18 +271,17 @@ constexpr int kBsrSliceRPW = 4;           // block rows per wave
 __host__ __device__ constexpr int bsr_slice_waves(int d) { return d <= 4 ? 16 : 8; }
 
 __host__ __device__ constexpr int bsr_xs(int d) { return (d * d + 3) / 4 * 4; }   // floats per X_j in LDS
-// Two workgroups per CU (NSRGS_BSR_OCC = 2, d <= 3): 64 KiB slices and at most
-// 64 VGPRs per lane, so that twice as many loads are in flight per CU.
-inline bool bsr_two_per_cu(int d) { return d <= 3 && env_int("NSRGS_BSR_OCC", 1) == 2; }
 // Slice width in blocks: what the LDS slice holds, or less with NSRGS_BSR_SLICE_W.
 inline int bsr_slice_w(int d) {
-  const int bytes = bsr_two_per_cu(d) ? kBsrSliceBytes / 2 : kBsrSliceBytes;
-  const int w = bytes / (4 * bsr_xs(d)), f = env_int("NSRGS_BSR_SLICE_W", 0);
+  const int w = kBsrSliceBytes / (4 * bsr_xs(d)), f = env_int("NSRGS_BSR_SLICE_W", 0);
   return (f > 0 && f < w) ? f : w;
 }
 inline int bsr_slices(int n, int d) { return (n + bsr_slice_w(d) - 1) / bsr_slice_w(d); }
 
-// bounds[s n + i] = first k of block row i with col_idx >= s W, s = 0 .. S.
+// bounds[s n + i] = first k of block row i with col_idx >= s W, s = 0 .. S:
+// one thread per (s, i), a binary search in the row's ascending columns.
+// (Searching all of a row's keys with one wave, each round probing 64
+// positions per key, measured three times slower: most probes are wasted.)
 __global__ void __launch_bounds__(256)
 bsr_bounds_kernel(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx, int n, int S, int W,
                   int32_t *__restrict__ bounds) {
@@ -379,11 +378,7 @@ bsr_slice_kernel(const int64_t *__restrict__ row_ptr, const int32_t *__restrict_
     rlo[q] = bounds[(int64_t)s * n + ic];
     rhi[q] = i < n ? bounds[(int64_t)(s + 1) * n + ic] : rlo[q];   // rows past n have no blocks
   }
-  for (int idx = tid; idx < jn * XS; idx += blockDim.x) {
-    const int jl = idx / XS, e = idx % XS;
-    sXf[idx] = e < D2 ? X[(int64_t)(j0 + jl) * D2 + e] : 0.0f;
-  }
-  __syncthreads();
+  // the first chunk is in flight while the slice of X is staged
   float an[UN][D2];
   int jn_next[UN];
   bool have = false;                                    // wave-uniform: a chunk is in flight
@@ -391,6 +386,11 @@ bsr_slice_kernel(const int64_t *__restrict__ row_ptr, const int32_t *__restrict_
     bsr_chunk_load<E, D, NT, UN>(row[0], rlo[0], rhi[0], lane, an, jn_next);
     have = true;
   }
+  for (int idx = tid; idx < jn * XS; idx += blockDim.x) {
+    const int jl = idx / XS, e = idx % XS;
+    sXf[idx] = e < D2 ? X[(int64_t)(j0 + jl) * D2 + e] : 0.0f;
+  }
+  __syncthreads();
 #pragma unroll
   for (int q = 0; q < RPW; ++q) {
     const int i = g * ROWS + q * NW + wave;
@@ -453,12 +453,14 @@ bsr_slice_kernel(const int64_t *__restrict__ row_ptr, const int32_t *__restrict_
   }
 }
 
-// C_i = the slices' partial sums in slice order, then the per-block step.
+// C_i = the slices' partial sums in slice order, then the per-block step, for
+// kBsrSliceEpiBlocks blocks per workgroup.
+constexpr int kBsrSliceEpiBlocks = 16;
 template <int D>
-__global__ void __launch_bounds__(kWave * kBsrRowsPerGroup)
+__global__ void __launch_bounds__(256)
 bsr_slice_epilogue_kernel(const float *__restrict__ part, int S, StreamArgs sa) {
   constexpr int D2 = D * D;
-  constexpr int NB = kBsrRowsPerGroup;
+  constexpr int NB = kBsrSliceEpiBlocks;
   constexpr int NE = NB * D2;
   __shared__ double s_scr[kMaxWaves];
   __shared__ float sbuf[6 * NE];
@@ -494,10 +496,11 @@ hipError_t bsr_slice_launch_d(const nsrgs_bsr_matrix &A, const StreamArgs &sa, i
   const float *Xf = static_cast<const float *>(sa.X_in);
   // Load hint (NSRGS_BSR_NT, default ordinary loads: a chunk's first and last
   // cache lines are shared with its neighbours) and chunk size
-  // (NSRGS_BSR_UN = 1, 2 or 4 blocks per lane; 2 by default for d <= 3,
-  // where two chunks' registers fit 16 waves per CU; 4 runs 8 waves).
+  // (NSRGS_BSR_UN = 1, 2 or 4 blocks per lane, 2 and 4 for d <= 3 only; one by
+  // default: two measured the same at p = 0.5 and slower at p = 0.2, four
+  // needs 8 waves per CU and was slower).
   const bool nt = env_int("NSRGS_BSR_NT", 0) != 0;
-  const int fu = env_int("NSRGS_BSR_UN", D <= 3 ? 2 : 1);
+  const int fu = env_int("NSRGS_BSR_UN", 1);
   const int un = D <= 3 && (fu == 2 || fu == 4) ? fu : 1;
 #define NSRGS_BSR_SLICE(NTV, UNV, NWV, MINW)                                                               \
   {                                                                                                          \
@@ -511,11 +514,7 @@ hipError_t bsr_slice_launch_d(const nsrgs_bsr_matrix &A, const StreamArgs &sa, i
   }
   // (more than 64 KiB of dynamic LDS has to be allowed per kernel, once)
   constexpr int NW1 = bsr_slice_waves(D);
-  if (bsr_two_per_cu(D)) {
-    if constexpr (D <= 3) {
-      if (nt) NSRGS_BSR_SLICE(true, 1, 16, 8) else NSRGS_BSR_SLICE(false, 1, 16, 8)
-    }
-  } else if (un == 4) {
+  if (un == 4) {
     if constexpr (D <= 3) {
       if (nt) NSRGS_BSR_SLICE(true, 4, 8, 1) else NSRGS_BSR_SLICE(false, 4, 8, 1)
     }
@@ -528,10 +527,11 @@ hipError_t bsr_slice_launch_d(const nsrgs_bsr_matrix &A, const StreamArgs &sa, i
   }
 #undef NSRGS_BSR_SLICE
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL((bsr_slice_epilogue_kernel<D>), dim3(sa.num_panels), dim3(kWave * kBsrRowsPerGroup), 0, s,
-                     part, S, sa);
+  StreamArgs se = sa;
+  se.num_panels = (n + kBsrSliceEpiBlocks - 1) / kBsrSliceEpiBlocks;
+  hipLaunchKernelGGL((bsr_slice_epilogue_kernel<D>), dim3(se.num_panels), dim3(256), 0, s, part, S, se);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL((stream_finish_kernel<float, D, 0>), dim3(1), dim3(256), 0, s, sa);
+  hipLaunchKernelGGL((stream_finish_kernel<float, D, 0>), dim3(1), dim3(256), 0, s, se);
   return hipGetLastError();
 }
 
