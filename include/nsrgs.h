@@ -185,7 +185,11 @@ int sync_workspace_init(void *ws, size_t ws_bytes, void *stream);
  * X_in and X_out are n*d x d device arrays that must not overlap.
  * For d > 16 (F64 / F32 storage) the product runs on the matrix cores
  * (v_mfma 16x16x4 tiles over column chunks, partial sums in the workspace)
- * and the per-block part in FP64.
+ * and the per-block part in FP64; so does d >= 10 with F64 and d >= 13 with
+ * F32 storage when ws holds sync_workspace_bytes(n, d, fmt) bytes, where the
+ * streaming kernel's 2d FMAs per element of A make it the slower one.  (That
+ * product covers whole rows and subtracts A_ii X_i afterwards, so there the
+ * diagonal blocks must be finite; the streaming kernel never reads them.)
  * Monitors (rel_change, max_orth_defect, nonfinite) go to the workspace and
  * can be read with sync_read_info.  Asynchronous. */
 int sync_step(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps,
@@ -247,9 +251,11 @@ int sync_step_noalloc(const nsrgs_matrix *A, int n, int d, double mu, int ns_ste
  * near the diagonal may still be loaded, so they must be readable memory;
  * their contents do not matter.  A may be packed (NSRGS_LD_PACKED), which
  * halves its footprint; the result is the same as from the full layout.
- * Formats F64, F32, BF16 and BF16_SPLIT; 1 <= d <= 16.  FP8_E4M3 is refused
- * with NSRGS_ERR_UNSUPPORTED: its per-row scales make the stored A_ij and
- * A_ji differ.
+ * Formats F64, F32 (1 <= d <= 16), BF16 and BF16_SPLIT (1 <= d <= 12: above
+ * that their tiles spill registers and run slower than sync_step, and the
+ * call refuses them with NSRGS_ERR_UNSUPPORTED).  FP8_E4M3 is refused with
+ * NSRGS_ERR_UNSUPPORTED: its per-row scales make the stored A_ij and A_ji
+ * differ.
  * ws must hold sync_step_symmetric_workspace_bytes(n, d, fmt) bytes: the
  * sync_step workspace followed by the per-tile partial sums (sized for every
  * format with fmt's accumulation type, so one workspace serves F32, BF16 and

@@ -377,12 +377,25 @@ static int wide_step_impl(const nsrgs_matrix *A, int n, int d, double mu, int ns
   return NSRGS_OK;
 }
 
+// NS-RGS with d <= 16 on F64 / F32 storage also runs on the matrix-core
+// product when the workspace holds its region: from d = 10 (F64) and d = 13
+// (F32) on, where it measured faster than the streaming kernel, whose 2d
+// FMAs per element of A outgrow the vector units (n d = 30000: F64 d = 10
+// 2.42 -> 1.72 ms, d = 16 49.7 -> 1.59 ms; F32 d = 13 1.14 -> 0.93 ms, d = 16
+// 3.32 -> 0.92 ms).  NSRGS_WIDE_FROM_D overrides the threshold.
+static bool ns_on_matrix_cores(int fmt, int d, size_t ws_bytes, int n) {
+  if (d > kMaxD) return true;
+  if (!wide_supported_fmt(fmt)) return false;
+  const int from = env_int("NSRGS_WIDE_FROM_D", fmt == NSRGS_A_F64 ? 10 : 13);
+  return d >= from && ws_bytes >= layout(n, d, fmt).total;
+}
+
 static int step_method_entry(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, int method,
                              const void *X_in, void *X_out, void *ws, size_t ws_bytes, void *stream) {
   int st;
   if ((st = check_step_io(A, n, d, mu, ns_steps, X_in, X_out, true))) return st;
   if ((st = check_ws(ws, ws_bytes, n, d, A->fmt, method != WIDE_NS || d > kMaxD))) return st;
-  if (method == WIDE_NS && d <= kMaxD)
+  if (method == WIDE_NS && !ns_on_matrix_cores(A->fmt, d, ws_bytes, n))
     return step_impl(A, n, d, mu, ns_steps, X_in, X_out, ws, (hipStream_t)stream, 0, 0.0, false);
   if (!wide_supported_fmt(A->fmt))
     return fail(NSRGS_ERR_UNSUPPORTED, "this retraction / block size needs F64 or F32 storage");
@@ -686,7 +699,9 @@ int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, int
     return fail(NSRGS_ERR_INVALID_ARG, "unknown stop rule %d", (int)o.stop_rule);
   // The matrix-core path runs d > 16, the exact-polar and GPM retractions and
   // the objective stop rule.
-  const bool wide = d > kMaxD || o.method != NSRGS_METHOD_NS_RGS || o.stop_rule == NSRGS_STOP_OBJECTIVE;
+  const bool wide = d > kMaxD || o.method != NSRGS_METHOD_NS_RGS || o.stop_rule == NSRGS_STOP_OBJECTIVE ||
+                    (!o.symmetric && ns_on_matrix_cores(A->fmt, d, ws_bytes, n) &&
+                     (o.refine_iters <= 0 || !o.A_refine || wide_supported_fmt(o.A_refine->fmt)));
   if (wide) {
     if (!wide_supported_fmt(A->fmt))
       return fail(NSRGS_ERR_UNSUPPORTED, "d > 16, exact polar, GPM and the objective stop need F64 or F32 storage");

@@ -121,6 +121,9 @@ int sym_check(const nsrgs_matrix *A, int n, int d, size_t ws_bytes) {
     return fail(NSRGS_ERR_UNSUPPORTED, "sync_step_symmetric: format %d is not stored symmetrically "
                 "(FP8 row scales differ between A_ij and A_ji)", (int)A->fmt);
   if (d > kSymMaxD) return fail(NSRGS_ERR_UNSUPPORTED, "sync_step_symmetric supports d <= %d", kSymMaxD);
+  if (d > kSymMaxD2 && (A->fmt == NSRGS_A_BF16 || A->fmt == NSRGS_A_BF16_SPLIT))
+    return fail(NSRGS_ERR_UNSUPPORTED, "sync_step_symmetric on 2-byte formats supports d <= %d (larger d spill "
+                "registers and run slower than sync_step)", kSymMaxD2);
   const size_t need = sym_ws_bytes(n, d, A->fmt);
   if (ws_bytes < need)
     return fail(NSRGS_ERR_OUT_OF_MEMORY, "workspace too small for sync_step_symmetric: %zu < %zu bytes", ws_bytes,
@@ -210,6 +213,7 @@ extern "C" {
 
 size_t sync_step_symmetric_workspace_bytes(int n, int d, int fmt) {
   if (n < 2 || d < 1 || d > kSymMaxD || !sym_format(fmt)) return 0;
+  if (d > kSymMaxD2 && (fmt == NSRGS_A_BF16 || fmt == NSRGS_A_BF16_SPLIT)) return 0;
   if ((int64_t)n * d >= (int64_t)1 << 31) return 0;
   return sym_ws_bytes(n, d, fmt);
 }

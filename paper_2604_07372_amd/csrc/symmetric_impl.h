@@ -52,6 +52,10 @@ struct SymArgs {
 // Blocks per epilogue workgroup, per d.
 constexpr int sym_epi_blocks(int d) { return d == 1 ? 64 : d == 2 ? 32 : d <= 4 ? 16 : d == 5 ? 8 : d == 6 ? 6 : 4; }
 constexpr int kSymMaxD = 16;
+// 2-byte formats: above d = 12 a lane's 8-element column slice and its sums
+// (16 d values) spill, and the step measured slower than the full stream
+// (n d = 30000, BF16: d = 13 2.01 ms against 1.59, d = 16 7.2 against 3.06).
+constexpr int kSymMaxD2 = 12;
 
 // The rows [strip0, strip1) of one tile for this wave's columns.
 template <int FMT, int D, int R, int U, bool MASK>

@@ -135,6 +135,11 @@ def test_symmetric_step_workspace_and_refusals():
     assert L.sync_step_symmetric_workspace_bytes(100, 17, P.F32) == 0         # d <= 16
     assert L.sync_step_symmetric_workspace_bytes(100, 16, P.F32) > 0
     assert L.sync_step_symmetric_workspace_bytes(100, 3, P.FP8_E4M3) == 0     # not symmetric storage
+    assert L.sync_step_symmetric_workspace_bytes(100, 13, P.BF16) == 0        # 2-byte formats: d <= 12
+    assert L.sync_step_symmetric_workspace_bytes(100, 12, P.BF16_SPLIT) > 0
+    assert L.sync_step_symmetric_workspace_bytes(100, 13, P.F32) > 0
+    st = L.sync_step_symmetric(ctypes.byref(_mat(P.BF16, ld=1312)), 100, 13, 0.0, 3, 4096, 1 << 20, 256, 1 << 30, None)
+    assert st == 2 and "2-byte" in L.nsrgs_last_error().decode()
     assert L.sync_step_symmetric_workspace_bytes(1, 3, P.F32) == 0
     n, d = 20000, 3
     base = L.sync_workspace_bytes(n, d, P.F32)

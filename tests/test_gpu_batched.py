@@ -30,7 +30,10 @@ def _batch(fmt, shapes, seed=0, c=0.25):
 
 
 def _alone(p, iters, monkeypatch, waves):
-    """The same problem through sync_solve with the batched launch's panel shape."""
+    """The same problem through sync_solve with the batched launch's panel shape
+    (on the streaming kernel, whose arithmetic the batched kernels share: not
+    on the matrix cores, which sync_solve picks for F64 from d = 10)."""
+    monkeypatch.setenv("NSRGS_WIDE_FROM_D", "99")
     rows = P.batch_rows_per_panel(p["d"])
     monkeypatch.setenv("NSRGS_STEP_B", str(rows // p["d"]))
     monkeypatch.setenv("NSRGS_STEP_U", "1")

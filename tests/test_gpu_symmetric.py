@@ -44,6 +44,10 @@ def _run(Ad, n, d, Xin, fmt, ws=None):
 def test_symmetric_step_parity(n, d, fmt):
     require_gpu()
     print(f"symmetric step parity n={n} d={d} fmt={FMT_NAME[fmt]}", flush=True)
+    if fmt in (P.BF16, P.BF16_SPLIT) and d > 12:
+        # refused: the 2-byte tiles spill above d = 12 and lose to sync_step
+        assert P.symmetric_workspace_bytes(n, d, fmt) == 0
+        return
     Z, A64, X = _problem(n, d, seed=1000 * n + d)
     assert np.array_equal(A64, A64.T)
     Ad = device_matrix(A64, fmt)
