@@ -80,14 +80,15 @@ typedef enum {
 
 /* Packed upper-block-triangle layout of a symmetric A, selected by
  * nsrgs_matrix.ld == NSRGS_LD_PACKED.  With ndp = n d rounded up to a multiple
- * of 16, row r of block row i = r / d keeps the columns [c0(i), ndp),
- * c0(i) = 16 floor(i d / 16): its part on and above the diagonal block,
- * widened to the left to a multiple of 16 (so every 16-element group of the
- * full layout stays whole and 16-byte aligned).  Rows follow one another
- * without gaps: element (r, c), c0(i) <= c < ndp, is at
+ * of 64, row r of block row i = r / d keeps the columns [c0(i), ndp),
+ * c0(i) = 64 floor(i d / 64): its part on and above the diagonal block,
+ * widened to the left to a multiple of 64 (so every row starts on a 64-element
+ * boundary: whole cache lines for the streaming loads, as in the full layout
+ * with ld a multiple of 64).  Rows follow one another without gaps: element
+ * (r, c), c0(i) <= c < ndp, is at
  *     off(r) + c - c0(i),   off(r) = d sum_{b < i} (ndp - c0(b)) + (r - i d)(ndp - c0(i)),
  * and the whole matrix takes nsrgs_packed_elems(n, d) elements, about
- * (n d)^2 / 2 + n d (d + 16).  Columns c >= n d are padding (the generator
+ * (n d)^2 / 2 + n d (d + 64) / 2.  Columns c >= n d are padding (the generator
  * writes zeros there); columns below the diagonal block that the widening
  * keeps hold A(r, c) when the generator writes them and are never used.
  * BF16_SPLIT keeps its low part in data_lo with the same layout. */

@@ -44,31 +44,36 @@ static_assert(sizeof(DevCtl) % 256 == 0, "DevCtl must keep 256-byte alignment");
 
 // --------------------------------------------------------------------------
 // Packed upper-block-triangle storage of a symmetric A (ld == NSRGS_LD_PACKED).
-// With ndp = n d rounded up to 16, row r of block i = r / d stores the columns
-// [c0(i), ndp), c0(i) = 16 floor(i d / 16): the row's part on and above its
-// diagonal block, widened to the left to a multiple of 16 so that every
-// column keeps the 16-element alignment of the full layout (a 16-byte vector
-// never straddles a row).  Rows follow one another; element (r, c), c >= c0(i),
-// is at packed_row_offset(r) + c - c0(i).  Columns past n d are padding.
+// With G = 64 and ndp = n d rounded up to G, row r of block i = r / d stores
+// the columns [c0(i), ndp), c0(i) = G floor(i d / G): the row's part on and
+// above its diagonal block, widened to the left to a multiple of G so that
+// every row starts on a 256-byte boundary (FP32; 128 bytes for 2-byte
+// formats): a wave's 16-byte loads then cover whole cache lines, as in the
+// full layout with ld a multiple of 64.  Rows follow one another; element
+// (r, c), c >= c0(i), is at packed_row_offset(r) + c - c0(i).  Columns past
+// n d are padding.
 // --------------------------------------------------------------------------
-__host__ __device__ inline int packed_c0(int64_t i, int d) { return (int)(16 * ((i * d) / 16)); }
+constexpr int kPackedG = 64;
+
+__host__ __device__ inline int packed_c0(int64_t i, int d) { return (int)(kPackedG * ((i * d) / kPackedG)); }
 
 // Elements stored before block row i: d * sum_{b < i} (ndp - c0(b)).
 __host__ __device__ inline int64_t packed_block_start(int64_t i, int d, int64_t ndp) {
-  // sum_{b < i} floor(b d / 16) = (d i (i - 1) / 2 - sum_{b < i} (b d mod 16)) / 16; the residues
-  // b d mod 16 repeat with period P = 16 / gcd(d, 16) and sum to 8 (P - 1) over a period
-  int g = 16, x = d;
+  // sum_{b < i} floor(b d / G) = (d i (i - 1) / 2 - sum_{b < i} (b d mod G)) / G; the residues
+  // b d mod G repeat with period P = G / gcd(d, G), taking every multiple of gcd(d, G) below G
+  // once, so they sum to G (P - 1) / 2 over a period
+  int g = kPackedG, x = d;
   while (x) {
     const int t = g % x;
     g = x;
     x = t;
   }
-  const int64_t P = 16 / g;
+  const int64_t P = kPackedG / g;
   const int64_t q = i / P, rem = i % P;
-  int64_t res = q * 8 * (P - 1);
-  for (int64_t b = 0; b < rem; ++b) res += (b * d) % 16;
-  const int64_t floors = (d * i * (i - 1) / 2 - res) / 16;
-  return (int64_t)d * (i * ndp - 16 * floors);
+  int64_t res = q * (kPackedG / 2) * (P - 1);
+  for (int64_t b = 0; b < rem; ++b) res += (b * d) % kPackedG;
+  const int64_t floors = (d * i * (i - 1) / 2 - res) / kPackedG;
+  return (int64_t)d * (i * ndp - kPackedG * floors);
 }
 
 __host__ __device__ inline int64_t packed_row_offset(int64_t r, int d, int64_t ndp) {
@@ -76,9 +81,12 @@ __host__ __device__ inline int64_t packed_row_offset(int64_t r, int d, int64_t n
   return packed_block_start(i, d, ndp) + (r - i * d) * (ndp - packed_c0(i, d));
 }
 
+__host__ __device__ inline int64_t packed_ndp(int n, int d) {
+  return ((int64_t)n * d + kPackedG - 1) / kPackedG * kPackedG;
+}
+
 __host__ __device__ inline int64_t packed_elems(int n, int d) {
-  const int64_t ndp = ((int64_t)n * d + 15) / 16 * 16;
-  return packed_block_start(n, d, ndp);
+  return packed_block_start(n, d, packed_ndp(n, d));
 }
 
 // Monitors of one panel of the step kernel (FP64 for every storage format).

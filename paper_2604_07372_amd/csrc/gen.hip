@@ -26,7 +26,7 @@ generate_kernel(const double *__restrict__ Z, int n, int d, double sigma, uint32
   T *out;
   int cbeg, cend;
   if (ld == NSRGS_LD_PACKED) {
-    const int64_t ndp = ((int64_t)nd + 15) / 16 * 16;
+    const int64_t ndp = packed_ndp(n, d);
     cbeg = packed_c0(br, d);
     cend = (int)ndp;
     out = A + packed_row_offset(r, d, ndp) - cbeg;

@@ -146,7 +146,7 @@ static int sym_launch(const nsrgs_matrix *A, int n, int d, double mu, int ns_ste
   a.A = A->data;
   a.A_lo = A->fmt == NSRGS_A_BF16_SPLIT ? A->data_lo : nullptr;
   a.ld = A->ld;
-  a.ndp = ((int64_t)nd + 15) / 16 * 16;
+  a.ndp = packed_ndp(n, d);
   a.X_in = X_in;
   a.nd = nd;
   a.H = c.H;

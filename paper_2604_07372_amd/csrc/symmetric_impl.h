@@ -29,7 +29,7 @@ struct SymArgs {
   const void *A;
   const void *A_lo;
   int64_t ld;             // elements; NSRGS_LD_PACKED: packed upper block triangle
-  int64_t ndp;            // packed: n d rounded up to 16
+  int64_t ndp;            // packed: n d rounded up to 64 (packed_ndp)
   const void *X_in;
   int nd;
   int H;          // strip height (rows), a multiple of d, of R and of the epilogue panel
@@ -88,6 +88,9 @@ __device__ __forceinline__ void sym_tile_rows(const SymArgs &a, const typename F
   // wave-uniform: the block of this wave's last column inside the matrix
   const int wlast_blk = cw0 < nd ? (min(cw0 + WCOLS, nd) - 1) / D : -1;
 
+  // packed layout: element offset of the next panel's first row, carried from
+  // panel to panel (-1: compute it from the closed form)
+  int64_t next_off = -1;
   for (int row0 = strip0; row0 < strip1; row0 += R) {
     T *out = myrow + (row0 - strip0) * D;
     if (MASK && row0 / D >= wlast_blk) {
@@ -95,6 +98,7 @@ __device__ __forceinline__ void sym_tile_rows(const SymArgs &a, const typename F
       // block diagonal (or past nd): its sums are zero
       static_assert(N <= kWave, "one lane per panel entry");
       out[lane < N ? lane : N - 1] = T(0);
+      next_off = -1;
       continue;
     }
     int64_t rowoff[R];
@@ -103,14 +107,18 @@ __device__ __forceinline__ void sym_tile_rows(const SymArgs &a, const typename F
       // of the row's stored range are never used: they lie below the block
       // diagonal, and a clamped column-0 read lands in earlier rows' storage)
       const int rfirst = (!MASK || row0 < nd) ? row0 : nd - 1;
-      int64_t off = packed_row_offset(rfirst, D, a.ndp);
+      int64_t off = next_off >= 0 ? next_off : packed_row_offset(rfirst, D, a.ndp);
+      int rlast = rfirst;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int row = (!MASK || row0 + r < nd) ? row0 + r : nd - 1;
         const int prev = r == 0 ? row : ((!MASK || row0 + r - 1 < nd) ? row0 + r - 1 : nd - 1);
         if (r > 0 && row != prev) off += a.ndp - packed_c0(prev / D, D);   // the previous row's length
         rowoff[r] = (off - packed_c0(row / D, D)) * EB;
+        rlast = row;
       }
+      // the next panel starts after this panel's last row (past nd: no next panel)
+      next_off = off + a.ndp - packed_c0(rlast / D, D);
     } else {
 #pragma unroll
       for (int r = 0; r < R; ++r) {

@@ -24,25 +24,25 @@ SHAPES = [(2, 1), (2, 3), (5, 2), (37, 3), (341, 3), (700, 3), (1500, 1), (100, 
 
 
 def pack_host(A: np.ndarray, n: int, d: int) -> np.ndarray:
-    """Row r of block i = r // d keeps the columns [16 floor(i d / 16), ndp) of
-    the matrix padded with zero columns to ndp = n d rounded up to 16; rows
+    """Row r of block i = r // d keeps the columns [64 floor(i d / 64), ndp) of
+    the matrix padded with zero columns to ndp = n d rounded up to 64; rows
     follow one another."""
     nd = n * d
-    ndp = -(-nd // 16) * 16
+    ndp = -(-nd // 64) * 64
     Af = np.zeros((nd, ndp), dtype=A.dtype)
     Af[:, :nd] = A[:, :nd]
-    return np.concatenate([Af[r, 16 * (((r // d) * d) // 16):] for r in range(nd)])
+    return np.concatenate([Af[r, 64 * (((r // d) * d) // 64):] for r in range(nd)])
 
 
 def stored_mask(n: int, d: int) -> np.ndarray:
     """Which packed positions lie on or above the block diagonal inside the
     matrix (the entries the method reads), in packed order."""
     nd = n * d
-    ndp = -(-nd // 16) * 16
+    ndp = -(-nd // 64) * 64
     out = []
     for r in range(nd):
         i = r // d
-        c = np.arange(16 * ((i * d) // 16), ndp)
+        c = np.arange(64 * ((i * d) // 64), ndp)
         out.append((c >= i * d) & (c < nd))
     return np.concatenate(out)
 
@@ -77,7 +77,7 @@ def full_matrix(A64: np.ndarray, fmt: int) -> P.StoredMatrix:
                                              (9, 32, False, 1.0), (1000, 1, False, 1.0), (150, 7, True, 0.3)])
 def test_generator_writes_the_packed_layout(n, d, zero_diag, p, fmt):
     """Packed output = the full output's upper block triangle (widened to
-    16-column groups), bit for bit, with zero padding columns."""
+    64-column groups), bit for bit, with zero padding columns."""
     require_gpu()
     print(f"packed generator n={n} d={d} fmt={FMT_NAME[fmt]}", flush=True)
     Z = torch.from_numpy(synth.haar_blocks(n, d, 3)).cuda()
@@ -103,7 +103,7 @@ def test_packed_conversion_matches_the_full_conversion(n, d, fmt):
     assert np.array_equal(cp.data.cpu().numpy(), pack_host(cf.data.cpu().numpy(), n, d))
     if fmt == P.BF16_SPLIT:
         assert np.array_equal(cp.data_lo.cpu().numpy(), pack_host(cf.data_lo.cpu().numpy(), n, d))
-    assert cp.nbytes < 0.5 * cf.nbytes + 64 * n * d * (d + 16)
+    assert cp.nbytes < 0.5 * cf.nbytes + 64 * n * d * (d + 64)
 
 
 @pytest.mark.parametrize("fmt", SYM_FMTS, ids=lambda f: FMT_NAME[f])
@@ -140,7 +140,7 @@ def test_packed_symmetric_step_parity(n, d, fmt):
 @pytest.mark.parametrize("d", [1, 3, 5, 8, 16])
 def test_packed_entries_below_the_diagonal_and_padding_are_never_used(d):
     """NaN in every packed position below the block diagonal (the widening to
-    16-column groups keeps some) and in the padding columns."""
+    64-column groups keeps some) and in the padding columns."""
     require_gpu()
     n = 211
     Z, A64, X = symmetric_problem(n, d, seed=41 + d)
