@@ -308,16 +308,19 @@ int nsrgs_bsr_fill(const double *Z, int n, int d, double sigma, double p, uint64
 /* sync_step on block-sparse A: C_i = sum over stored j != i of A_ij X_j, then
  * the per-block step of sync_step.  X_in / X_out are FP32.  mu <= 0 selects
  * 1/n; for the incomplete observation model pass mu = 1/(np).  1 <= d <= 32.
- * For d <= 8, with ws of sync_step_bsr_workspace_bytes(n, d) bytes the step
- * runs sliced: block columns are cut into slices whose X fits 64 KiB of LDS,
+ * For d <= 6, with ws of sync_step_bsr_workspace_bytes(n, d) bytes the step
+ * runs sliced: block columns are cut into slices whose X fits 128 KiB of LDS,
  * each workgroup streams its block rows' blocks of one slice (their X_j read
  * from LDS), and an epilogue adds the slices' partial sums in slice order;
- * with a smaller ws (at least the sync_step part of sync_workspace_bytes) it
- * runs one fused kernel, one wave per block row, reading X_j through the
- * caches.  Both give the same C_i up to the order of additions.  For d > 8
+ * for d <= 8 with a smaller ws (at least the sync_step part of
+ * sync_workspace_bytes) it runs one fused kernel, one wave per block row,
+ * reading X_j through the caches.  Both give the same C_i up to the order of additions.  For d > 8
  * ws must hold sync_workspace_bytes(n, d, NSRGS_A_F32) bytes, and a
  * block-sparse product (chunks of blocks through LDS) is followed by the
  * matrix-core path's per-block epilogue.  Asynchronous. */
+/* sync_workspace_bytes(n, d, NSRGS_A_F32) plus, for d <= 6, the sliced
+ * product's slice bounds and partial sums after it; serves sync_step_bsr and
+ * sync_solve_bsr. */
 size_t sync_step_bsr_workspace_bytes(int n, int d);   /* 0 for unsupported (n, d) */
 int sync_step_bsr(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_steps,
                   const void *X_in, void *X_out, void *ws, size_t ws_bytes, void *stream);
@@ -333,7 +336,16 @@ int sync_step_bsr(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_ste
  * as zero, which leaves the iteration unchanged (it never reads them) and
  * shifts the spectrum only by A_ii (= I in the paper's model, so the same
  * eigenvectors).  X: FP32 device n*d x d; ws of sync_workspace_bytes(n, d,
- * NSRGS_A_F32) bytes; 1 <= d <= 32.  Waits for the stream and fills *info. */
+ * NSRGS_A_F32) bytes; 1 <= d <= 32.  With d <= 6 and ws of
+ * sync_step_bsr_workspace_bytes(n, d) bytes every product (initialization and
+ * iterations) runs on the sliced kernel of sync_step_bsr, its slice bounds
+ * found once per call; NS-RGS iterations with the relative-change rule are
+ * then sync_step_bsr's steps (its per-block epilogue, FP32), the others add
+ * the slices' partial sums in slice order for the matrix-core path's FP64
+ * per-block epilogue.  Otherwise, and for the first product of a solve with
+ * the R^t rule (which also sums the squares of A), a chunked block-sparse
+ * product that serves any d.  Waits for the stream and fills *info (the
+ * objective fields only when the R^t rule or the matrix-core epilogue ran). */
 int sync_solve_bsr(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_steps, int max_iters,
                    double tol, void *X, void *ws, size_t ws_bytes, void *stream,
                    const nsrgs_solve_opts *opts, nsrgs_info *info);

@@ -499,7 +499,8 @@ def solve_bsr(A: BsrMatrix, n: int, d: int, X: torch.Tensor, ws: Workspace, mu: 
               init_iters: int = 60, init_tol: float = 0.0, check_every: int = 16, check: bool = True,
               method: str = "ns_rgs", stop: str = "rel_change") -> dict:
     """sync_solve_bsr: Algorithm 2 on block-sparse A (spectral initialization with
-    the block-sparse product, then the iterations); ws = workspace(n, d, F32)."""
+    the block-sparse product, then the iterations); ws = workspace(n, d, F32), or
+    workspace(n, d, F32, bsr=True) for the sliced product at d <= 6."""
     _check_x(X, n * d, d, F32, "X")
     m = A.c()
     opts = _SolveOpts(int(init), int(init_iters), float(init_tol), 0, None, int(check_every), 0,

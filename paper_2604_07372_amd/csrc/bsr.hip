@@ -279,9 +279,15 @@ inline int bsr_slice_w(int d) {
 inline int bsr_slices(int n, int d) { return (n + bsr_slice_w(d) - 1) / bsr_slice_w(d); }
 
 // bounds[s n + i] = first k of block row i with col_idx >= s W, s = 0 .. S:
-// one thread per (s, i), a binary search in the row's ascending columns.
-// (Searching all of a row's keys with one wave, each round probing 64
-// positions per key, measured three times slower: most probes are wasted.)
+// one thread per (s, i).  The row's columns ascend over [0, n), so the entry
+// sits near m s W / n when the stored blocks spread evenly (as the mask's do);
+// the search probes that guess, gallops away from it in steps of 32, 64, ...
+// entries until the answer is bracketed, and bisects the bracket.  The result
+// is the unique first index whatever the spread (an uneven row costs only
+// more gallop steps); about four cache lines per search against ten to
+// fourteen for a bisection of the whole row.  (Searching all of a row's keys
+// with one wave, each round probing 64 positions per key, measured three
+// times slower: most probes are wasted.)
 __global__ void __launch_bounds__(256)
 bsr_bounds_kernel(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx, int n, int S, int W,
                   int32_t *__restrict__ bounds) {
@@ -289,11 +295,39 @@ bsr_bounds_kernel(const int64_t *__restrict__ row_ptr, const int32_t *__restrict
   if (t >= (int64_t)(S + 1) * n) return;
   const int s = (int)(t / n), i = (int)(t % n);
   const int64_t base = row_ptr[i];
+  const int64_t m = row_ptr[i + 1] - base;
   const int64_t key = (int64_t)s * W;
-  int64_t lo = 0, hi = row_ptr[i + 1] - base;
+  const int32_t *__restrict__ c = col_idx + base;
+  int64_t lo, hi;                                   // the answer lies in [lo, hi]
+  if (m <= 0 || key <= 0) {
+    lo = hi = 0;
+  } else if (key >= n) {
+    lo = hi = m;
+  } else {
+    const int64_t g = m * key / n;                  // < m
+    if (c[g] < key) {                               // answer in (g, m]: gallop up
+      lo = g + 1;
+      hi = m;
+      for (int64_t step = 32;; step *= 2) {
+        const int64_t q = g + step;
+        if (q >= m) break;
+        if (c[q] >= key) { hi = q; break; }
+        lo = q + 1;
+      }
+    } else {                                        // answer in [0, g]: gallop down
+      lo = 0;
+      hi = g;
+      for (int64_t step = 32;; step *= 2) {
+        const int64_t q = g - step;
+        if (q < 0) break;
+        if (c[q] < key) { lo = q + 1; break; }
+        hi = q;
+      }
+    }
+  }
   while (lo < hi) {
     const int64_t mid = (lo + hi) / 2;
-    if (col_idx[base + mid] < key) lo = mid + 1;
+    if (c[mid] < key) lo = mid + 1;
     else hi = mid;
   }
   bounds[t] = (int32_t)lo;
@@ -357,10 +391,13 @@ template <typename E, int D, bool NT, int UN, int NW, int MINW = 1>
 __global__ void __launch_bounds__(kWave * NW, MINW)
 bsr_slice_kernel(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
                  const E *__restrict__ values, const int32_t *__restrict__ bounds, const float *__restrict__ X,
-                 int n, int W, float *__restrict__ part) {
+                 int n, int W, float *__restrict__ part, const int *stop_flag) {
   constexpr int D2 = D * D, XS = bsr_xs(D), XQ = XS / 4, RPW = kBsrSliceRPW, CH = kWave * UN;
   constexpr int ROWS = NW * kBsrSliceRPW;
   extern __shared__ float4 sX4[];
+  if (stop_flag) {
+    if (__atomic_load_n(stop_flag, __ATOMIC_RELAXED)) return;   // uniform: a solve has stopped
+  }
   float *sXf = reinterpret_cast<float *>(sX4);
   const int tid = threadIdx.x, lane = tid & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -464,6 +501,9 @@ bsr_slice_epilogue_kernel(const float *__restrict__ part, int S, StreamArgs sa) 
   constexpr int NE = NB * D2;
   __shared__ double s_scr[kMaxWaves];
   __shared__ float sbuf[6 * NE];
+  if (sa.stop_flag) {
+    if (__atomic_load_n(sa.stop_flag, __ATOMIC_RELAXED)) return;   // uniform: a solve has stopped
+  }
   const int tid = threadIdx.x, n = sa.n;
   const float *__restrict__ X = static_cast<const float *>(sa.X_in);
   float *sX = sbuf, *sC = sX + NE, *sG = sC + NE, *sT = sG + NE, *sF = sT + NE, *sM = sF + NE;
@@ -482,18 +522,22 @@ bsr_slice_epilogue_kernel(const float *__restrict__ part, int S, StreamArgs sa) 
                                     s_scr);
 }
 
-template <typename E, int D>
-hipError_t bsr_slice_launch_d(const nsrgs_bsr_matrix &A, const StreamArgs &sa, int32_t *bounds, float *part,
-                              hipStream_t s) {
-  const int n = sa.n, W = bsr_slice_w(D), S = bsr_slices(n, D);
+hipError_t bsr_bounds_launch(const nsrgs_bsr_matrix &A, int n, int d, int32_t *bounds, hipStream_t s) {
+  const int W = bsr_slice_w(d), S = bsr_slices(n, d);
   const int64_t nb = (int64_t)(S + 1) * n;
   hipLaunchKernelGGL(bsr_bounds_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, A.row_ptr, A.col_idx,
                      n, S, W, bounds);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+// The sliced product: part[s n + i] = slice s's share of block row i's
+// C_i, from the bounds table of bsr_bounds_launch.
+template <typename E, int D>
+hipError_t bsr_slice_product_d(const nsrgs_bsr_matrix &A, int n, const float *Xf, const int32_t *bounds,
+                               float *part, const int *stop_flag, hipStream_t s) {
+  const int W = bsr_slice_w(D), S = bsr_slices(n, D);
   const size_t lds = (size_t)W * bsr_xs(D) * sizeof(float);
   const E *vals = static_cast<const E *>(A.values);
-  const float *Xf = static_cast<const float *>(sa.X_in);
   // Load hint (NSRGS_BSR_NT, default ordinary loads: a chunk's first and last
   // cache lines are shared with its neighbours) and chunk size
   // (NSRGS_BSR_UN = 1, 2 or 4 blocks per lane, 2 and 4 for d <= 3 only; one by
@@ -510,7 +554,7 @@ hipError_t bsr_slice_launch_d(const nsrgs_bsr_matrix &A, const StreamArgs &sa, i
     if (!ok_) return hipErrorInvalidConfiguration;                                                         \
     const dim3 grid_((n + NWV * kBsrSliceRPW - 1) / (NWV * kBsrSliceRPW), S);                                \
     hipLaunchKernelGGL((bsr_slice_kernel<E, D, NTV, UNV, NWV, MINW>), grid_, dim3(kWave * NWV), lds, s,      \
-                       A.row_ptr, A.col_idx, vals, bounds, Xf, n, W, part);                                  \
+                       A.row_ptr, A.col_idx, vals, bounds, Xf, n, W, part, stop_flag);                       \
   }
   // (more than 64 KiB of dynamic LDS has to be allowed per kernel, once)
   constexpr int NW1 = bsr_slice_waves(D);
@@ -526,7 +570,21 @@ hipError_t bsr_slice_launch_d(const nsrgs_bsr_matrix &A, const StreamArgs &sa, i
     if (nt) NSRGS_BSR_SLICE(true, 1, NW1, 1) else NSRGS_BSR_SLICE(false, 1, NW1, 1)
   }
 #undef NSRGS_BSR_SLICE
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+// One sliced step: the bounds (unless a solve found them already), the
+// product, the epilogue and the monitor finish; sa.stop_flag (a solve's) ends
+// every launch at once after the stop rule has fired.
+template <typename E, int D>
+hipError_t bsr_slice_launch_d(const nsrgs_bsr_matrix &A, const StreamArgs &sa, int32_t *bounds, float *part,
+                              bool find_bounds, hipStream_t s) {
+  const int n = sa.n, S = bsr_slices(n, D);
+  hipError_t e;
+  if (find_bounds && (e = bsr_bounds_launch(A, n, D, bounds, s)) != hipSuccess) return e;
+  if ((e = bsr_slice_product_d<E, D>(A, n, static_cast<const float *>(sa.X_in), bounds, part, sa.stop_flag, s)) !=
+      hipSuccess)
+    return e;
   StreamArgs se = sa;
   se.num_panels = (n + kBsrSliceEpiBlocks - 1) / kBsrSliceEpiBlocks;
   hipLaunchKernelGGL((bsr_slice_epilogue_kernel<D>), dim3(se.num_panels), dim3(256), 0, s, part, S, se);
@@ -535,23 +593,52 @@ hipError_t bsr_slice_launch_d(const nsrgs_bsr_matrix &A, const StreamArgs &sa, i
   return hipGetLastError();
 }
 
+// C_i for the matrix-core path's epilogue: P[(i d + a) 32 + c] = the slices'
+// partial sums of entry (a, c) in slice order (the order of the sliced step).
+template <int D>
+__global__ void __launch_bounds__(256)
+bsr_slice_to_wide_kernel(const float *__restrict__ part, int S, int n, float *__restrict__ P, const int *stop_flag) {
+  constexpr int D2 = D * D;
+  if (stop_flag) {
+    if (__atomic_load_n(stop_flag, __ATOMIC_RELAXED)) return;   // uniform
+  }
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * D2) return;
+  const int i = (int)(t / D2), e = (int)(t % D2);
+  float c = 0.0f;
+  for (int s = 0; s < S; ++s) c += part[((int64_t)s * n + i) * D2 + e];
+  P[((int64_t)i * D + e / D) * 32 + e % D] = c;
+}
+
+template <typename E, int D>
+hipError_t bsr_slice_wide_d(const nsrgs_bsr_matrix &A, int n, const float *X, const int32_t *bounds, float *part,
+                            float *P, const int *stop_flag, hipStream_t s) {
+  hipError_t e = bsr_slice_product_d<E, D>(A, n, X, bounds, part, stop_flag, s);
+  if (e != hipSuccess) return e;
+  const int64_t nt = (int64_t)n * D * D;
+  hipLaunchKernelGGL((bsr_slice_to_wide_kernel<D>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, part,
+                     bsr_slices(n, D), n, P, stop_flag);
+  return hipGetLastError();
+}
+
 template <typename E>
 hipError_t bsr_slice_launch(int d, const nsrgs_bsr_matrix &A, const StreamArgs &sa, int32_t *bounds, float *part,
-                            hipStream_t s) {
+                            bool find_bounds, hipStream_t s) {
   switch (d) {
-    case 1: return bsr_slice_launch_d<E, 1>(A, sa, bounds, part, s);
-    case 2: return bsr_slice_launch_d<E, 2>(A, sa, bounds, part, s);
-    case 3: return bsr_slice_launch_d<E, 3>(A, sa, bounds, part, s);
-    case 4: return bsr_slice_launch_d<E, 4>(A, sa, bounds, part, s);
-    case 5: return bsr_slice_launch_d<E, 5>(A, sa, bounds, part, s);
-    case 6: return bsr_slice_launch_d<E, 6>(A, sa, bounds, part, s);
+    case 1: return bsr_slice_launch_d<E, 1>(A, sa, bounds, part, find_bounds, s);
+    case 2: return bsr_slice_launch_d<E, 2>(A, sa, bounds, part, find_bounds, s);
+    case 3: return bsr_slice_launch_d<E, 3>(A, sa, bounds, part, find_bounds, s);
+    case 4: return bsr_slice_launch_d<E, 4>(A, sa, bounds, part, find_bounds, s);
+    case 5: return bsr_slice_launch_d<E, 5>(A, sa, bounds, part, find_bounds, s);
+    case 6: return bsr_slice_launch_d<E, 6>(A, sa, bounds, part, find_bounds, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-// Workspace of the sliced step: the sync_step part, then the slice bounds and
-// the partial sums.
-size_t bsr_slice_table_off(int n, int d) { return narrow_ws_bytes(n, d, NSRGS_A_F32); }
+// Workspace of the sliced product: everything sync_workspace_bytes covers (the
+// sync_step part and the matrix-core region a solve uses), then the slice
+// bounds and the partial sums.
+size_t bsr_slice_table_off(int n, int d) { return sync_workspace_bytes(n, d, NSRGS_A_F32); }
 size_t bsr_slice_part_off(int n, int d) {
   return bsr_slice_table_off(n, d) + align256((size_t)(bsr_slices(n, d) + 1) * n * sizeof(int32_t));
 }
@@ -687,6 +774,63 @@ hipError_t launch_bsr_wide_product(const nsrgs_bsr_matrix &A, int n, int d, cons
   return hipGetLastError();
 }
 
+bool bsr_sliced(int n, int d, size_t ws_bytes) {
+  return d <= kBsrSliceMaxD && (int64_t)n * d * d * 4 < ((int64_t)1 << 31) && ws_bytes >= bsr_slice_ws_bytes(n, d) &&
+         env_int("NSRGS_BSR_SLICED", 1) != 0;
+}
+
+hipError_t launch_bsr_slice_bounds(const nsrgs_bsr_matrix &A, int n, int d, void *ws, hipStream_t s) {
+  return bsr_bounds_launch(A, n, d, reinterpret_cast<int32_t *>(static_cast<char *>(ws) + bsr_slice_table_off(n, d)),
+                           s);
+}
+
+template <typename E>
+static hipError_t slice_wide(const nsrgs_bsr_matrix &A, int n, int d, const float *X, const int32_t *bounds,
+                             float *part, float *P, const int *stop_flag, hipStream_t s) {
+  switch (d) {
+    case 1: return bsr_slice_wide_d<E, 1>(A, n, X, bounds, part, P, stop_flag, s);
+    case 2: return bsr_slice_wide_d<E, 2>(A, n, X, bounds, part, P, stop_flag, s);
+    case 3: return bsr_slice_wide_d<E, 3>(A, n, X, bounds, part, P, stop_flag, s);
+    case 4: return bsr_slice_wide_d<E, 4>(A, n, X, bounds, part, P, stop_flag, s);
+    case 5: return bsr_slice_wide_d<E, 5>(A, n, X, bounds, part, P, stop_flag, s);
+    case 6: return bsr_slice_wide_d<E, 6>(A, n, X, bounds, part, P, stop_flag, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_bsr_slice_wide_product(const nsrgs_bsr_matrix &A, int n, int d, const float *X, float *P,
+                                         void *ws, const int *stop_flag, hipStream_t s) {
+  char *base = static_cast<char *>(ws);
+  const int32_t *bounds = reinterpret_cast<const int32_t *>(base + bsr_slice_table_off(n, d));
+  float *part = reinterpret_cast<float *>(base + bsr_slice_part_off(n, d));
+  return A.fmt == NSRGS_A_F32 ? slice_wide<float>(A, n, d, X, bounds, part, P, stop_flag, s)
+                              : slice_wide<uint16_t>(A, n, d, X, bounds, part, P, stop_flag, s);
+}
+
+int bsr_sliced_iterate(const nsrgs_bsr_matrix &A, int n, int d, double mu, int ns_steps, const void *X_in,
+                       void *X_out, void *ws, hipStream_t s, int iter, double tol) {
+  StreamArgs sa{};
+  sa.X_in = X_in;
+  sa.X_out = X_out;
+  sa.n = n;
+  sa.d = d;
+  sa.nd = n * d;
+  sa.mu = mu > 0.0 ? mu : 1.0 / n;
+  sa.ns_steps = ns_steps;
+  sa.partials = static_cast<char *>(ws) + step_ws_stats_offset(n, d, NSRGS_A_F32);
+  sa.ctl = static_cast<DevCtl *>(ws);
+  sa.iter = iter;
+  sa.tol = tol;
+  sa.stop_flag = &sa.ctl->done;
+  char *base = static_cast<char *>(ws);
+  int32_t *bounds = reinterpret_cast<int32_t *>(base + bsr_slice_table_off(n, d));
+  float *part = reinterpret_cast<float *>(base + bsr_slice_part_off(n, d));
+  const hipError_t e = A.fmt == NSRGS_A_F32 ? bsr_slice_launch<float>(d, A, sa, bounds, part, false, s)
+                                            : bsr_slice_launch<uint16_t>(d, A, sa, bounds, part, false, s);
+  NSRGS_HIP(e, "block-sparse step launch");
+  return NSRGS_OK;
+}
+
 namespace {
 
 int bsr_common(int n, int d, double p) {
@@ -757,8 +901,7 @@ int sync_step_bsr(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_ste
   if (!ws || ((uintptr_t)ws & 255u)) return fail(NSRGS_ERR_INVALID_ARG, "workspace must be non-NULL and 256-byte aligned");
   if (d > kBsrStepMaxD)
     return bsr_wide_step(A, n, d, mu, ns_steps, X_in, X_out, ws, ws_bytes, (hipStream_t)stream);
-  const bool sliced = d <= kBsrSliceMaxD && ws_bytes >= bsr_slice_ws_bytes(n, d) &&
-                      (int64_t)n * d * d * 4 < ((int64_t)1 << 31) && env_int("NSRGS_BSR_SLICED", 1) != 0;
+  const bool sliced = bsr_sliced(n, d, ws_bytes);
   const size_t need = narrow_ws_bytes(n, d, NSRGS_A_F32);
   if (ws_bytes < need) return fail(NSRGS_ERR_OUT_OF_MEMORY, "workspace too small: %zu < %zu bytes", ws_bytes, need);
   StreamArgs sa{};
@@ -778,8 +921,8 @@ int sync_step_bsr(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_ste
     char *base = static_cast<char *>(ws);
     int32_t *bounds = reinterpret_cast<int32_t *>(base + bsr_slice_table_off(n, d));
     float *part = reinterpret_cast<float *>(base + bsr_slice_part_off(n, d));
-    e = A->fmt == NSRGS_A_F32 ? bsr_slice_launch<float>(d, *A, sa, bounds, part, s)
-                              : bsr_slice_launch<uint16_t>(d, *A, sa, bounds, part, s);
+    e = A->fmt == NSRGS_A_F32 ? bsr_slice_launch<float>(d, *A, sa, bounds, part, true, s)
+                              : bsr_slice_launch<uint16_t>(d, *A, sa, bounds, part, true, s);
   } else {
     e = A->fmt == NSRGS_A_F32 ? bsr_launch<float>(d, *A, sa, s) : bsr_launch<uint16_t>(d, *A, sa, s);
   }
@@ -789,10 +932,8 @@ int sync_step_bsr(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_ste
 
 size_t sync_step_bsr_workspace_bytes(int n, int d) {
   if (n < 2 || d < 1 || d > kBsrMaxD || (int64_t)n * d * d >= (int64_t)1 << 31) return 0;
-  const size_t full = sync_workspace_bytes(n, d, NSRGS_A_F32);
-  if (d > kBsrSliceMaxD) return full;
-  const size_t sl = bsr_slice_ws_bytes(n, d);
-  return sl > full ? sl : full;
+  if (d > kBsrSliceMaxD || (int64_t)n * d * d * 4 >= ((int64_t)1 << 31)) return sync_workspace_bytes(n, d, NSRGS_A_F32);
+  return bsr_slice_ws_bytes(n, d);
 }
 
 }  // extern "C"

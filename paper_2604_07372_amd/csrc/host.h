@@ -92,6 +92,18 @@ int sym_init_product(const nsrgs_matrix *A, int n, int d, const void *Y, void *W
 // (runtime.hip) one step through that epilogue for d up to 32.
 hipError_t launch_bsr_wide_product(const nsrgs_bsr_matrix &A, int n, int d, const float *X, float *P,
                                    double *sumsq, const int *stop_flag, hipStream_t s);
+// The sliced block-sparse product (d <= 6) for solves: usable when ws holds
+// sync_step_bsr_workspace_bytes; the bounds table is written once per matrix
+// and then serves every product on it.
+bool bsr_sliced(int n, int d, size_t ws_bytes);
+hipError_t launch_bsr_slice_bounds(const nsrgs_bsr_matrix &A, int n, int d, void *ws, hipStream_t s);
+hipError_t launch_bsr_slice_wide_product(const nsrgs_bsr_matrix &A, int n, int d, const float *X, float *P,
+                                         void *ws, const int *stop_flag, hipStream_t s);
+// One iteration of a solve on the sliced step (NS-RGS, relative-change rule):
+// product on the bounds found before, the per-block epilogue of sync_step_bsr,
+// the monitor finish with the stop rule (control block at ws).
+int bsr_sliced_iterate(const nsrgs_bsr_matrix &A, int n, int d, double mu, int ns_steps, const void *X_in,
+                       void *X_out, void *ws, hipStream_t s, int iter, double tol);
 int bsr_wide_step(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_steps, const void *X_in,
                   void *X_out, void *ws, size_t ws_bytes, hipStream_t s);
 

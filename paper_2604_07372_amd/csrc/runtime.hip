@@ -813,7 +813,7 @@ static double *bsr_sumsq(int n, int d, void *ws) {
 
 static int bsr_step_launch(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_steps, int method,
                            const void *X_in, void *X_out, void *ws, hipStream_t s, int iter, double tol,
-                           int stop_rule, bool objective, bool check_done) {
+                           int stop_rule, bool objective, bool check_done, bool sliced) {
   WideArgs a = bsr_wide_args(n, d, ws);
   a.X_in = X_in;
   a.X_out = X_out;
@@ -828,8 +828,14 @@ static int bsr_step_launch(const nsrgs_bsr_matrix *A, int n, int d, double mu, i
   a.sumsq = (objective && iter == 0) ? bsr_sumsq(n, d, ws) : nullptr;
   a.stop_flag = check_done ? &a.ctl->done : nullptr;
   if (objective) NSRGS_HIP(launch_wide_gram(NSRGS_A_F32, a, s), "gram launch");
-  NSRGS_HIP(launch_bsr_wide_product(*A, n, d, static_cast<const float *>(X_in), static_cast<float *>(a.part),
-                                    a.sumsq, a.stop_flag, s), "block-sparse product launch");
+  // the sliced product does not form the sum of squares the objective's
+  // constant needs on the first iteration
+  if (sliced && !a.sumsq)
+    NSRGS_HIP(launch_bsr_slice_wide_product(*A, n, d, static_cast<const float *>(X_in), static_cast<float *>(a.part),
+                                            ws, a.stop_flag, s), "block-sparse product launch");
+  else
+    NSRGS_HIP(launch_bsr_wide_product(*A, n, d, static_cast<const float *>(X_in), static_cast<float *>(a.part),
+                                      a.sumsq, a.stop_flag, s), "block-sparse product launch");
   NSRGS_HIP(launch_wide_post(NSRGS_A_F32, a, s), "epilogue launch");
   return NSRGS_OK;
 }
@@ -843,7 +849,7 @@ int bsr_wide_step(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_ste
   if (ws_bytes < need)
     return fail(NSRGS_ERR_OUT_OF_MEMORY, "workspace too small for d = %d: %zu < %zu bytes (sync_workspace_bytes)",
                 d, ws_bytes, need);
-  return bsr_step_launch(A, n, d, mu, ns_steps, WIDE_NS, X_in, X_out, ws, s, 0, 0.0, 0, false, false);
+  return bsr_step_launch(A, n, d, mu, ns_steps, WIDE_NS, X_in, X_out, ws, s, 0, 0.0, 0, false, false, false);
 }
 }  // namespace nsrgs
 
@@ -880,12 +886,19 @@ int sync_solve_bsr(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_st
   const WsLayout L = layout(n, d, NSRGS_A_F32);
   void *buf[2] = {X, static_cast<char *>(ws) + L.xalt};
   DevCtl host{};
+  // d <= 6 with the larger workspace: every product runs sliced, on one
+  // bounds table for the whole call (A does not change during it)
+  const bool sliced = bsr_sliced(n, d, ws_bytes);
+  if (sliced) NSRGS_HIP(launch_bsr_slice_bounds(*A, n, d, ws, s), "block-sparse bounds launch");
   if (o.init) {
     const int ist = wide_init_loop(NSRGS_A_F32, n, d, X, o.init_iters, o.init_tol, ws, s, &host,
                                    bsr_wide_args(n, d, ws), [&](const WideArgs &a) {
-                                     hipError_t e = launch_bsr_wide_product(*A, n, d, static_cast<const float *>(a.X_in),
-                                                                            static_cast<float *>(a.part), nullptr,
-                                                                            a.stop_flag, s);
+                                     const float *Y = static_cast<const float *>(a.X_in);
+                                     float *P = static_cast<float *>(a.part);
+                                     hipError_t e = sliced ? launch_bsr_slice_wide_product(*A, n, d, Y, P, ws,
+                                                                                          a.stop_flag, s)
+                                                           : launch_bsr_wide_product(*A, n, d, Y, P, nullptr,
+                                                                                     a.stop_flag, s);
                                      return e != hipSuccess ? e : launch_wide_init_post(NSRGS_A_F32, a, s);
                                    });
     if (ist != NSRGS_OK && ist != NSRGS_ERR_NOT_CONVERGED) {
@@ -895,13 +908,19 @@ int sync_solve_bsr(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_st
   }
   NSRGS_HIP(launch_ctl_reset(static_cast<DevCtl *>(ws), 1, s), "ctl reset");
   NSRGS_HIP(launch_wide_ctl_reset(wide_ctl(ws, n, d, NSRGS_A_F32), s), "wide ctl reset");
+  // NS-RGS with the relative-change rule on the sliced product takes the
+  // sliced step's own epilogue (16 blocks per workgroup): at small d the
+  // matrix-core epilogue's workgroup per block costs more than the product
+  const bool narrow = sliced && o.method == NSRGS_METHOD_NS_RGS && !objective;
   int t = 0;
   while (t < max_iters) {
     const int tend = std::min(max_iters, t + o.check_every);
-    for (; t < tend; ++t)
-      if ((st = bsr_step_launch(A, n, d, mu, ns_steps, o.method, buf[t & 1], buf[(t + 1) & 1], ws, s, t, tol,
-                                o.stop_rule, objective, true)))
-        return st;
+    for (; t < tend; ++t) {
+      st = narrow ? bsr_sliced_iterate(*A, n, d, mu, ns_steps, buf[t & 1], buf[(t + 1) & 1], ws, s, t, tol)
+                  : bsr_step_launch(A, n, d, mu, ns_steps, o.method, buf[t & 1], buf[(t + 1) & 1], ws, s, t, tol,
+                                    o.stop_rule, objective, true, sliced);
+      if (st) return st;
+    }
     if ((st = read_ctl(ws, &host, s))) return st;
     if (host.done) break;
   }
@@ -917,7 +936,7 @@ int sync_solve_bsr(const nsrgs_bsr_matrix *A, int n, int d, double mu, int ns_st
     fill_info(host, d, info, result);
     info->iters = done_iters;
     info->init_residual = host.init_res;
-    if ((st = read_wide_info(ws, n, d, NSRGS_A_F32, info, s))) return st;
+    if (!narrow && (st = read_wide_info(ws, n, d, NSRGS_A_F32, info, s))) return st;
   }
   return result;
 }

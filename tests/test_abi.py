@@ -195,6 +195,25 @@ def test_block_sparse_entry_points_reject_on_the_host():
     assert L.nsrgs_bsr_fill(16, 100, 3, float("inf"), 0.5, 0, ctypes.byref(b), None) == 1
 
 
+@pytest.mark.parametrize("n,d", [(2, 1), (100, 3), (20000, 3), (7000, 4), (513, 6), (100, 7), (40, 25)])
+def test_block_sparse_workspace_holds_the_slice_region(n, d):
+    """sync_step_bsr_workspace_bytes: the whole sync_workspace_bytes region, and
+    for d <= 6 after it the sliced product's (S + 1) n int32 slice bounds and
+    S n d^2 FP32 partial sums, S = ceil(n / W) slices of W = 128 KiB / (4 ceil4(d^2))
+    block columns (X_j padded to whole float4s in LDS), each part 256-byte aligned."""
+    L = P.lib()
+    full = L.sync_workspace_bytes(n, d, P.F32)
+    got = L.sync_step_bsr_workspace_bytes(n, d)
+    if d > 6:
+        assert got == full
+        return
+    a256 = lambda v: (v + 255) // 256 * 256
+    W = 131072 // (4 * ((d * d + 3) // 4 * 4))
+    S = (n + W - 1) // W
+    assert full % 256 == 0
+    assert got == full + a256((S + 1) * n * 4) + a256(S * n * d * d * 4)
+
+
 def test_wide_block_sizes_need_f64_or_f32():
     """16 < d <= 32 runs on the matrix-core path, F64 and F32 storage only; the
     exact-polar and GPM steps likewise (checked before any device work)."""

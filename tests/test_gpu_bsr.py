@@ -293,3 +293,154 @@ def test_table1_masked_rows_on_block_sparse_storage(golden_dir, p):
         assert abs(got / want[(p, sigma)] - 1.0) <= 0.02
         del B, ws
     torch.cuda.empty_cache()
+
+
+def _bsr_from_rows(A, rows, n, d):
+    """Block-sparse FP32 device arrays holding the blocks of A at the given
+    (ascending) block columns of each block row, in the grouped value layout."""
+    rp = np.zeros(n + 1, dtype=np.int64)
+    for i, cols in enumerate(rows):
+        rp[i + 1] = rp[i] + len(cols)
+    ci = np.concatenate([np.asarray(c, dtype=np.int32) for c in rows] + [np.zeros(0, dtype=np.int32)])
+    vals = np.zeros(max(1, int(rp[-1])) * d * d, dtype=np.float32)
+    for i, cols in enumerate(rows):
+        m = len(cols)
+        for k, j in enumerate(cols):
+            blk = A[i * d:(i + 1) * d, j * d:(j + 1) * d]
+            for e in range(d * d):
+                vals[rp[i] * d * d + _entry_off(k, e, m, d * d)] = blk.flat[e]
+    return P.BsrMatrix(P.F32, torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(), torch.from_numpy(vals).cuda(),
+                       n, d, int(rp[-1]))
+
+
+@pytest.mark.parametrize("slice_w", [0, 7, 50])
+def test_bsr_sliced_step_on_uneven_rows(slice_w, monkeypatch):
+    """Rows whose stored blocks crowd the first or the last tenth of the
+    columns, rows of one block, empty rows and nearly full rows: the slice
+    bounds (a guess from an even spread of the row's blocks, a gallop away from
+    it, a bisection) cut every row where a search of the whole row would, so
+    the sliced step is the oracle's step on the dense masked matrix."""
+    require_gpu()
+    monkeypatch.setenv("NSRGS_BSR_SLICED", "1")
+    if slice_w:
+        monkeypatch.setenv("NSRGS_BSR_SLICE_W", str(slice_w))
+    n, d = 400, 3
+    rng = np.random.default_rng(77 + slice_w)
+    rows = []
+    for i in range(n):
+        kind = i % 5
+        if kind == 0:
+            cols = rng.choice(n // 10, size=int(rng.integers(1, n // 10)), replace=False)
+        elif kind == 1:
+            cols = n - 1 - rng.choice(n // 10, size=int(rng.integers(1, n // 10)), replace=False)
+        elif kind == 2:
+            cols = [int(rng.integers(n))]
+        elif kind == 3:
+            cols = []
+        else:
+            cols = np.nonzero(rng.random(n) < 0.9)[0]
+        rows.append(sorted(set(int(c) for c in cols) - {i}))
+    Z = synth.haar_blocks(n, d, 78)
+    A64 = synth.measurement_matrix(Z, synth.sigma_for(0.3, n, d), 79)
+    mask = np.zeros((n, n), dtype=bool)
+    for i, cols in enumerate(rows):
+        mask[i, cols] = True
+    A = np.where(np.kron(mask, np.ones((d, d), dtype=bool)), A64, 0.0)
+    B = _bsr_from_rows(A, rows, n, d)
+    Xin = to_dev(_orthogonal_start(Z, 0.05, 80), torch.float32)
+    Xout = torch.empty_like(Xin)
+    ws = P.workspace(n, d, P.F32, bsr=True)
+    P.step_bsr(B, n, d, Xin, Xout, ws, mu=1.0 / n)
+    torch.cuda.synchronize()
+    As = oracle_matrix(A, P.F32)
+    ref = O.rgs_step(As, host(Xin), d, mu=1.0 / n, Ts=3)
+    err = np.abs(host(Xout) - ref.X).max()
+    tol = step_tolerance(As, host(Xin), n, P.F32)
+    print(f"uneven rows slice_w={slice_w}: err {err:.2e} tol {tol:.2e}", flush=True)
+    assert err <= tol
+
+
+@pytest.mark.parametrize("method", ["ns_rgs", "polar"])
+@pytest.mark.parametrize("d", [3, 5])
+def test_bsr_solve_small_d_on_the_sliced_product(d, method, monkeypatch):
+    """sync_solve_bsr for d <= 6 with the larger workspace runs every product on
+    the sliced kernel: 25 iterations from the oracle's spectral start against
+    the oracle on the dense masked matrix, and against the same solve on the
+    chunked product (equal up to the order of additions)."""
+    require_gpu()
+    n, p = 300, 0.5
+    print(f"bsr solve sliced d={d} {method}", flush=True)
+    Z, sigma, A64 = _masked(n, d, 0.2, 600 + d, p)
+    B = P.generate_bsr(torch.from_numpy(Z).cuda(), sigma, 601 + d, p, fmt=P.F32)
+    As = oracle_matrix(A64, P.F32)
+    X0 = host(to_dev(O.spectral_init(As, d), torch.float32))
+    mu = 1.0 / (n * p)
+    out = {}
+    for path in ("sliced", "chunked"):
+        monkeypatch.setenv("NSRGS_BSR_SLICED", "1" if path == "sliced" else "0")
+        X = to_dev(X0, torch.float32)
+        info = P.solve_bsr(B, n, d, X, P.workspace(n, d, P.F32, bsr=True), mu=mu, ns_steps=3, max_iters=25,
+                           init=False, method=method)
+        assert info["iters"] == 25 and info["status"] == 0
+        out[path] = host(X)
+    ref = O.solve(As, d, mu=mu, Ts=3, T=25, X0=X0, retraction="polar" if method == "polar" else "ns")
+    e_g, e_o = O.alignment_error(out["sliced"], Z), O.alignment_error(ref.X, Z)
+    dist = O.dist_F(out["sliced"], ref.X) / math.sqrt(n)
+    print(f"  e {e_g:.8f} vs {e_o:.8f} d_F/sqrt(n) {dist:.2e}", flush=True)
+    assert abs(e_g - e_o) <= 1e-4 * e_o
+    assert dist <= 1e-4 * e_o
+    assert O.dist_F(out["sliced"], out["chunked"]) / math.sqrt(n) <= 1e-5
+
+
+@pytest.mark.parametrize("d", [3, 6])
+def test_bsr_spectral_init_small_d_on_the_sliced_product(d, monkeypatch):
+    """The initialization's products on the sliced kernel: the top-d subspace
+    of A without its diagonal blocks, as eigh finds it."""
+    require_gpu()
+    monkeypatch.setenv("NSRGS_BSR_SLICED", "1")
+    n, p = 400, 0.8
+    Z, sigma, A64 = _masked(n, d, 0.1, 700 + d, p)
+    B = P.generate_bsr(torch.from_numpy(Z).cuda(), sigma, 701 + d, p, fmt=P.F32)
+    As = oracle_matrix(A64, P.F32)
+    blk = np.arange(n * d) // d
+    X0_ref = O.spectral_init(np.where(blk[:, None] == blk[None, :], 0.0, As), d)
+    X = torch.empty((n * d, d), dtype=torch.float32, device="cuda")
+    info = P.solve_bsr(B, n, d, X, P.workspace(n, d, P.F32, bsr=True), mu=1.0 / (n * p), max_iters=0, init=True,
+                       init_iters=200)
+    dist = O.dist_F(host(X), X0_ref) / math.sqrt(n)
+    print(f"bsr init sliced d={d}: residual {info['init_residual']:.2e} d_F/sqrt(n) {dist:.2e}", flush=True)
+    assert dist <= 1e-4
+
+
+def test_bsr_sliced_solve_is_the_sliced_step_repeated(monkeypatch):
+    """With the larger workspace, NS-RGS iterations of sync_solve_bsr (d <= 6,
+    relative-change rule) are sync_step_bsr's sliced steps on bounds found once:
+    bitwise the same iterates, and the stop rule fires at the step whose
+    relative change first reaches the tolerance."""
+    require_gpu()
+    monkeypatch.setenv("NSRGS_BSR_SLICED", "1")
+    n, d, p = 500, 3, 0.5
+    Z, sigma, A64 = _masked(n, d, 0.2, 909, p)
+    B = P.generate_bsr(torch.from_numpy(Z).cuda(), sigma, 910, p, fmt=P.F32)
+    X0 = to_dev(_orthogonal_start(Z, 0.05, 911), torch.float32)
+    mu = 1.0 / (n * p)
+    X = X0.clone()
+    info = P.solve_bsr(B, n, d, X, P.workspace(n, d, P.F32, bsr=True), mu=mu, max_iters=12, init=False)
+    assert info["iters"] == 12 and info["status"] == 0
+    ws = P.workspace(n, d, P.F32, bsr=True)
+    Xa, Xb = X0.clone(), torch.empty_like(X0)
+    rel = []
+    for _ in range(60):
+        P.step_bsr(B, n, d, Xa, Xb, ws, mu=mu)
+        Xa, Xb = Xb, Xa
+        rel.append(P.read_info(ws)["rel_change"])
+        if len(rel) == 12:
+            assert torch.equal(X, Xa)
+    tol = 1e-5
+    want = next(k + 1 for k, r in enumerate(rel) if r <= tol)
+    X = X0.clone()
+    info = P.solve_bsr(B, n, d, X, P.workspace(n, d, P.F32, bsr=True), mu=mu, max_iters=60, tol=tol, init=False,
+                       check_every=4)
+    print(f"sliced solve stop: iters {info['iters']} (stepping: {want}), rel {info['rel_change']:.2e}", flush=True)
+    assert info["converged"] == 1 and info["iters"] == want
+    assert info["rel_change"] == rel[want - 1]
