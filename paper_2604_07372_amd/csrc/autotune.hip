@@ -48,6 +48,7 @@ int nsrgs_autotune_step(const nsrgs_matrix *A, int n, int d, const void *X_in, v
   st = NSRGS_OK;
   for (int i = 0; i < nv && st == NSRGS_OK; ++i) {
     for (int W : kTuneWaves) {
+      if (v[i].unroll == 0 && W > kPipeMaxWaves) continue;   // launched with kPipeMaxWaves
       const StreamConfig cfg{v[i].blocks_per_panel, W, v[i].unroll};
       // one untimed launch, then reps timed launches on the stream
       if ((st = step_with_config(A, n, d, 0.0, 3, X_in, X_out, ws, s, cfg))) break;

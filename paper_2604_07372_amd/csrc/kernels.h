@@ -31,6 +31,12 @@ struct StreamArgs {
   const int *stop_flag;   // non-NULL: return at once when *stop_flag != 0
 };
 
+// Waves per workgroup of the software-pipelined (U = 0) step shapes: two
+// register buffers of a column group need more than the 256 VGPRs of two
+// waves per SIMD, so these are built for one wave per SIMD (512 VGPRs) and
+// each wave hides its own load latency; launches cap W at this.
+constexpr int kPipeMaxWaves = 4;
+
 struct StreamConfig {
   int blocks_per_panel;   // B: rows per panel R = B d
   int waves;              // W: waves per workgroup splitting the columns

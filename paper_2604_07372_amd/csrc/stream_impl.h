@@ -409,37 +409,42 @@ __device__ __forceinline__ void panel_compute(const PanelJob &job, char *lds) {
   if constexpr (U == 0) {
     // Software pipeline over this wave's full groups (diagonal groups skipped):
     // the loads of the next group are in flight while the current one is
-    // accumulated.  g, gn are wave-uniform, so the branches are scalar.
+    // accumulated.  g, gn are wave-uniform, so the branches are scalar.  The
+    // skip is two selects, not a loop: gd1 <= gd0 + 1, so at most two steps
+    // land on diagonal groups, and a loop nested in the pipelined one makes
+    // the compiler drain every load in flight (the prefetch too) on entry.
     auto skip_diag = [&](int g) {
-      while (g < nfull && (g == gd0 || g == gd1)) g += nw;
-      return g;
+      g = (g == gd0 || g == gd1) ? g + nw : g;
+      return (g == gd0 || g == gd1) ? g + nw : g;
     };
     // Two register buffers take turns (unrolled by two, so no copy hands one
-    // over to the other); in the loop the prefetch is unconditional, so the
-    // arithmetic waits only for the previous round's loads, never for the
-    // one just issued.  The exits accumulate the last group.
-    int g = skip_diag(wave);
+    // over to the other).  The loop runs while two more groups remain, so
+    // every load it issues is consumed on every path (by its own second half,
+    // or by the next round or the tail): a prefetch that some path leaves
+    // unused gets sunk past the branch by the compiler, behind the arithmetic
+    // it was meant to overlap.
     constexpr int NQ = x_quads<FMT, D>();
+    int g = skip_diag(wave);
     if (g < nfull) {
       uint4 b0[R], b0lo[R], x0[NQ], b1[R], b1lo[R], x1[NQ];
       load_group<FMT, D, R, NQ>(b0, b0lo, x0, Ab, Alo, rowoff, X, g * GROUP + lane * V);
-      for (;;) {
-        int gn = skip_diag(g + nw);
-        if (gn >= nfull) {
-          fma_group<FMT, D, R, NQ>(acc, b0, b0lo, x0);
-          break;
-        }
-        load_group<FMT, D, R, NQ>(b1, b1lo, x1, Ab, Alo, rowoff, X, gn * GROUP + lane * V);
+      int ga = skip_diag(g + nw);
+      int gb = skip_diag(ga + nw);
+      while (gb < nfull) {                 // b0 holds g; ga < gb are the next two
+        load_group<FMT, D, R, NQ>(b1, b1lo, x1, Ab, Alo, rowoff, X, ga * GROUP + lane * V);
         fma_group<FMT, D, R, NQ>(acc, b0, b0lo, x0);
-        g = gn;
-        gn = skip_diag(g + nw);
-        if (gn >= nfull) {
-          fma_group<FMT, D, R, NQ>(acc, b1, b1lo, x1);
-          break;
-        }
-        load_group<FMT, D, R, NQ>(b0, b0lo, x0, Ab, Alo, rowoff, X, gn * GROUP + lane * V);
+        load_group<FMT, D, R, NQ>(b0, b0lo, x0, Ab, Alo, rowoff, X, gb * GROUP + lane * V);
         fma_group<FMT, D, R, NQ>(acc, b1, b1lo, x1);
-        g = gn;
+        g = gb;
+        ga = skip_diag(g + nw);
+        gb = skip_diag(ga + nw);
+      }
+      if (ga < nfull) {                    // one more group
+        load_group<FMT, D, R, NQ>(b1, b1lo, x1, Ab, Alo, rowoff, X, ga * GROUP + lane * V);
+        fma_group<FMT, D, R, NQ>(acc, b0, b0lo, x0);
+        fma_group<FMT, D, R, NQ>(acc, b1, b1lo, x1);
+      } else {
+        fma_group<FMT, D, R, NQ>(acc, b0, b0lo, x0);
       }
     }
   } else {
@@ -595,7 +600,7 @@ __device__ inline void finish_gram(const StreamArgs &args) {
 }
 
 template <int FMT, int D, int B, int U, int MODE>
-__global__ void __launch_bounds__(kWave * kMaxWaves)
+__global__ void __launch_bounds__(kWave * (U == 0 ? kPipeMaxWaves : kMaxWaves))
 stream_kernel(StreamArgs args) {
   using T = typename Fmt<FMT>::acc_t;
   __shared__ __attribute__((aligned(16))) char lds[panel_lds_bytes<FMT, D, B>()];
@@ -661,7 +666,9 @@ __global__ void __launch_bounds__(256) stream_finish_kernel(StreamArgs args) {
 template <int MODE, int FMT, int D, int B, int U>
 hipError_t launch_one(const StreamConfig &cfg, const StreamArgs &args, hipStream_t s) {
   using T = typename Fmt<FMT>::acc_t;
-  const dim3 grid(args.num_panels), block(kWave * cfg.waves);
+  // the pipelined shapes take at most kPipeMaxWaves waves per workgroup
+  const int waves = U == 0 && cfg.waves > kPipeMaxWaves ? kPipeMaxWaves : cfg.waves;
+  const dim3 grid(args.num_panels), block(kWave * waves);
   hipLaunchKernelGGL((stream_kernel<FMT, D, B, U, MODE>), grid, block, 0, s, args);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
