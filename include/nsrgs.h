@@ -561,7 +561,8 @@ int nsrgs_server_destroy(nsrgs_server *server);
  * (blocks_per_panel B: the workgroup's panel is B d rows; unroll U: 0 = one
  * 16-byte column vector per row per loop iteration with the next iteration's
  * loads issued before this one's arithmetic, U >= 1 = U vectors per row
- * loaded together; waves W splitting the columns) for storage format fmt,
+ * loaded together; waves W splitting the columns, at most 4 with U = 0) for
+ * storage format fmt,
  * block size d and n*d in [nd_min, nd_max]; an entry whose (B, U) is not
  * compiled for d is ignored.  kind 1: waves per workgroup of the
  * grouped batched launch for format fmt and batches whose largest d is <= d.
@@ -589,7 +590,9 @@ int nsrgs_step_variants(int d, int32_t *blocks_per_panel, int32_t *unroll, int m
  * options).  Both wait for the stream.
  *
  * nsrgs_autotune_step: every compiled (blocks_per_panel, unroll) shape of d
- *   and waves in {1, 2, 4, 8}; reps timed sync_step launches each (HIP events,
+ *   and waves in {1, 2, 4, 8} (at most 4 for unroll = 0, the software-pipelined
+ *   shapes, which launch with at most 4 waves per workgroup whatever the
+ *   table or NSRGS_STEP_W asks); reps timed sync_step launches each (HIP events,
  *   after one untimed launch), T_s = 3, mu = 1/n.  X_out is overwritten.
  * nsrgs_autotune_batched: the grouped and persistent schedules, unit orders 0
  *   and 1, waves in {1, 2, 4}, persistent tickets of 128 / 512 / 2048 KiB;

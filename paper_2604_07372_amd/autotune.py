@@ -27,7 +27,8 @@ def _results(arr, n):
 def tune_step(A, n: int, d: int, X: torch.Tensor, ws: Workspace | None = None, reps: int = 5,
               install: bool = True, nd_range: tuple[int, int] | None = None) -> list:
     """Time every compiled (blocks_per_panel, unroll) shape and waves in
-    {1, 2, 4, 8} for sync_step on this problem; fastest first.  With install,
+    {1, 2, 4, 8} (at most 4 for the software-pipelined unroll = 0 shapes) for
+    sync_step on this problem; fastest first.  With install,
     the fastest becomes the table entry for (format, d) over nd_range
     (default: half to twice this n*d)."""
     ws = ws if ws is not None else workspace(n, d, A.fmt)
