@@ -252,6 +252,54 @@ def test_spectral_init_fp64_matches_eigh():
     assert np.allclose(info["ritz"][:d], w, rtol=1e-12)
 
 
+@pytest.mark.parametrize("c,seed", [(0.5, 11), (0.8, 13)])
+def test_spectral_init_near_the_dominance_edge(c, seed):
+    """Subspace iteration on d columns finds the dominant (largest |lambda|)
+    subspace.  For sigma = c sqrt(n/d) the bottom of the noise spectrum, about
+    -2 c n, approaches the top-d eigenvalues, about (1 + c^2) n: at c = 0.8
+    (this seed) lambda_d = 160.4 against |lambda_min| = 156.1, a convergence
+    ratio of 0.974 per iteration.  The precondition still holds, and the
+    initialization still finds eigh's top-d algebraic subspace and Ritz values."""
+    require_gpu()
+    n, d = 100, 3
+    Z = synth.haar_blocks(n, d, seed)
+    A = synth.measurement_matrix(Z, synth.sigma_for(c, n, d), seed + 1)
+    evals = np.linalg.eigvalsh(A)
+    Y, w, _ = O.spectral_subspace(A, d)
+    assert w[-1] > abs(evals[0])                        # lambda_d > |lambda_min|
+    X0 = torch.empty((n * d, d), dtype=torch.float64, device="cuda")
+    info = P.init_spectral(device_matrix(A, P.F64), n, d, X0, P.workspace(n, d, P.F64), max_iters=3000, tol=1e-12)
+    print(f"c={c}: init iterations {info['iters']}, ritz {info['ritz'][:d]}", flush=True)
+    assert info["converged"] == 1
+    assert O.dist_F(host(X0), O.sgn_blocks(Y, d)) / math.sqrt(n) <= 1e-8
+    assert np.allclose(info["ritz"][:d], w, rtol=1e-10)
+
+
+def test_spectral_init_beyond_the_dominance_precondition_shows_in_the_ritz_values():
+    """A planted eigenvalue below -lambda_1 breaks the precondition: the
+    iteration then converges to the d largest-magnitude eigenvalues, and the
+    reported Ritz values show it (one is negative, not among the top d), so a
+    caller can tell."""
+    require_gpu()
+    n, d = 100, 3
+    Z = synth.haar_blocks(n, d, 14)
+    A = synth.measurement_matrix(Z, synth.sigma_for(0.3, n, d), 15)
+    u = np.random.default_rng(16).standard_normal(n * d)
+    u /= np.linalg.norm(u)
+    A2 = A - 2.0 * np.linalg.eigvalsh(A)[-1] * np.outer(u, u)
+    evals = np.linalg.eigvalsh(A2)
+    by_mag = evals[np.argsort(-np.abs(evals))][:d]
+    assert by_mag.min() < 0 and abs(by_mag.min()) > evals[-1]
+    X0 = torch.empty((n * d, d), dtype=torch.float64, device="cuda")
+    info = P.init_spectral(device_matrix(A2, P.F64), n, d, X0, P.workspace(n, d, P.F64), max_iters=3000, tol=1e-11)
+    ritz = np.array(info["ritz"][:d])
+    print(f"beyond the precondition: iterations {info['iters']}, ritz {ritz}, top-d {np.sort(evals)[::-1][:d]}",
+          flush=True)
+    assert info["converged"] == 1
+    assert ritz.min() < 0
+    assert np.allclose(np.sort(ritz)[::-1], np.sort(by_mag)[::-1], rtol=1e-8)
+
+
 @pytest.mark.parametrize("sigma_c", [None, 0.1, 0.3])
 def test_solve_fp32_mid_workload(sigma_c):
     """n = 2000, d = 3, sigma in {0.5, 0.1 sqrt(n/d), 0.3 sqrt(n/d)}, 200 iterations:
