@@ -193,6 +193,16 @@ def batched_bench(iters: int = 100, base_iters: int = 10, count: int = 512, seed
            "speedup_vs_per_problem_launches": t_base / t_group,
            "status": st, "all_iters_done": all(i["iters"] == iters for i in infos)}
     res["speedup_tuned_vs_per_problem_launches"] = t_base / t_tuned
+    # every schedule the autotuner timed (3 iterations each, wall time per
+    # iteration): how the persistent launch's time moves with its ticket size
+    res["tuning_candidates"] = [
+        {"persistent": bool(r["persistent"]), "order": int(r["order"]), "waves": int(r["waves"]),
+         "ticket_kb": int(r["ticket_kb"]), "ms_per_iter": float(r["ms"]),
+         "GBps": a_bytes / (float(r["ms"]) * 1e-3) / 1e9} for r in ranking]
+    for c in res["tuning_candidates"]:
+        print(f"[bench] batched candidate: persistent={c['persistent']} order={c['order']} waves={c['waves']} "
+              f"ticket={c['ticket_kb']} KiB: {c['ms_per_iter']:.2f} ms/iter ({c['GBps']:.0f} GB/s)",
+              file=sys.stderr, flush=True)
     print(f"[bench] batched: tuned {best} {t_tuned:.3f} s ({res['tuned_GBps']:.0f} GB/s)",
           file=sys.stderr, flush=True)
     print(f"[bench] batched: persistent {t_pers:.3f} s ({res['persistent_GBps']:.0f} GB/s), "
