@@ -360,19 +360,21 @@ def test_bsr_sliced_step_on_uneven_rows(slice_w, monkeypatch):
     assert err <= tol
 
 
+@pytest.mark.parametrize("fmt", [P.F32, P.BF16], ids=lambda f: FMT_NAME[f])
 @pytest.mark.parametrize("method", ["ns_rgs", "polar"])
 @pytest.mark.parametrize("d", [3, 5])
-def test_bsr_solve_small_d_on_the_sliced_product(d, method, monkeypatch):
+def test_bsr_solve_small_d_on_the_sliced_product(d, method, fmt, monkeypatch):
     """sync_solve_bsr for d <= 6 with the larger workspace runs every product on
     the sliced kernel: 25 iterations from the oracle's spectral start against
-    the oracle on the dense masked matrix, and against the same solve on the
-    chunked product (equal up to the order of additions)."""
+    the oracle on the dense masked matrix of the stored values (FP32 or BF16),
+    and against the same solve on the chunked product (equal up to the order of
+    additions)."""
     require_gpu()
     n, p = 300, 0.5
-    print(f"bsr solve sliced d={d} {method}", flush=True)
+    print(f"bsr solve sliced d={d} {method} {FMT_NAME[fmt]}", flush=True)
     Z, sigma, A64 = _masked(n, d, 0.2, 600 + d, p)
-    B = P.generate_bsr(torch.from_numpy(Z).cuda(), sigma, 601 + d, p, fmt=P.F32)
-    As = oracle_matrix(A64, P.F32)
+    B = P.generate_bsr(torch.from_numpy(Z).cuda(), sigma, 601 + d, p, fmt=fmt)
+    As = oracle_matrix(A64, fmt)
     X0 = host(to_dev(O.spectral_init(As, d), torch.float32))
     mu = 1.0 / (n * p)
     out = {}
