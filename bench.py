@@ -273,6 +273,47 @@ def masked_bench(Zd, sigma, dense_ms: float, steps: int, warmup: int, p: float =
     return out
 
 
+def stiefel_bench(Zd, sigma, dense_ms: float, steps: int, warmup: int, ps=(3, 5)):
+    """NS-RGS on the Stiefel manifold St(p, d)^n (the Sec. 6 extension, the
+    Burer-Monteiro relaxation of Sec. 1) at the headline n, d on its FP32 A:
+    sync_step_stiefel per step from a random Stiefel start, mu = 1/n, for
+    p = d (the orthogonal iterate on the Stiefel path) and p = 5."""
+    import torch
+    import paper_2604_07372_amd as P
+    import synth
+    nd, d = Zd.shape
+    n = nd // d
+    A = P.stored(P.generate(Zd, sigma, SEED, fmt=P.F32), P.F32)
+    out = {}
+    for p in ps:
+        S0 = torch.from_numpy(synth.stiefel_start(n, d, p, SEED + 2)).to(Zd.device, torch.float32)
+        ws = P.stiefel_workspace(n, d, p, P.F32)
+        Sa, Sb = S0.clone(), torch.empty_like(S0)
+        for _ in range(warmup):
+            P.step_stiefel(A, n, d, p, Sa, Sb, ws)
+            Sa, Sb = Sb, Sa
+        torch.cuda.synchronize()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(steps):
+            P.step_stiefel(A, n, d, p, Sa, Sb, ws)
+            Sa, Sb = Sb, Sa
+        end.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end) / steps
+        alg = nd * nd * 4 + 2 * nd * p * 4
+        info = P.read_info(ws)
+        out[f"p={p}"] = {"p": p, "ms_per_step": ms, "iters_per_s": 1e3 / ms, "alg_bytes": alg,
+                         "alg_GBps": alg / (ms * 1e-3) / 1e9, "time_vs_dense_sync_step": ms / dense_ms,
+                         "nonfinite": info["nonfinite"], "max_orth_defect": info["max_orth_defect"]}
+        print(f"[bench] stiefel p={p}: {ms:.4f} ms/iter, {out[f'p={p}']['alg_GBps']:.0f} GB/s, "
+              f"{ms / dense_ms:.2f}x the time of sync_step", file=sys.stderr, flush=True)
+        del ws, Sa, Sb, S0
+    del A
+    torch.cuda.empty_cache()
+    return out
+
+
 def serving_bench(window_s: float = 60.0, warmup_s: float = 10.0, rate: float = 50.0, seed0: int = 5000):
     """Poisson arrivals at `rate` requests/s for warmup_s + window_s seconds;
     each request: n log-uniform in [100, 20000], d in {3, 4}, sigma = 0.2
@@ -520,6 +561,7 @@ def main(argv=None):
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-symmetric", action="store_true")
     ap.add_argument("--no-masked", action="store_true")
+    ap.add_argument("--no-stiefel", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-table1", action="store_true")
     ap.add_argument("--no-config1", action="store_true")
@@ -754,6 +796,7 @@ def main(argv=None):
     masked = None if a.no_masked else {
         f"p={pm}": masked_bench(Zd, sigma, results["f32"]["ms_per_step"], a.steps, a.warmup, p=pm)
         for pm in (0.5, 0.2)}
+    stiefel = None if a.no_stiefel else stiefel_bench(Zd, sigma, results["f32"]["ms_per_step"], a.steps, a.warmup)
     table1 = None if a.no_table1 else table1_bench()
     config1 = None if a.no_config1 else config1_bench()
     batched = None if a.no_batched else batched_bench()
@@ -790,6 +833,7 @@ def main(argv=None):
         "speedup_vs_f32": {k: results["f32"]["ms_per_step"] / r["ms_per_step"] for k, r in results.items()},
         "symmetric_step": symmetric,
         "masked_step": masked,
+        "stiefel_step": stiefel,
         "solve": solve,
         "table1_shape": table1,
         "config_n2000": config1,
