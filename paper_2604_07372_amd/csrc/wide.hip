@@ -505,7 +505,11 @@ __global__ void __launch_bounds__(256) wide_gram_kernel(const T *__restrict__ X,
 // and the stop rules: relative change ||X^{t+1} - X^t|| / ||X^t|| <= tol, or
 // the paper's ratio R^{t-1} = (F(X^{t-1}) - F(X^t)) / F(X^t) < tol, which
 // stops with X^t (this step's input) as the result.
-__global__ void __launch_bounds__(256) wide_finish_kernel(WideArgs a) {
+// One workgroup of kWideFinishThreads (at most kMaxWaves waves: the
+// reductions' scratch); the record loop is unrolled so that several records
+// per thread are in flight (n records at 20000 blocks took 34 us one by one).
+constexpr int kWideFinishThreads = kWave * kMaxWaves;
+__global__ void __launch_bounds__(kWideFinishThreads) wide_finish_kernel(WideArgs a) {
   __shared__ double s_scr[kMaxWaves];
   __shared__ double s_scr7[7 * kMaxWaves];
   if (a.stop_flag) {
@@ -515,6 +519,7 @@ __global__ void __launch_bounds__(256) wide_finish_kernel(WideArgs a) {
   // sums in a fixed order; the non-finite and polar-failure flags are 0 / 1
   // per block, so their sums are counts
   double v[7] = {0, 0, 0, 0, 0, 0, 0}, dmax = 0;
+#pragma unroll 4
   for (int p = tid; p < a.n; p += blockDim.x) {
     const WideStat s = a.stats[p];
     v[0] += s.dx2;
@@ -848,16 +853,23 @@ __device__ inline void wmm_rect(double *out, const double *A, const double *B, i
 // One workgroup per block i: C_i from the partials (diagonal block included,
 // as the product streams whole rows), the Stiefel step in FP64, S_i^{t+1} and
 // the block's monitors (||S^{t+1} - S^t||^2, ||S^t||^2, ||I - F_i F_i^T||_F).
+// Dynamic LDS: seven d x p arrays (every d x d and d x p intermediate fits, as
+// p >= d), wide_stiefel_epi_lds(d, p) bytes; launched with one wave when
+// d p <= 64, so that small blocks do not hold a CU's LDS and threads idle.
+__host__ __device__ inline int wide_stiefel_epi_stride(int d, int p) { return (d * p + 1) & ~1; }
+inline size_t wide_stiefel_epi_lds(int d, int p) { return (size_t)7 * wide_stiefel_epi_stride(d, p) * sizeof(double); }
+inline int wide_stiefel_epi_threads(int d, int p) { return d * p <= kWave ? kWave : 256; }
+
 template <typename T>
 __global__ void __launch_bounds__(256) wide_stiefel_epilogue_kernel(WideArgs a) {
-  constexpr int NE = kWideMaxD * kWideMaxD;
-  __shared__ double sm[7][NE];
+  extern __shared__ double sm_dyn[];
   __shared__ double s_scr4[4 * kMaxWaves];
   if (a.stop_flag) {
     if (__atomic_load_n(a.stop_flag, __ATOMIC_RELAXED)) return;   // uniform
   }
   const int i = blockIdx.x, d = a.d, p = a.p, dd = d * d, dp = d * p, tid = threadIdx.x;
-  double *S = sm[0], *C = sm[1], *Ad = sm[2], *G = sm[3], *F = sm[4], *M = sm[5], *W = sm[6];
+  const int es = wide_stiefel_epi_stride(d, p);
+  double *S = sm_dyn, *C = S + es, *Ad = C + es, *G = Ad + es, *F = G + es, *M = F + es, *W = M + es;
   const T *__restrict__ Sin = static_cast<const T *>(a.X_in);
   const T *__restrict__ Pp = static_cast<const T *>(a.part);
   const T *__restrict__ A = static_cast<const T *>(a.A);
@@ -1099,7 +1111,7 @@ static hipError_t wide_post_t(const WideArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(wide_epilogue_kernel<T>, dim3(a.n), dim3(256), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(wide_finish_kernel, dim3(1), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(wide_finish_kernel, dim3(1), dim3(kWideFinishThreads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1197,9 +1209,10 @@ template <typename T>
 static hipError_t wide_stiefel_step_t(const WideArgs &a, hipStream_t s) {
   hipError_t e;
   if ((e = wide_launch_product<T>(a, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(wide_stiefel_epilogue_kernel<T>, dim3(a.n), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(wide_stiefel_epilogue_kernel<T>, dim3(a.n), dim3(wide_stiefel_epi_threads(a.d, a.p)),
+                     wide_stiefel_epi_lds(a.d, a.p), s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(wide_finish_kernel, dim3(1), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(wide_finish_kernel, dim3(1), dim3(kWideFinishThreads), 0, s, a);
   return hipGetLastError();
 }
 
