@@ -345,18 +345,25 @@ __device__ inline int wide_polar(double *S, double *M, double *N, int d, double 
 // diagonal-block term, the retraction, X_i^{t+1} and the block's record.
 // Init mode: W_i = (A Y)_i and the block's Grams Y_i^T W_i, W_i^T W_i.
 // The d x d arithmetic is FP64 for every storage format.
+// Dynamic LDS: seven d x d arrays, wide_epi_lds(d) bytes, and as many waves
+// as d^2 entries need (up to four), so that small blocks do not hold a CU's
+// LDS with a fixed 32 x 32 layout and idle threads.
 // ---------------------------------------------------------------------------
+__host__ __device__ inline int wide_epi_stride(int d) { return (d * d + 1) & ~1; }
+inline size_t wide_epi_lds(int d) { return (size_t)7 * wide_epi_stride(d) * sizeof(double); }
+inline int wide_epi_threads(int d) { return min(256, (d * d + kWave - 1) / kWave * kWave); }
+
 template <typename T>
 __global__ void __launch_bounds__(256) wide_epilogue_kernel(WideArgs a) {
-  constexpr int NE = kWideMaxD * kWideMaxD;
-  __shared__ double sm[7][NE];
+  extern __shared__ double sm_dyn[];
   __shared__ double s_scr[kMaxWaves];
   __shared__ double s_scr7[7 * kMaxWaves];
   if (a.stop_flag) {
     if (__atomic_load_n(a.stop_flag, __ATOMIC_RELAXED)) return;   // uniform
   }
   const int i = blockIdx.x, d = a.d, dd = d * d, tid = threadIdx.x;
-  double *X = sm[0], *C = sm[1], *Ad = sm[2], *G = sm[3], *Tm = sm[4], *F = sm[5], *M = sm[6];
+  const int es = wide_epi_stride(d);
+  double *X = sm_dyn, *C = X + es, *Ad = C + es, *G = Ad + es, *Tm = G + es, *F = Tm + es, *M = F + es;
   const T *__restrict__ Xin = static_cast<const T *>(a.X_in);
   const T *__restrict__ P = static_cast<const T *>(a.part);
   const T *__restrict__ A = static_cast<const T *>(a.A);
@@ -1108,7 +1115,7 @@ static hipError_t wide_gram_t(const WideArgs &a, hipStream_t s) {
 
 template <typename T>
 static hipError_t wide_post_t(const WideArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(wide_epilogue_kernel<T>, dim3(a.n), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(wide_epilogue_kernel<T>, dim3(a.n), dim3(wide_epi_threads(a.d)), wide_epi_lds(a.d), s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(wide_finish_kernel, dim3(1), dim3(kWideFinishThreads), 0, s, a);
@@ -1117,7 +1124,7 @@ static hipError_t wide_post_t(const WideArgs &a, hipStream_t s) {
 
 template <typename T>
 static hipError_t wide_init_post_t(const WideArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(wide_epilogue_kernel<T>, dim3(a.n), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(wide_epilogue_kernel<T>, dim3(a.n), dim3(wide_epi_threads(a.d)), wide_epi_lds(a.d), s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int ne = 2 * a.d * a.d;
