@@ -255,9 +255,48 @@ __global__ void __launch_bounds__(256) wide_xs_kernel(const T *__restrict__ X, i
 // d x d helpers in FP64 on LDS, for every thread of a workgroup.
 // ---------------------------------------------------------------------------
 // out = op(A) op(B), op = transpose when TA / TB; ends with a barrier.
+// out = op(A) op(B) for d x d FP64 matrices in LDS (row-major, stride d),
+// op = transpose where TA / TB.  Blocks larger than 16 with at least four
+// waves use the matrix cores: wave w < 4 owns the 16 x 16 output tile
+// (w / 2, w % 2) and runs ceil(d / 4) FP64 16 x 16 x 4 steps, entries past d
+// read as zero.  (Each entry's d products summed one by one took one LDS read
+// of each operand per product, which bounds the per-block epilogue at
+// d = 25.)  Otherwise each thread sums whole entries.  Ends with a barrier.
 template <bool TA, bool TB>
-__device__ inline void wmm(double *out, const double *A, const double *B, int d) {
+__device__ __forceinline__ void wmm(double *out, const double *A, const double *B, int d) {
+  static_assert(kWideMaxD <= 32, "2 x 2 output tiles and eight 4-wide steps cover d <= 32");
   const int dd = d * d;
+  if (d > 16 && blockDim.x >= 4 * kWave) {   // uniform
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (w < 4) {
+      const int r0 = (w >> 1) * 16, c0 = (w & 1) * 16;
+      const int i = r0 + (lane & 15), c = c0 + (lane & 15), kq = lane >> 4;
+      // every operand read is issued before the first product (clamped
+      // in-bounds addresses, zero selected past d), so the eight steps wait
+      // for LDS once
+      const int ic = i < d ? i : 0, cc = c < d ? c : 0;
+      double av[8], bv[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int k = 4 * t + kq, kc = k < d ? k : 0;
+        const double x = TA ? A[kc * d + ic] : A[ic * d + kc];
+        const double y = TB ? B[cc * d + kc] : B[kc * d + cc];
+        av[t] = (k < d && i < d) ? x : 0.0;
+        bv[t] = (k < d && c < d) ? y : 0.0;
+      }
+      WideT<double>::v4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (4 * t < d) acc = mfma4<double>(av[t], bv[t], acc);   // uniform
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + kq + 4 * r;
+        if (row < d && c < d) out[row * d + c] = acc[r];
+      }
+    }
+    __syncthreads();
+    return;
+  }
   for (int e = threadIdx.x; e < dd; e += blockDim.x) {
     const int r = e / d, k = e % d;
     double s0 = 0.0, s1 = 0.0;
@@ -310,7 +349,7 @@ __device__ inline double wdefect(const double *M, int d, double *scr) {
 // ||I - S^T S||_F <= 64 d eps, then two more (quadratic) steps.  M, N are LDS
 // scratch.  Returns the number of steps, or -1 if the matrix is singular or
 // not finite (no convergence within 200 steps).
-__device__ inline int wide_polar(double *S, double *M, double *N, int d, double *scr) {
+__device__ __forceinline__ int wide_polar(double *S, double *M, double *N, int d, double *scr) {
   const int dd = d * d;
   wmm<true, false>(M, S, S, d);
   double g = 0.0;
@@ -372,6 +411,7 @@ __global__ void __launch_bounds__(256) wide_epilogue_kernel(WideArgs a) {
     const int64_t row = (int64_t)i * d + r;
     X[e] = (double)Xin[row * d + k];
     double c = 0.0;
+#pragma unroll 4
     for (int s = 0; s < a.g.ks; ++s) c += (double)P[((size_t)s * a.g.rows_pad + row) * 32 + k];
     C[e] = c;
     Ad[e] = a.no_diag ? 0.0 : (double)A[row * a.ld + (int64_t)i * d + k];
