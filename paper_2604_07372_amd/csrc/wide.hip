@@ -285,7 +285,6 @@ __global__ void __launch_bounds__(256) wide_xs_kernel(const T *__restrict__ X, i
 // ---------------------------------------------------------------------------
 // d x d helpers in FP64 on LDS, for every thread of a workgroup.
 // ---------------------------------------------------------------------------
-// out = op(A) op(B), op = transpose when TA / TB; ends with a barrier.
 // out = op(A) op(B) for d x d FP64 matrices in LDS (row-major, stride d),
 // op = transpose where TA / TB.  Blocks larger than 16 with at least four
 // waves use the matrix cores: wave w < 4 owns the 16 x 16 output tile
