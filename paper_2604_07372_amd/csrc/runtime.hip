@@ -354,10 +354,16 @@ static WideCtl *wide_ctl(void *ws, int n, int d, int fmt) {
 
 // One iteration on the matrix-core path.  objective: evaluate F(X^t) (the
 // constant part of F is computed from A on the solve's first iteration).
+// chain: a step of a solve's run of steps on the same workspace; its
+// epilogue writes X^{t+1} in the product's operand order as well, and
+// xs_ready says that the previous step of the run did so for X_in.
 static int wide_step_impl(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, int method,
                           const void *X_in, void *X_out, void *ws, hipStream_t s, int iter, double tol,
-                          int stop_rule, bool objective, bool check_done) {
+                          int stop_rule, bool objective, bool check_done, bool chain = false,
+                          bool xs_ready = false) {
   WideArgs a = wide_args(A, n, d, ws);
+  a.xs_write = chain ? 1 : 0;
+  a.xs_ready = chain && xs_ready ? 1 : 0;
   a.X_in = X_in;
   a.X_out = X_out;
   a.mu = mu > 0.0 ? mu : 1.0 / n;
@@ -718,10 +724,13 @@ int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, int
   }
   const bool objective = o.stop_rule == NSRGS_STOP_OBJECTIVE;
   // one iteration on matrix M, with the solve's iteration index and stop rule
-  auto iterate = [&](const nsrgs_matrix *M, const void *xi, void *xo, int t, double tl) {
+  // xs_ready: the previous launch of this phase was a matrix-core step (its
+  // epilogue wrote this step's X in operand order); each phase's first step
+  // stages X itself
+  auto iterate = [&](const nsrgs_matrix *M, const void *xi, void *xo, int t, double tl, bool xs_ready) {
     if (wide)
       return wide_step_impl(M, n, d, mu, ns_steps, o.method, xi, xo, ws, (hipStream_t)stream, t, tl,
-                            o.stop_rule, objective, true);
+                            o.stop_rule, objective, true, true, xs_ready);
     return o.symmetric ? sym_step_launch(M, n, d, mu, ns_steps, xi, xo, ws, (hipStream_t)stream, t, tl, true)
                        : step_impl(M, n, d, mu, ns_steps, xi, xo, ws, (hipStream_t)stream, t, tl, true);
   };
@@ -756,7 +765,7 @@ int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, int
   while (t < phase1) {
     const int tend = std::min(phase1, t + o.check_every);
     for (; t < tend; ++t)
-      if ((st = iterate(A, buf[t & 1], buf[(t + 1) & 1], t, tol))) return st;
+      if ((st = iterate(A, buf[t & 1], buf[(t + 1) & 1], t, tol, t > 0))) return st;
     if ((st = read_ctl(ws, &host, s))) return st;
     if (host.done) break;
   }
@@ -767,7 +776,7 @@ int sync_solve(const nsrgs_matrix *A, int n, int d, double mu, int ns_steps, int
     NSRGS_HIP(launch_ctl_reset(static_cast<DevCtl *>(ws), 1, s), "ctl reset");
     for (int r = 0; r < refine; ++r) {
       const int tt = done_iters + r;
-      if ((st = iterate(o.A_refine, buf[tt & 1], buf[(tt + 1) & 1], tt, 0.0))) return st;
+      if ((st = iterate(o.A_refine, buf[tt & 1], buf[(tt + 1) & 1], tt, 0.0, r > 0))) return st;
     }
     const int conv = host.converged;
     if ((st = read_ctl(ws, &host, s))) return st;

@@ -99,6 +99,9 @@ struct WideArgs {
   int no_diag;         // 1: the partials already exclude A_ii and A is not read
                        //    (block-sparse storage); A_ii counts as zero
   int p;               // columns of X (d, or the Stiefel width p >= d)
+  int xs_ready;        // 1: xs already holds X_in (written by the previous
+                       //    step's epilogue), so the product skips wide_xs_kernel
+  int xs_write;        // 1: the step epilogue also writes X_out into xs
   WideGeom g;
 };
 

@@ -516,9 +516,25 @@ __global__ void __launch_bounds__(256) wide_epilogue_kernel(WideArgs a) {
     S = cur;
   }
   T *__restrict__ Xo = static_cast<T *>(a.X_out);
+  // With xs_write the block's entries of X^{t+1} also go to their places in
+  // the product's operand copy (the layout of wide_xs_kernel: entry (k, c) at
+  // ((step NT + c / 16) 64 + l) KU V + j, step = k / KSTEP and, with
+  // r = k mod KSTEP, l = 16 ((r / V) mod 4) + c mod 16, j = V (r / V / 4) + r mod V),
+  // so the next step's product needs no staging launch.  Its zero padding
+  // (columns past d, rows past n d) stays as the staging kernel wrote it.
+  T *__restrict__ Xs = a.xs_write ? static_cast<T *>(a.xs) : nullptr;
+  constexpr int V = WideT<T>::V;
+  const int xs_per = a.g.ku * V, xs_nt = a.g.nt, xs_kstep = a.g.kstep;
   for (int e = tid; e < dd; e += blockDim.x) {
     const T v = (T)S[e];
-    Xo[((int64_t)i * d + e / d) * d + e % d] = v;
+    const int64_t k = (int64_t)i * d + e / d;
+    const int c = e % d;
+    Xo[k * d + c] = v;
+    if (Xs) {
+      const int step = (int)(k / xs_kstep), r = (int)(k % xs_kstep), g4 = r / V;
+      const int l = (g4 % 4) * 16 + c % 16, j = (g4 / 4) * V + r % V;
+      Xs[(((int64_t)step * xs_nt + c / 16) * 64 + l) * xs_per + j] = v;
+    }
     const double dv = (double)v - X[e];
     red[4] += dv * dv;
     red[5] += isfinite(v) ? 0.0 : 1.0;
@@ -1161,8 +1177,9 @@ static void wide_launch_product_t(const WideArgs &a, hipStream_t s) {
   const int64_t xs_elems = (int64_t)a.g.steps * NT * 64 * (a.g.kstep / 4);
   const int total = a.g.row_tiles * a.g.ks;
   const int wgs = a.g.xcd_remap ? 8 * ((total + 7) / 8) : total;
-  hipLaunchKernelGGL((wide_xs_kernel<T, NT, MT>), dim3((unsigned)((xs_elems + 255) / 256)), dim3(256), 0, s,
-                     static_cast<const T *>(a.X_in), a.nd, a.p, a.g.steps, static_cast<T *>(a.xs), a.stop_flag);
+  if (!a.xs_ready)
+    hipLaunchKernelGGL((wide_xs_kernel<T, NT, MT>), dim3((unsigned)((xs_elems + 255) / 256)), dim3(256), 0, s,
+                       static_cast<const T *>(a.X_in), a.nd, a.p, a.g.steps, static_cast<T *>(a.xs), a.stop_flag);
   hipLaunchKernelGGL((wide_product_kernel<T, NT, MT>), dim3(wgs), dim3(256), 0, s, a);
 }
 
